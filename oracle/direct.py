@@ -1,0 +1,49 @@
+"""Direct summation (Sec. 2.2) and the footprint DFT of the deposit.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+* ``delta_direct``: delta_DS(k) = N_P^-1 sum_j exp(-i k.x_j) for k != 0, the
+  alias-free Fourier density of eq. deltaDS in the standard normalisation.
+* ``footprint_dft``: the DFT of a deposited grid evaluated particle by
+  particle, F(m) = sum_j prod_i sum_t w_{j,i,t} exp(-2 pi i m_i c_{j,i,t}/N),
+  with no grid and no FFT (separability of the kernel, Sec. 2.3).
+"""
+
+import numpy as np
+
+from .assign import grid_coords, stencil
+
+
+def delta_direct(pos, box, modes, chunk=1 << 16):
+    """N_P^-1 sum_j exp(-2 pi i m.x_j / L) for integer modes (n_modes, 3)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    modes = np.asarray(modes, dtype=np.float64).reshape(-1, 3)
+    kvec = 2.0 * np.pi / box * modes
+    acc = np.zeros(len(modes), dtype=np.complex128)
+    for s in range(0, len(pos), chunk):
+        ph = pos[s:s + chunk] @ kvec.T
+        acc += np.exp(-1j * ph).sum(axis=0)
+    return acc / len(pos)
+
+
+def footprint_dft(pos, box, n_grid, p, modes, shift=0.0, chunk=1 << 18):
+    """DFT of the (shifted) deposit at integer modes, without a grid.
+
+    ``shift`` = 0 for the primary grid and 0.5 for the interlaced one.
+    """
+    modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
+    out = np.zeros(len(modes), dtype=np.complex128)
+    pos = np.asarray(pos)
+    for s in range(0, len(pos), chunk):
+        u = grid_coords(pos[s:s + chunk], box, n_grid) + shift
+        per_axis = []
+        for ax in range(3):
+            cells, w = stencil(u[:, ax], p, n_grid)
+            per_axis.append((cells, w))
+        for i, m in enumerate(modes):
+            f = np.ones(len(u), dtype=np.complex128)
+            for ax in range(3):
+                cells, w = per_axis[ax]
+                f *= (w * np.exp(-2j * np.pi * m[ax] * cells / n_grid)).sum(axis=1)
+            out[i] += f.sum()
+    return out

@@ -1,0 +1,163 @@
+"""FFT, interlace combination, window deconvolution and |k|-shell P(k).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Steps, in the paper's order:
+
+1. F_a = unnormalised forward real-to-complex DFT of each grid, sign
+   exp(-i k.x) as in the Fourier convention of Sec. 2.1 (library routine
+   ``scipy.fft.rfftn``; half spectrum, last axis m_z = 0..N/2).
+2. Interlacing (eq. intdelta and the shift theorem above it):
+   C = (F_1 + exp(+i pi (m_x+m_y+m_z)/N) F_2) / 2; without interlacing C = F_1.
+3. Window deconvolution (eqs. windowcorrection, intkerFT):
+   delta = C / (N_P W(m)),  W = prod_i [sin(pi m_i/N)/(pi m_i/N)]^p.
+4. Power in shells (eq. ps, the direct-summation estimator of Sec. 2.2, the
+   shells of Sec. 4): P(m) = V |delta(m)|^2; a bin averages P over its modes.
+
+Readings (the paper is silent or garbled here):
+
+* Normalisation: the power is reported in the standard convention
+  P = V |delta|^2 with delta -> 1 - like N_P^-1 sum_j exp(-i k.x_j); the
+  paper's (2 pi)^3 factors only rescale it (P_paper = P / (2 pi)^3).  The shot
+  noise is the constant V/N_P; it is subtracted only on request (the N-body
+  test subtracts it, the Zel'dovich tests do not).
+* Signed frequencies: index i maps to m = i for i <= N/2 and i - N above, so
+  the Nyquist index N/2 is +N/2 on every axis (this only matters for the
+  interlace phase on the Nyquist planes).
+* Half-spectrum weights: w = 1 on the planes m_z = 0 and m_z = N/2, 2
+  elsewhere; sum w over a bin equals the full-grid mode count.
+* Bins: width dk = n_dk k_f, centred on b dk, lower-inclusive:
+  (2b-1)^2 n_dk^2 <= 4 |m|^2 < (2b+1)^2 n_dk^2, decided in integers;
+  the mode m = 0 is never used; b runs 1..n_bins.
+"""
+
+import numpy as np
+import scipy.fft
+
+from .assign import deposit
+from .kernels import window_1d
+
+
+def signed_index(n):
+    """Signed frequency of each FFT index along a full axis (N/2 -> +N/2)."""
+    i = np.arange(n, dtype=np.int64)
+    return np.where(i <= n // 2, i, i - n)
+
+
+def half_axes(n):
+    """(m_x, m_y, m_z) broadcastable arrays for the rfftn half spectrum."""
+    mx = signed_index(n)[:, None, None]
+    my = signed_index(n)[None, :, None]
+    mz = np.arange(n // 2 + 1, dtype=np.int64)[None, None, :]
+    return mx, my, mz
+
+
+def fft_grid(rho, workers=None):
+    """Unnormalised forward r2c DFT, exp(-2 pi i m.g/N), in float64."""
+    if workers is None:
+        workers = -1
+    return scipy.fft.rfftn(rho, workers=workers)
+
+
+def interlace(f1, f2, n):
+    """C = (F_1 + exp(i pi (m_x+m_y+m_z)/N) F_2) / 2  (eq. intdelta)."""
+    mx, my, mz = half_axes(n)
+    phase = np.exp(1j * np.pi * (mx + my + mz).astype(np.float64) / n)
+    return 0.5 * (f1 + phase * f2)
+
+
+def window(n, p):
+    """W(m) on the half spectrum (eq. intkerFT, three axes multiplied)."""
+    mx, my, mz = half_axes(n)
+    return window_1d(p, mx, n) * window_1d(p, my, n) * window_1d(p, mz, n)
+
+
+def half_weights(n):
+    """w = 1 on m_z in {0, N/2}, 2 elsewhere (broadcastable over the half)."""
+    w = np.full(n // 2 + 1, 2, dtype=np.int64)
+    w[0] = 1
+    w[n // 2] = 1
+    return w[None, None, :]
+
+
+def isqrt(x):
+    """Exact integer square root of a non-negative int64 array."""
+    x = np.asarray(x, dtype=np.int64)
+    r = np.floor(np.sqrt(x.astype(np.float64))).astype(np.int64)
+    r = np.where(r * r > x, r - 1, r)
+    r = np.where((r + 1) * (r + 1) <= x, r + 1, r)
+    return r
+
+
+def bin_index(m2, n_dk):
+    """Bin b with (2b-1)^2 n^2 <= 4 m2 < (2b+1)^2 n^2 (b = 0 if 4 m2 < n^2).
+
+    (2b-1) n <= 2 sqrt(m2) holds for integer (2b-1) n iff it is <= isqrt(4 m2).
+    """
+    q = isqrt(4 * np.asarray(m2, dtype=np.int64)) // n_dk
+    return (q + 1) // 2
+
+
+def max_bins(n, n_dk):
+    """Bins reaching the Nyquist frequency: b <= N / (2 n_dk)."""
+    return n // (2 * n_dk)
+
+
+def mode_table(n, n_dk, n_bins):
+    """(N_b int64, sum_b w|m| float64) per bin, from the half spectrum."""
+    mx, my, mz = half_axes(n)
+    m2 = mx * mx + my * my + mz * mz
+    b = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
+    w = np.broadcast_to(half_weights(n), m2.shape)
+    sel = (m2 > 0) & (b >= 1) & (b <= n_bins)
+    counts = np.bincount(b[sel], weights=w[sel], minlength=n_bins + 1)
+    ksum = np.bincount(b[sel], weights=(w * np.sqrt(m2.astype(np.float64)))[sel],
+                       minlength=n_bins + 1)
+    return np.rint(counts[1:]).astype(np.int64), ksum[1:]
+
+
+def delta_half(pos, box, n, p, interlace_on, workers=None):
+    """delta(m) on the half spectrum (steps 1-3 above) and N_P."""
+    n_p = pos.shape[0]
+    rho1, rho2 = deposit(pos, box, n, p, interlace_on)
+    f1 = fft_grid(rho1, workers)
+    if interlace_on:
+        f2 = fft_grid(rho2, workers)
+        c = interlace(f1, f2, n)
+    else:
+        c = f1
+    return c / (n_p * window(n, p)), n_p
+
+
+def bin_power(delta, box, n, n_dk, n_bins):
+    """(k_b, P_b raw, N_b) from a half-spectrum delta (step 4)."""
+    mx, my, mz = half_axes(n)
+    m2 = mx * mx + my * my + mz * mz
+    b = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
+    w = np.broadcast_to(half_weights(n), m2.shape).astype(np.float64)
+    sel = (m2 > 0) & (b >= 1) & (b <= n_bins)
+    vol = float(box) ** 3
+    pk_mode = vol * np.abs(delta) ** 2
+    s = np.bincount(b[sel], weights=(w * pk_mode)[sel], minlength=n_bins + 1)[1:]
+    counts, ksum = mode_table(n, n_dk, n_bins)
+    kf = 2.0 * np.pi / box
+    with np.errstate(invalid="ignore", divide="ignore"):
+        k = kf * ksum / counts
+        pk = s / counts
+    return k, pk, counts
+
+
+def power(pos, box, n_grid, order, interlace_on, n_dk=1, n_bins=None,
+          subtract_shot=False, workers=None):
+    """Binned power spectrum of a particle set.
+
+    Returns (k_b [h/Mpc units of 1/box], P_b, N_b); P is raw unless
+    ``subtract_shot`` (then P_b - V/N_P).
+    """
+    if n_bins is None:
+        n_bins = max_bins(n_grid, n_dk)
+    delta, n_p = delta_half(np.asarray(pos), box, n_grid, order, interlace_on, workers)
+    k, pk, counts = bin_power(delta, box, n_grid, n_dk, n_bins)
+    if subtract_shot:
+        pk = pk - float(box) ** 3 / n_p
+    return k, pk, counts

@@ -1,0 +1,170 @@
+"""Pins of the oracle's assignment kernels (Sec. 2.3) and deposit (eq. delgrid).
+
+Each check compares against something the paper or mathematics fixes, not
+against the oracle itself: exact rational weights, partition of unity, the
+Fourier transform of eq. intkerFT, finite differences, brute-force gather
+sums with periodic images, and exact lattice identities.
+"""
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import assign, direct, kernels, spectrum
+import synth
+
+ORDERS = [1, 2, 3, 4]
+
+
+@pytest.mark.parametrize("p,u,expected", [
+    # particle on a grid point: stencil cells and exact weights
+    (2, 3.0, [1.0, 0.0]),
+    (3, 3.0, [1 / 8, 3 / 4, 1 / 8]),
+    (4, 3.0, [1 / 6, 2 / 3, 1 / 6, 0.0]),
+    # particle at a cell centre (half-integer offset)
+    (2, 3.5, [0.5, 0.5]),
+    (3, 3.5, [0.5, 0.5, 0.0]),
+    (4, 3.5, [1 / 48, 23 / 48, 23 / 48, 1 / 48]),
+    (1, 3.49, [1.0]),
+])
+def test_rational_weights(p, u, expected):
+    cells, w = assign.stencil(np.array([u]), p, 16)
+    nz = [x for x in expected]
+    assert np.allclose(w[0], nz, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_partition_of_unity(p):
+    rng = np.random.default_rng(0)
+    u = rng.uniform(0, 64, 5000)
+    _, w = assign.stencil(u, p, 64)
+    assert np.allclose(w.sum(axis=1), 1.0, atol=1e-14)
+    # the stencil holds the whole kernel: W vanishes outside it
+    for off in (-3, -2, p, p + 1):
+        if p % 2 == 0:
+            first = np.floor(u) - (p // 2 - 1)
+        else:
+            first = np.floor(u + 0.5) - (p - 1) // 2
+        assert np.all(kernels.weight(p, first + off - u) == 0.0) or p == 1
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_kernel_fourier_transform_is_sinc_power(p):
+    """int W^(p)(s) exp(-i q s) ds = [sin(q/2)/(q/2)]^p  (eq. intkerFT, H = 1)."""
+    for q in (0.3, 1.1, 2.5, np.pi, 5.0):
+        def f(s):
+            return kernels.weight(p, np.array([s]))[0] * np.cos(q * s)
+        pts = [-2, -1.5, -1, -0.5, 0, 0.5, 1, 1.5, 2]
+        val = integrate.quad(f, -2.5, 2.5, points=pts, limit=200, epsabs=1e-13)[0]
+        assert val == pytest.approx(np.sinc(q / (2 * np.pi)) ** p, abs=1e-10)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_kernel_derivative_matches_finite_difference(p):
+    s = np.linspace(-2.3, 2.3, 1001)
+    s = s[np.all(np.abs(np.abs(s)[:, None] - np.array([0.5, 1.0, 1.5, 2.0])) > 1e-3, axis=1)]
+    h = 1e-6
+    fd = (kernels.weight(p, s + h) - kernels.weight(p, s - h)) / (2 * h)
+    assert np.allclose(kernels.dweight(p, s), fd, atol=1e-6)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("il", [False, True])
+def test_mass_conservation(p, il):
+    pos = synth.uniform(3000, 500.0, 7, np.float64)
+    r1, r2 = assign.deposit(pos, 500.0, 16, p, il)
+    assert r1.sum() == pytest.approx(3000.0, rel=1e-13)
+    if il:
+        assert r2.sum() == pytest.approx(3000.0, rel=1e-13)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_deposit_equals_bruteforce_gather(p):
+    """rho(g) = sum_j sum_images prod_i W(g_i - u_ji + n_i N), every cell x particle."""
+    n, box = 8, 10.0
+    rng = np.random.default_rng(p)
+    pos = rng.uniform(-3.0, 13.0, size=(25, 3))  # also exercises the wrap
+    r1, r2 = assign.deposit(pos, box, n, p, True)
+    xw = np.mod(pos, box)
+    u = xw * (n / box)
+    g = np.arange(n, dtype=np.float64)
+    for shift, rho in ((0.0, r1), (0.5, r2)):
+        per_axis = []
+        for ax in range(3):
+            acc = np.zeros((len(pos), n))
+            for img in (-1, 0, 1):
+                s = g[None, :] + img * n - (u[:, ax, None] + shift)
+                if p == 1:
+                    # nearest cell, ties upward (a cell is [g - 1/2, g + 1/2))
+                    acc += ((s > -0.5) & (s <= 0.5)).astype(float)
+                else:
+                    acc += kernels.weight(p, s)
+            per_axis.append(acc)
+        brute = np.einsum("jx,jy,jz->xyz", *per_axis)
+        assert np.allclose(rho, brute, atol=1e-13)
+
+
+def _lattice_factor(p, theta):
+    return {1: np.ones_like(theta), 2: np.ones_like(theta),
+            3: 0.75 + 0.25 * np.cos(theta), 4: 2 / 3 + np.cos(theta) / 3}[p]
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_lattice_particles_match_direct_sum(p):
+    """Particles on grid points: FFT(rho1)(m) = sum_j exp(-i k.x_j) prod_i Lambda_p(2 pi m_i/N)."""
+    n, box = 8, 100.0
+    full = synth.lattice(n, box)
+    rng = np.random.default_rng(11)
+    pos = full[rng.choice(len(full), 150, replace=False)]
+    r1, _ = assign.deposit(pos, box, n, p, False)
+    f1 = spectrum.fft_grid(r1)
+    mx, my, mz = spectrum.half_axes(n)
+    modes = np.stack(np.broadcast_arrays(mx, my, mz), axis=-1).reshape(-1, 3)
+    ds = direct.delta_direct(pos, box, modes) * len(pos)
+    lam = np.prod(_lattice_factor(p, 2 * np.pi * modes / n), axis=1)
+    assert np.allclose(f1.reshape(-1), ds * lam, atol=1e-10)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_half_lattice_interlaced_grid_matches_direct_sum(p):
+    """Particles at cell centres: exp(+i pi sum m / N) FFT(rho2)(m) equals the
+    direct sum at the same signed k (pins the interlace phase sign and the
+    Nyquist index convention)."""
+    n, box = 8, 100.0
+    full = synth.half_lattice(n, box)
+    rng = np.random.default_rng(12)
+    pos = full[rng.choice(len(full), 150, replace=False)]
+    _, r2 = assign.deposit(pos, box, n, p, True)
+    f2 = spectrum.fft_grid(r2)
+    mx, my, mz = spectrum.half_axes(n)
+    phase = np.exp(1j * np.pi * (mx + my + mz) / n)
+    modes = np.stack(np.broadcast_arrays(mx, my, mz), axis=-1).reshape(-1, 3)
+    ds = direct.delta_direct(pos, box, modes) * len(pos)
+    lam = np.prod(_lattice_factor(p, 2 * np.pi * modes / n), axis=1)
+    assert np.allclose((phase * f2).reshape(-1), ds * lam, atol=1e-10)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_footprint_dft_matches_fft_of_deposit(p, shift):
+    n, box = 12, 50.0
+    pos = synth.uniform(200, box, 21 + p, np.float64)
+    r1, r2 = assign.deposit(pos, box, n, p, True)
+    rho = r1 if shift == 0.0 else r2
+    f = spectrum.fft_grid(rho)
+    rng = np.random.default_rng(5)
+    idx = np.stack([rng.integers(0, n, 20), rng.integers(0, n, 20),
+                    rng.integers(0, n // 2 + 1, 20)], axis=1)
+    modes = np.where(idx <= n // 2, idx, idx - n)
+    fp = direct.footprint_dft(pos, box, n, p, modes, shift=shift)
+    assert np.allclose(f[idx[:, 0], idx[:, 1], idx[:, 2]], fp, atol=1e-10)
+
+
+def test_wrap_edge_cases():
+    box = 1000.0
+    x = np.array([0.0, -0.0, 1000.0, -1e-300, 999.9999999999999, 2000.5, -0.25,
+                  np.float32(999.99994)], dtype=np.float64)
+    w = assign.wrap(x, box)
+    assert np.all((w >= 0) & (w < box))
+    assert w[2] == 0.0 and w[3] == 0.0
+    assert w[5] == pytest.approx(0.5) and w[6] == pytest.approx(999.75)
