@@ -1,0 +1,193 @@
+/*
+ * fsest.h - C ABI of the interlaced, order-p Fourier-space estimators of
+ * Sefusatti, Crocce, Scoccimarro & Couchman, "Accurate Estimators of
+ * Correlation Functions in Fourier Space" (arXiv:1512.07295), on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Pipeline (one handle = one grid size, box, order and interlacing choice,
+ * for a batch of one or more particle sets that share them):
+ *
+ *   estimator_deposit    particles -> primary grid (and the grid shifted by
+ *                        H/2 on every axis when interlacing)       Sec. 2.3, 3.1
+ *   estimator_transform  3D FFT of both grids                      Sec. 2.3
+ *   estimator_power      interlace, deconvolve, bin P(k)           Sec. 3.1, 2.2
+ *   estimator_bispectrum FFT-shell bispectrum                      Sec. 4.1
+ *   estimator_backward   dL/dx of a loss of P(k)       (adjoint, not in paper)
+ *   estimator_graph_*    the deposit->transform->power sequence captured
+ *                        once as a HIP graph and replayed
+ *
+ * Conventions (shared by every entry point):
+ *   - Positions: row-major (n, 3) arrays of x, y, z in the units of `box`,
+ *     float32 or float64, in device memory.  Any finite value is accepted and
+ *     wrapped periodically into [0, box).  Non-finite values give unspecified
+ *     (but memory-safe) results.
+ *   - Grid: point g = 0..N-1 sits at x = g H, H = box/N (grid-1 origin at 0).
+ *   - Fourier convention: forward transform exp(-i k.x); signed frequency of
+ *     FFT index i is i for i <= N/2, i - N above (Nyquist index -> +N/2).
+ *   - Normalisation: P = V |delta|^2 with delta = N_P^-1 sum_j exp(-i k.x_j)
+ *     in the alias-free limit (shot noise V/N_P); B = V^2 <delta delta delta>.
+ *     The paper's (2 pi)^3 factors only rescale these.
+ *   - Shells: width dk = n_dk * k_f (k_f = 2 pi / box), centred on b dk,
+ *     lower-inclusive, decided on integer |m|^2; b = 1..n_bins; k = 0 unused.
+ *   - Every call enqueues work on the stream given to estimator_create and
+ *     returns without synchronising the host; device outputs are valid once
+ *     that stream reaches the point of the call.  The library owns no device
+ *     memory: the caller provides a workspace of estimator_workspace_bytes()
+ *     bytes that must outlive the handle.
+ *   - Errors: every entry point returns an est_status; on failure
+ *     estimator_last_error() (thread-local, never NULL) describes it.  All
+ *     argument checks happen on the host before any launch, so they need no
+ *     GPU.  After a device error the handle can still be destroyed.
+ */
+#ifndef FSEST_H
+#define FSEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct est_ctx* est_handle;
+
+typedef enum {
+  EST_OK = 0,
+  EST_EINVAL = 1,       /* invalid argument                                  */
+  EST_ENOMEM = 2,       /* workspace too small / size overflow               */
+  EST_ESTATE = 3,       /* call out of order (e.g. power before transform)   */
+  EST_EDEVICE = 4,      /* HIP runtime or kernel launch failure              */
+  EST_EUNSUPPORTED = 5  /* valid but not implemented (e.g. N not 2^k)        */
+} est_status;
+
+typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
+
+typedef struct {
+  int32_t n_grid;        /* N: power of two in [8, 1024]                       */
+  int32_t order;         /* p = 1..4: NGP, CIC, TSC, PCS (Sec. 2.3)            */
+  int32_t interlace;     /* 0 or 1: second grid shifted by H/2 (Sec. 3.1)     */
+  int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
+  double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */
+  int64_t max_particles; /* upper bound of n_total per call, 1 .. 2^31-1      */
+  int32_t flags;         /* reserved, must be 0                                */
+  int32_t reserved;      /* must be 0                                          */
+} est_config;
+
+/* Bytes of device workspace a handle with this configuration needs.
+ * Host only.  EINVAL for an invalid config, EUNSUPPORTED for N not a power of
+ * two in [8, 1024], ENOMEM if the size overflows. */
+est_status estimator_workspace_bytes(const est_config* cfg, size_t* bytes);
+
+/* Create a handle.  `workspace` is a device pointer to at least
+ * estimator_workspace_bytes(cfg) bytes, 256-byte aligned, owned by the caller.
+ * `stream` is a hipStream_t (NULL = the default stream).  Initialises the
+ * handle's tables on that stream.  ENOMEM if workspace_bytes is too small. */
+est_status estimator_create(const est_config* cfg, void* workspace,
+                            size_t workspace_bytes, void* stream,
+                            est_handle* out);
+
+/* Destroy a handle (frees host state and any captured graph).  Safe on NULL
+ * and after errors.  Does not touch the workspace. */
+est_status estimator_destroy(est_handle h);
+
+/* Mass assignment (Sec. 2.3, eq. delgrid) onto the primary grid and, when
+ * interlacing, onto the grid sampled at x + H/2 (Sec. 3.1).
+ *   pos      device (n_total, 3) positions of `dtype`.
+ *   offsets  device int64 [batch + 1] prefix sums (offsets[0] = 0,
+ *            offsets[batch] = n_total, non-decreasing); must be NULL when
+ *            batch == 1 and non-NULL otherwise.  Set i holds particles
+ *            offsets[i] .. offsets[i+1]-1.  An empty set gives a zero grid.
+ *   n_total  1 .. max_particles.
+ * EINVAL on a bad argument.  Overwrites both grids of every set. */
+est_status estimator_deposit(est_handle h, const void* pos, est_dtype dtype,
+                             const int64_t* offsets, int64_t n_total);
+
+/* Forward 3D FFT of the deposited grids (Sec. 2.3, eqs. tdelG1-tdelG2).
+ * ESTATE before a deposit.  The last axis may be completed lazily by the
+ * next estimator_power / estimator_bispectrum call. */
+est_status estimator_transform(est_handle h);
+
+/* Interlace (eq. intdelta), deconvolve by prod_i sinc^p (eqs.
+ * windowcorrection, intkerFT) and average V|delta|^2 in |k| shells.
+ *   n_dk       shell width in units of k_f, >= 1.
+ *   n_bins     1 .. N/(2 n_dk) (shells up to the Nyquist frequency).
+ *   subtract_shot  0 = raw P, 1 = P - V/N_P (per set).
+ *   k, p       device float64 [batch][n_bins]: mean |k| and P per shell.
+ *   nmodes     device int64 [batch][n_bins]: modes per shell (full grid).
+ * ESTATE before estimator_transform.  A set with no particles gives NaN. */
+est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins,
+                           int32_t subtract_shot, double* k, double* p,
+                           int64_t* nmodes);
+
+/* Bytes of extra device workspace estimator_bispectrum needs for n_bins
+ * shells and n_tri triangles.  Host only. */
+est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_bins,
+                                                int64_t n_tri, size_t* bytes);
+
+/* FFT-shell bispectrum (Sec. 4.1, eqs. Best, VBest, Best2, IntI) of set 0
+ * (or of `mock`), shells of width n_dk k_f.
+ *   tri_host   host int32 [n_tri][3], 1 <= b3 <= b2 <= b1 <= n_bins; read
+ *              during the call only.
+ *   bws        device workspace of estimator_bispectrum_workspace_bytes().
+ *   b          device float64 [n_tri]: V^2 sum III / sum JJJ (NaN if no
+ *              closed triplet).
+ *   ntri       device float64 [n_tri]: number of closed mode triplets.
+ * EINVAL if (n_bins + 1/2) n_dk >= N/3 (the triangle limit of Sec. 4.1).
+ * ESTATE before estimator_transform. */
+est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk,
+                                int32_t n_bins, const int32_t* tri_host,
+                                int64_t n_tri, void* bws, size_t bws_bytes,
+                                double* b, double* ntri);
+
+/* Adjoint of deposit -> transform -> power for a loss L(P): given
+ * dL/dP_b (device float64 [batch][n_bins]) writes dL/dx (device, same dtype
+ * and layout as pos) for every particle.  The grids are recomputed from pos
+ * (nothing is kept from the forward); the handle's grids are overwritten.
+ * Same argument rules as estimator_deposit and estimator_power. */
+est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype,
+                              const int64_t* offsets, int64_t n_total,
+                              const double* dldp, int32_t n_dk, int32_t n_bins,
+                              void* grad);
+
+/* Capture deposit -> transform -> power with these arguments into a HIP
+ * graph owned by the handle (replacing any earlier one).  Pointers are baked
+ * into the graph; the buffers must stay valid while it is replayed.  Also
+ * runs the pipeline once. */
+est_status estimator_graph_capture(est_handle h, const void* pos,
+                                   est_dtype dtype, const int64_t* offsets,
+                                   int64_t n_total, int32_t n_dk,
+                                   int32_t n_bins, int32_t subtract_shot,
+                                   double* k, double* p, int64_t* nmodes);
+
+/* Replay the captured graph on the handle's stream.  ESTATE if none. */
+est_status estimator_graph_launch(est_handle h);
+
+/* Time candidate launch shapes for this handle on the given input (which
+ * is deposited, transformed and binned `iters` times per candidate) and keep
+ * the fastest; returns its index in *choice.  Host-synchronising. */
+est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype,
+                              const int64_t* offsets, int64_t n_total,
+                              int32_t n_dk, int32_t n_bins, int32_t iters,
+                              int32_t* choice);
+
+/* Test hook: copy grid `which` (1 = primary, 2 = interlaced) of set `mock`
+ * as float32 [N][N][N] (z fastest) to dst (device).  ESTATE unless the last
+ * call was estimator_deposit. */
+est_status estimator_copy_grid(est_handle h, int32_t which, int32_t mock,
+                               float* dst);
+
+/* Test hook: delta(m) = C(m) / (N_P W(m)) of set `mock` at n signed integer
+ * modes (device int32 [n][3], each component in (-N/2, N/2]) into device
+ * float64 [n][2] (re, im).  Brings the handle to the full-spectrum state. */
+est_status estimator_sample_delta(est_handle h, int32_t mock,
+                                  const int32_t* modes, int64_t n,
+                                  double* out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* estimator_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSEST_H */

@@ -1,0 +1,523 @@
+// C ABI of libfsest (declared in include/fsest.h): argument validation, the
+// workspace layout, the call-order state machine, HIP-graph capture and the
+// launch-shape autotuner.  All kernels live in deposit.hip, fft.hip and
+// spectral.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fsest_internal.hpp"
+
+using namespace fsest;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+est_status fail(est_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+est_status ok() { return EST_OK; }
+
+enum State { kCreated = 0, kDeposited = 1, kXY = 2, kSpectrum = 3 };
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct est_ctx {
+  est_config cfg;
+  Geom g;
+  Buffers b;
+  Tune tu;
+  hipStream_t stream;
+  int device;
+  int state = kCreated;
+  int mode_dk = -1, mode_nbins = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* tune_out = nullptr;
+};
+
+namespace {
+
+est_status check_config(const est_config* c) {
+  if (!c) return fail(EST_EINVAL, "config is NULL");
+  if (c->order < 1 || c->order > 4) return fail(EST_EINVAL, "order must be 1..4 (got %d)", c->order);
+  if (c->interlace != 0 && c->interlace != 1)
+    return fail(EST_EINVAL, "interlace must be 0 or 1 (got %d)", c->interlace);
+  if (c->batch < 1 || c->batch > 65535) return fail(EST_EINVAL, "batch must be 1..65535 (got %d)", c->batch);
+  if (!(c->box > 0.0) || !std::isfinite(c->box)) return fail(EST_EINVAL, "box must be finite and > 0");
+  if (c->max_particles < 1 || c->max_particles > 2147483647LL)
+    return fail(EST_EINVAL, "max_particles must be 1..2^31-1");
+  if (c->flags != 0 || c->reserved != 0) return fail(EST_EINVAL, "flags and reserved must be 0");
+  if (!pow2(c->n_grid) || c->n_grid < 8 || c->n_grid > 1024)
+    return fail(EST_EUNSUPPORTED, "n_grid must be a power of two in [8, 1024] (got %d)", c->n_grid);
+  const int64_t nb = c->n_grid / kBucket;
+  if ((int64_t)c->batch * nb * nb * nb + 1 >= 4294967295LL)
+    return fail(EST_EINVAL, "batch * (N/4)^3 exceeds the 32-bit bucket index");
+  return ok();
+}
+
+Geom make_geom(const est_config& c) {
+  Geom g;
+  g.n = c.n_grid;
+  g.nz = c.interlace ? c.n_grid : c.n_grid / 2;
+  g.order = c.order;
+  g.il = c.interlace;
+  g.batch = c.batch;
+  g.nb = c.n_grid / kBucket;
+  g.tile = c.n_grid < kTileMax ? c.n_grid : kTileMax;
+  g.box = c.box;
+  g.inv = (double)c.n_grid / c.box;
+  return g;
+}
+
+// Workspace layout; with base == nullptr only the size is computed.
+size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
+  const Geom g = make_geom(c);
+  const size_t n = (size_t)g.n, batch = (size_t)g.batch, half = n / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const size_t nkeys = batch * (size_t)g.nb * g.nb * g.nb + 1;
+  Buffers bb;
+  bb.grid = (float2*)take(batch * n * n * (size_t)g.nz * sizeof(float2));
+  bb.sorted = take((size_t)c.max_particles * 3 * sizeof(double));
+  bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
+  bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
+  bb.scan_tmp = (uint32_t*)take(((nkeys + 2047) / 2048 + 1) * sizeof(uint32_t));
+  bb.tw_n = (float2*)take(n * sizeof(float2));
+  bb.tw_nz = (float2*)take((size_t)g.nz * sizeof(float2));
+  bb.inv_w2 = (float*)take(n * sizeof(float));
+  bb.win1 = (float*)take(n * sizeof(float));
+  bb.phase = (float2*)take(2 * n * sizeof(float2));
+  bb.partials = (double*)take(batch * kMaxBinBlocks * half * sizeof(double));
+  bb.mode_n = (int64_t*)take(half * sizeof(int64_t));
+  bb.mode_k = (double*)take(half * sizeof(double));
+  bb.np = (int64_t*)take(batch * sizeof(int64_t));
+  bb.coef = (double*)take(batch * half * sizeof(double));
+  bb.mode_partials_n = (uint64_t*)take(512 * half * sizeof(uint64_t));
+  bb.mode_partials_k = (double*)take(512 * half * sizeof(double));
+  char* to = take(batch * half * 3 * sizeof(double));
+  if (b) *b = bb;
+  if (tune_out) *tune_out = to;
+  return off;
+}
+
+est_status dev_err(hipError_t e, const char* what) {
+  if (e == hipSuccess) return EST_OK;
+  return fail(EST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+est_status check_handle(est_handle h) {
+  if (!h) return fail(EST_EINVAL, "handle is NULL");
+  return ok();
+}
+
+est_status check_particles(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
+                           int64_t n_total) {
+  if (!pos) return fail(EST_EINVAL, "pos is NULL");
+  if (dt != EST_F32 && dt != EST_F64) return fail(EST_EINVAL, "dtype must be EST_F32 or EST_F64");
+  if (n_total < 1 || n_total > h->cfg.max_particles)
+    return fail(EST_EINVAL, "n_total must be 1..max_particles (%lld), got %lld",
+                (long long)h->cfg.max_particles, (long long)n_total);
+  if (h->cfg.batch == 1 && offsets) return fail(EST_EINVAL, "offsets must be NULL when batch == 1");
+  if (h->cfg.batch > 1 && !offsets) return fail(EST_EINVAL, "offsets required when batch > 1");
+  return ok();
+}
+
+est_status check_bins(est_handle h, int32_t n_dk, int32_t n_bins) {
+  if (n_dk < 1) return fail(EST_EINVAL, "n_dk must be >= 1");
+  const int maxb = h->g.n / (2 * n_dk);
+  if (n_bins < 1 || n_bins > maxb)
+    return fail(EST_EINVAL, "n_bins must be 1..N/(2 n_dk) = %d (got %d)", maxb, n_bins);
+  return ok();
+}
+
+est_status ensure_modes(est_handle h, int n_dk, int n_bins) {
+  if (h->mode_dk == n_dk && h->mode_nbins == n_bins) return ok();
+  est_status st = dev_err(launch_mode_table(h->g, h->b, n_dk, n_bins, h->stream), "mode table");
+  if (st != EST_OK) return st;
+  h->mode_dk = n_dk;
+  h->mode_nbins = n_bins;
+  return ok();
+}
+
+est_status run_deposit(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
+                       int64_t n_total) {
+  est_status st = dev_err(launch_set_counts(offsets, n_total, h->g.batch, h->b.np, h->stream), "counts");
+  if (st) return st;
+  st = dev_err(launch_sort(h->g, pos, dt, offsets, n_total, h->b, h->stream), "bucket sort");
+  if (st) return st;
+  return dev_err(launch_deposit(h->g, dt, h->b, h->tu, h->stream), "deposit");
+}
+
+est_status run_xy(est_handle h, int dir) {
+  est_status st;
+  if (dir < 0) {
+    st = dev_err(launch_fft_axis(h->g, h->b.grid, 0, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft x");
+    if (st) return st;
+    return dev_err(launch_fft_axis(h->g, h->b.grid, 1, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft y");
+  }
+  st = dev_err(launch_fft_axis(h->g, h->b.grid, 1, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft y");
+  if (st) return st;
+  return dev_err(launch_fft_axis(h->g, h->b.grid, 0, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft x");
+}
+
+est_status to_spectrum(est_handle h) {
+  if (h->state == kSpectrum) return ok();
+  if (h->state != kXY) return fail(EST_ESTATE, "needs estimator_transform first");
+  est_status st = dev_err(launch_fft_axis(h->g, h->b.grid, 2, -1, h->g.batch, h->g.nz, h->b.tw_nz, h->tu, h->stream), "fft z");
+  if (st) return st;
+  h->state = kSpectrum;
+  return ok();
+}
+
+est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
+                       int64_t n_total, int n_dk, int n_bins, int sub, double* k, double* p,
+                       int64_t* nm) {
+  est_status st = run_deposit(h, pos, dt, offsets, n_total);
+  if (st) return st;
+  st = run_xy(h, -1);
+  if (st) return st;
+  return dev_err(launch_power(h->g, h->b, h->tu, true, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* estimator_last_error(void) { return g_err; }
+
+est_status estimator_workspace_bytes(const est_config* cfg, size_t* bytes) {
+  est_status st = check_config(cfg);
+  if (st) return st;
+  if (!bytes) return fail(EST_EINVAL, "bytes is NULL");
+  *bytes = layout(*cfg, nullptr, nullptr, nullptr);
+  return ok();
+}
+
+est_status estimator_create(const est_config* cfg, void* workspace, size_t workspace_bytes,
+                            void* stream, est_handle* out) {
+  est_status st = check_config(cfg);
+  if (st) return st;
+  if (!out) return fail(EST_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!workspace) return fail(EST_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(EST_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = layout(*cfg, nullptr, nullptr, nullptr);
+  if (workspace_bytes < need)
+    return fail(EST_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  est_ctx* h = new (std::nothrow) est_ctx();
+  if (!h) return fail(EST_ENOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->g = make_geom(*cfg);
+  layout(*cfg, (char*)workspace, &h->b, &h->tune_out);
+  h->stream = (hipStream_t)stream;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  st = dev_err(launch_tables(h->g, h->b, h->stream), "tables");
+  if (st) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return ok();
+}
+
+est_status estimator_destroy(est_handle h) {
+  if (!h) return ok();
+  if (h->exec) hipGraphExecDestroy(h->exec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  delete h;
+  return ok();
+}
+
+est_status estimator_deposit(est_handle h, const void* pos, est_dtype dtype, const int64_t* offsets,
+                             int64_t n_total) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
+  h->state = kCreated;
+  if ((st = run_deposit(h, pos, dtype, offsets, n_total))) return st;
+  h->state = kDeposited;
+  return ok();
+}
+
+est_status estimator_transform(est_handle h) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (h->state != kDeposited) return fail(EST_ESTATE, "estimator_transform needs a fresh deposit");
+  if ((st = run_xy(h, -1))) return st;
+  h->state = kXY;
+  return ok();
+}
+
+est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins, int32_t subtract_shot,
+                           double* k, double* p, int64_t* nmodes) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if ((st = check_bins(h, n_dk, n_bins))) return st;
+  if (!k || !p || !nmodes) return fail(EST_EINVAL, "output pointers must not be NULL");
+  if (subtract_shot != 0 && subtract_shot != 1) return fail(EST_EINVAL, "subtract_shot must be 0 or 1");
+  if (h->state != kXY && h->state != kSpectrum)
+    return fail(EST_ESTATE, "estimator_power needs estimator_transform first");
+  if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  return dev_err(launch_power(h->g, h->b, h->tu, h->state == kXY, n_dk, n_bins, subtract_shot, k, p,
+                              nmodes, h->stream),
+                 "power");
+}
+
+static int bispec_xranges(int64_t n_tri) {
+  const int64_t tb = (n_tri + 255) / 256;
+  int64_t nx = 4096 / tb;
+  if (nx < 1) nx = 1;
+  if (nx > 512) nx = 512;
+  return (int)nx;
+}
+
+static size_t bispec_bytes(const Geom& g, int n_bins, int64_t n_tri) {
+  const size_t n3 = (size_t)g.n * g.n * g.n;
+  const size_t npairs = (size_t)(n_bins + 1) / 2;
+  size_t off = 0;
+  off = align_up(off + npairs * n3 * sizeof(float2));  // I pairs
+  off = align_up(off + npairs * n3 * sizeof(float2));  // J pairs
+  off = align_up(off + (size_t)n_tri * 3 * sizeof(int32_t));
+  off = align_up(off + (size_t)bispec_xranges(n_tri) * n_tri * 2 * sizeof(double));
+  return off;
+}
+
+est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_bins, int64_t n_tri,
+                                                size_t* bytes) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!bytes) return fail(EST_EINVAL, "bytes is NULL");
+  if (n_bins < 1 || n_bins > kMaxBins) return fail(EST_EINVAL, "n_bins out of range");
+  if (n_tri < 1) return fail(EST_EINVAL, "n_tri must be >= 1");
+  *bytes = bispec_bytes(h->g, n_bins, n_tri);
+  return ok();
+}
+
+est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_t n_bins,
+                                const int32_t* tri_host, int64_t n_tri, void* bws, size_t bws_bytes,
+                                double* bk, double* ntri) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  const Geom& g = h->g;
+  if (mock < 0 || mock >= g.batch) return fail(EST_EINVAL, "mock out of range");
+  if (n_dk < 1) return fail(EST_EINVAL, "n_dk must be >= 1");
+  if (n_bins < 1 || n_bins > kMaxBins) return fail(EST_EINVAL, "n_bins out of range");
+  // triangle limit k_max = k_f N / 3 (Sec. 4.1): (n_bins + 1/2) n_dk < N/3
+  if (3LL * (2 * n_bins + 1) * n_dk >= 2LL * g.n)
+    return fail(EST_EINVAL, "(n_bins + 1/2) n_dk must be < N/3 (triangle aliasing limit)");
+  if (!tri_host || n_tri < 1) return fail(EST_EINVAL, "triangles missing");
+  if (!bws || !bk || !ntri) return fail(EST_EINVAL, "NULL device pointer");
+  if (((uintptr_t)bws & 255) != 0) return fail(EST_EINVAL, "bispectrum workspace must be 256-byte aligned");
+  for (int64_t t = 0; t < n_tri; ++t) {
+    const int32_t a = tri_host[3 * t], b = tri_host[3 * t + 1], c = tri_host[3 * t + 2];
+    if (!(1 <= c && c <= b && b <= a && a <= n_bins))
+      return fail(EST_EINVAL, "triangle %lld must satisfy 1 <= b3 <= b2 <= b1 <= n_bins", (long long)t);
+  }
+  const size_t need = bispec_bytes(g, n_bins, n_tri);
+  if (bws_bytes < need) return fail(EST_ENOMEM, "bispectrum workspace too small: %zu < %zu", bws_bytes, need);
+  if ((st = to_spectrum(h))) return st;
+  const size_t n3 = (size_t)g.n * g.n * g.n;
+  const int npairs = (n_bins + 1) / 2;
+  char* base = (char*)bws;
+  size_t off = 0;
+  float2* ip = (float2*)(base + off);
+  off = align_up(off + (size_t)npairs * n3 * sizeof(float2));
+  float2* jp = (float2*)(base + off);
+  off = align_up(off + (size_t)npairs * n3 * sizeof(float2));
+  int32_t* tri_dev = (int32_t*)(base + off);
+  off = align_up(off + (size_t)n_tri * 3 * sizeof(int32_t));
+  double* part = (double*)(base + off);
+  if ((st = dev_err(hipMemcpyAsync(tri_dev, tri_host, (size_t)n_tri * 3 * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, h->stream), "copy triangles")))
+    return st;
+  // full-length complex transforms of the shell fields
+  Geom gf = g;
+  gf.nz = g.n;
+  gf.batch = 1;
+  for (int q = 0; q < npairs; ++q) {
+    const int b1 = 2 * q + 1, b2 = (2 * q + 2 <= n_bins) ? 2 * q + 2 : 0;
+    for (int which = 0; which < 2; ++which) {
+      float2* dst = (which ? jp : ip) + (size_t)q * n3;
+      if ((st = dev_err(launch_shell_pair(g, h->b, mock, n_dk, b1, b2, which == 1, dst, h->stream), "shell fields")))
+        return st;
+      for (int ax = 2; ax >= 0; --ax) {
+        if ((st = dev_err(launch_fft_axis(gf, dst, ax, +1, 1, g.n, h->b.tw_n, h->tu, h->stream), "inverse fft")))
+          return st;
+      }
+    }
+  }
+  const int nx = bispec_xranges(n_tri);
+  if ((st = dev_err(launch_triple_sums((int64_t)n3, ip, jp, n_bins, tri_dev, n_tri, part, nx, h->stream), "triple sums")))
+    return st;
+  if ((st = dev_err(launch_bispec_finalize(part, nx, n_tri, g.box * g.box * g.box, (double)n3, bk, ntri, h->stream), "bispectrum")))
+    return st;
+  // the host triangle buffer must outlive the copy
+  return dev_err(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype, const int64_t* offsets,
+                              int64_t n_total, const double* dldp, int32_t n_dk, int32_t n_bins,
+                              void* grad) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
+  if ((st = check_bins(h, n_dk, n_bins))) return st;
+  if (!dldp || !grad) return fail(EST_EINVAL, "NULL device pointer");
+  if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  h->state = kCreated;
+  if ((st = run_deposit(h, pos, dtype, offsets, n_total))) return st;
+  if ((st = run_xy(h, -1))) return st;
+  if ((st = dev_err(launch_adjoint_spectrum(h->g, h->b, h->tu, dldp, n_dk, n_bins, h->stream), "adjoint spectrum")))
+    return st;
+  if ((st = run_xy(h, +1))) return st;
+  if ((st = dev_err(launch_gather_grad(h->g, pos, dtype, offsets, n_total, h->b, grad, h->stream), "gather")))
+    return st;
+  h->state = kCreated;  // the grid now holds dL/drho, not a density
+  return ok();
+}
+
+est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtype, const int64_t* offsets,
+                                   int64_t n_total, int32_t n_dk, int32_t n_bins, int32_t subtract_shot,
+                                   double* k, double* p, int64_t* nmodes) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
+  if ((st = check_bins(h, n_dk, n_bins))) return st;
+  if (!k || !p || !nmodes) return fail(EST_EINVAL, "output pointers must not be NULL");
+  if (subtract_shot != 0 && subtract_shot != 1) return fail(EST_EINVAL, "subtract_shot must be 0 or 1");
+  if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  // one eager run (also sets kernel attributes outside the capture)
+  if ((st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, subtract_shot, k, p, nmodes)))
+    return st;
+  if ((st = dev_err(hipStreamSynchronize(h->stream), "synchronize"))) return st;
+  if (h->exec) { hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+  if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
+  hipStream_t cs;
+  if ((st = dev_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return st;
+  hipStream_t saved = h->stream;
+  h->stream = cs;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, subtract_shot, k, p, nmodes);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (st == EST_OK && e2 != hipSuccess) st = dev_err(e2, "end capture");
+    if (st == EST_OK) {
+      h->graph = graph;
+      st = dev_err(hipGraphInstantiate(&h->exec, graph, nullptr, nullptr, 0), "instantiate graph");
+    } else if (graph) {
+      hipGraphDestroy(graph);
+    }
+  } else {
+    st = dev_err(e, "begin capture");
+  }
+  h->stream = saved;
+  hipStreamDestroy(cs);
+  h->state = (st == EST_OK) ? kXY : kCreated;
+  return st;
+}
+
+est_status estimator_graph_launch(est_handle h) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!h->exec) return fail(EST_ESTATE, "no captured graph");
+  if ((st = dev_err(hipGraphLaunch(h->exec, h->stream), "graph launch"))) return st;
+  h->state = kXY;
+  return ok();
+}
+
+est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, const int64_t* offsets,
+                              int64_t n_total, int32_t n_dk, int32_t n_bins, int32_t iters, int32_t* choice) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
+  if ((st = check_bins(h, n_dk, n_bins))) return st;
+  if (iters < 1 || iters > 1000) return fail(EST_EINVAL, "iters must be 1..1000");
+  if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  std::vector<Tune> cands;
+  const int cols[2] = {8, 16};
+  const int bins[3] = {256, 1024, 2048};
+  const int dep[2] = {256, 512};
+  for (int a : cols)
+    for (int bb : bins)
+      for (int d : dep) {
+        Tune t;
+        t.cols_c = a;
+        t.bin_blocks = bb;
+        t.dep_threads = d;
+        cands.push_back(t);
+      }
+  const size_t per = (size_t)h->g.batch * n_bins;
+  double* kk = (double*)h->tune_out;
+  double* pp = kk + per;
+  int64_t* nm = (int64_t*)(pp + per);
+  hipEvent_t e0, e1;
+  if ((st = dev_err(hipEventCreate(&e0), "event"))) return st;
+  if ((st = dev_err(hipEventCreate(&e1), "event"))) { hipEventDestroy(e0); return st; }
+  int best = 0;
+  float best_ms = 1e30f;
+  const Tune saved = h->tu;
+  for (size_t i = 0; i < cands.size() && st == EST_OK; ++i) {
+    h->tu = cands[i];
+    st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);  // warm-up
+    if (st) break;
+    hipEventRecord(e0, h->stream);
+    for (int it = 0; it < iters && st == EST_OK; ++it)
+      st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
+    hipEventRecord(e1, h->stream);
+    if (st) break;
+    if ((st = dev_err(hipEventSynchronize(e1), "synchronize"))) break;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; best = (int)i; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  h->tu = (st == EST_OK) ? cands[best] : saved;
+  h->state = (st == EST_OK) ? kXY : kCreated;
+  if (st == EST_OK && choice) *choice = best;
+  return st;
+}
+
+est_status estimator_copy_grid(est_handle h, int32_t which, int32_t mock, float* dst) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (which != 1 && which != 2) return fail(EST_EINVAL, "which must be 1 or 2");
+  if (which == 2 && !h->g.il) return fail(EST_EINVAL, "grid 2 exists only with interlacing");
+  if (mock < 0 || mock >= h->g.batch) return fail(EST_EINVAL, "mock out of range");
+  if (!dst) return fail(EST_EINVAL, "dst is NULL");
+  if (h->state != kDeposited) return fail(EST_ESTATE, "grids are only available right after a deposit");
+  return dev_err(launch_copy_grid(h->g, h->b, which, mock, dst, h->stream), "copy grid");
+}
+
+est_status estimator_sample_delta(est_handle h, int32_t mock, const int32_t* modes, int64_t n, double* out) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (mock < 0 || mock >= h->g.batch) return fail(EST_EINVAL, "mock out of range");
+  if (!modes || !out || n < 1) return fail(EST_EINVAL, "modes/out missing");
+  if ((st = to_spectrum(h))) return st;
+  return dev_err(launch_sample_delta(h->g, h->b, mock, modes, n, out, h->stream), "sample delta");
+}
+
+}  // extern "C"

@@ -1,0 +1,523 @@
+// Mass assignment (Sec. 2.3, eq. delgrid) onto the primary grid and the grid
+// shifted by H/2 on every axis (Sec. 3.1), and its adjoint gather.
+//
+// Design (gfx950): particles are counting-sorted by bucket (kBucket^3 cells)
+// so that every deposit workgroup owns one output tile of T^3 cells outright:
+// it reads the particles of the buckets that can reach the tile, adds the
+// clipped footprints of both grids with LDS float atomics, and writes the
+// finished tile once with coalesced stores.  No global atomics touch the grid
+// and the grid needs no clearing.  A particle whose base cell is c reaches
+// cells c-1 .. c+3 of either grid for every p <= 4, so the buckets holding
+// cells t0-3 .. t0+T are enough.
+#include "fsest_internal.hpp"
+
+namespace fsest {
+
+// ------------------------------------------------------------------ utils
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  np[i] = offsets ? (offsets[i + 1] - offsets[i]) : n_total;
+}
+
+hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counts, dim3((batch + 63) / 64), dim3(64), 0, s, offsets, n_total,
+                     batch, np);
+  return hipGetLastError();
+}
+
+// set index of particle j: largest i with offsets[i] <= j (offsets has batch+1 entries)
+__device__ __forceinline__ int mock_of(const int64_t* offsets, int batch, int64_t j) {
+  if (batch == 1 || offsets == nullptr) return 0;
+  int lo = 0, hi = batch;  // offsets[lo] <= j < offsets[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (offsets[mid] <= j) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename TP>
+__device__ __forceinline__ void load_pos(const TP* pos, int64_t j, double& x, double& y, double& z) {
+  x = (double)pos[3 * j + 0];
+  y = (double)pos[3 * j + 1];
+  z = (double)pos[3 * j + 2];
+}
+
+__device__ __forceinline__ int base_cell(double u, int n) {
+  return ((int)floor(u)) & (n - 1);
+}
+
+// ------------------------------------------------------------------ sort
+template <typename TP>
+__global__ __launch_bounds__(256) void k_bucket_count(const TP* __restrict__ pos, int64_t n_total,
+                                                      const int64_t* __restrict__ offsets, Geom g,
+                                                      uint32_t* __restrict__ counts,
+                                                      uint32_t* __restrict__ rank) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_total) return;
+  double x, y, z;
+  load_pos(pos, j, x, y, z);
+  const int mock = mock_of(offsets, g.batch, j);
+  const int bx = base_cell(grid_coord(x, g.box, g.inv), g.n) / kBucket;
+  const int by = base_cell(grid_coord(y, g.box, g.inv), g.n) / kBucket;
+  const int bz = base_cell(grid_coord(z, g.box, g.inv), g.n) / kBucket;
+  const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
+  rank[j] = atomicAdd(&counts[key], 1u);
+}
+
+template <typename TP>
+__global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ pos, int64_t n_total,
+                                                        const int64_t* __restrict__ offsets, Geom g,
+                                                        const uint32_t* __restrict__ boff,
+                                                        const uint32_t* __restrict__ rank,
+                                                        TP* __restrict__ sorted) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_total) return;
+  TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+  const int mock = mock_of(offsets, g.batch, j);
+  const int bx = base_cell(grid_coord((double)px, g.box, g.inv), g.n) / kBucket;
+  const int by = base_cell(grid_coord((double)py, g.box, g.inv), g.n) / kBucket;
+  const int bz = base_cell(grid_coord((double)pz, g.box, g.inv), g.n) / kBucket;
+  const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
+  const int64_t dst = (int64_t)boff[key] + rank[j];
+  sorted[3 * dst + 0] = px;
+  sorted[3 * dst + 1] = py;
+  sorted[3 * dst + 2] = pz;
+}
+
+// exclusive scan of n items in place, 2048 items per block
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  // Hillis-Steele over the block in LDS (256 entries)
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    uint32_t a = (t >= off) ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  total = sh[kScanThreads - 1];
+  uint32_t incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(uint32_t* data, size_t n, uint32_t* sums) {
+  __shared__ uint32_t sh[kScanThreads];
+  const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? data[base + i] : 0u;
+    uint32_t c = v[i];
+    v[i] = run;
+    run += c;
+  }
+  uint32_t total;
+  uint32_t pre = block_exclusive_scan(run, sh, total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) data[base + i] = v[i] + pre;
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t* sums, int nblk) {
+  __shared__ uint32_t sh[kScanThreads];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nblk; c0 += kScanThreads) {
+    int i = c0 + threadIdx.x;
+    uint32_t v = (i < nblk) ? sums[i] : 0u;
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan(v, sh, total);
+    if (i < nblk) sums[i] = pre + carry;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t* data, size_t n, const uint32_t* sums) {
+  const uint32_t add = sums[blockIdx.x];
+  const size_t base = (size_t)blockIdx.x * kScanBlock;
+  for (int i = threadIdx.x; i < kScanBlock; i += kScanThreads)
+    if (base + i < n) data[base + i] += add;
+}
+
+hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                       int64_t n_total, const Buffers& b, hipStream_t s) {
+  const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
+  hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
+  if (e != hipSuccess) return e;
+  const unsigned pblocks = (unsigned)((n_total + 255) / 256);
+  if (dt == EST_F32)
+    hipLaunchKernelGGL(k_bucket_count<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
+                       n_total, offsets, g, b.boff, b.rank);
+  else
+    hipLaunchKernelGGL(k_bucket_count<double>, dim3(pblocks), dim3(256), 0, s, (const double*)pos,
+                       n_total, offsets, g, b.boff, b.rank);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t n = nkeys + 1;
+  const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, b.scan_tmp, nblk);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (dt == EST_F32)
+    hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
+                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted);
+  else
+    hipLaunchKernelGGL(k_bucket_scatter<double>, dim3(pblocks), dim3(256), 0, s,
+                       (const double*)pos, n_total, offsets, g, b.boff, b.rank,
+                       (double*)b.sorted);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ stencils
+// Cells (mod N) and weights of the p-point stencil of one axis, for grid
+// coordinate u (float64).  Even p: first cell floor(u) - (p/2 - 1); odd p:
+// first cell floor(u + 1/2) - (p-1)/2.  Weights are W^(p)(cell - u) of
+// Sec. 2.3 written per offset with f = u - floor(...).
+template <int P>
+__device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], float (&w)[P]) {
+  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
+  const int first = (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
+  const float f = (float)(u - fl);
+  if constexpr (P == 1) {
+    w[0] = 1.0f;
+  } else if constexpr (P == 2) {
+    w[0] = 1.0f - f;
+    w[1] = f;
+  } else if constexpr (P == 3) {
+    const float a = 0.5f - f, c = 0.5f + f;
+    w[0] = 0.5f * a * a;
+    w[1] = 0.75f - f * f;
+    w[2] = 0.5f * c * c;
+  } else {
+    const float t = 1.0f - f;
+    const float f2 = f * f, t2 = t * t;
+    w[0] = t2 * t * (1.0f / 6.0f);
+    w[1] = (4.0f - 6.0f * f2 + 3.0f * f2 * f) * (1.0f / 6.0f);
+    w[2] = (4.0f - 6.0f * t2 + 3.0f * t2 * t) * (1.0f / 6.0f);
+    w[3] = f2 * f * (1.0f / 6.0f);
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) cell[i] = (first + i) & (n - 1);
+}
+
+// derivative dW/ds of the same weights (s = cell - u)
+template <int P>
+__device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
+  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
+  const float f = (float)(u - fl);
+  if constexpr (P == 1) {
+    dw[0] = 0.0f;
+  } else if constexpr (P == 2) {
+    // s = -f (|s|<1, s<=0) -> W' = +1 ; s = 1-f > 0 -> W' = -1
+    // at f == 0: s = 0 gives sign(0) = 0 and s = 1 lies outside |s| < 1
+    dw[0] = (f > 0.0f) ? 1.0f : 0.0f;
+    dw[1] = (f > 0.0f) ? -1.0f : 0.0f;
+  } else if constexpr (P == 3) {
+    // s0 = -1-f, s1 = -f, s2 = 1-f
+    dw[0] = (0.5f - f);           // W' = -(3/2-|s|) sgn(s), s<0 -> +(1/2 - f)
+    dw[1] = 2.0f * f;             // -2 s
+    dw[2] = -(0.5f + f);          // s>0 -> -(3/2 - (1-f))
+  } else {
+    const float t = 1.0f - f;
+    // s0 = -1-f (|s| in [1,2)): W' = +(1/2)(2-|s|)^2 = t^2/2
+    dw[0] = 0.5f * t * t;
+    // s1 = -f: W' = -2 s + 1.5 s |s| = 2 f - 1.5 f^2
+    dw[1] = 2.0f * f - 1.5f * f * f;
+    // s2 = 1 - f = t: W' = -2 t + 1.5 t^2
+    dw[2] = -2.0f * t + 1.5f * t * t;
+    // s3 = 2 - f (|s| in (1,2]): W' = -(1/2)(2-|s|)^2 = -f^2/2
+    dw[3] = -0.5f * f * f;
+  }
+}
+
+// ------------------------------------------------------------------ deposit
+struct DepRanges {
+  uint32_t start[72];
+  uint32_t pref[73];
+  int count;
+};
+
+template <int P, bool IL, typename TP>
+__global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
+                                                 const uint32_t* __restrict__ boff, float* grid,
+                                                 Geom g) {
+  constexpr int TM = kTileMax;
+  constexpr int NG = IL ? 2 : 1;
+  __shared__ float acc[NG * TM * TM * TM];
+  __shared__ DepRanges rg;
+  const int n = g.n, T = g.tile, nb = g.nb;
+  const int tpa = n / T;  // tiles per axis
+  const int64_t tid_all = blockIdx.x;
+  const int mock = (int)(tid_all / ((int64_t)tpa * tpa * tpa));
+  const int trem = (int)(tid_all % ((int64_t)tpa * tpa * tpa));
+  const int tx = trem / (tpa * tpa), ty = (trem / tpa) % tpa, tz = trem % tpa;
+  const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
+  const int T3 = T * T * T;
+
+  for (int i = threadIdx.x; i < NG * T3; i += blockDim.x) acc[i] = 0.0f;
+
+  // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
+  int cnt = T / kBucket + 2;
+  if (cnt > nb) cnt = nb;
+  const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - 1 + nb) % nb;
+  const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - 1 + nb) % nb;
+  const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - 1 + nb) % nb;
+  const int ncomb = cnt * cnt;
+  const int64_t mbase = (int64_t)mock * nb * nb * nb;
+  if ((int)threadIdx.x < ncomb) {
+    const int ix = threadIdx.x / cnt, iy = threadIdx.x % cnt;
+    const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
+    const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
+    const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
+    uint32_t s0, e0, s1 = 0, e1 = 0;
+    if (z1 <= nb) {
+      s0 = boff[row + b0z];
+      e0 = boff[row + z1];
+    } else {
+      s0 = boff[row + b0z];
+      e0 = boff[row + nb];
+      s1 = boff[row];
+      e1 = boff[row + (z1 - nb)];
+    }
+    rg.start[2 * threadIdx.x] = s0;
+    rg.pref[2 * threadIdx.x + 1] = e0 - s0;
+    rg.start[2 * threadIdx.x + 1] = s1;
+    rg.pref[2 * threadIdx.x + 2] = e1 - s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rg.pref[0] = 0;
+    for (int i = 1; i <= 2 * ncomb; ++i) rg.pref[i] += rg.pref[i - 1];
+    rg.count = 2 * ncomb;
+  }
+  __syncthreads();
+  const uint32_t total = rg.pref[rg.count];
+  const int nr = rg.count;
+
+  for (uint32_t item = threadIdx.x; item < total; item += blockDim.x) {
+    int lo = 0, hi = nr;  // pref[lo] <= item < pref[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (rg.pref[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int64_t j = (int64_t)rg.start[lo] + (item - rg.pref[lo]);
+    double x, y, z;
+    load_pos(sorted, j, x, y, z);
+    const double ux = grid_coord(x, g.box, g.inv);
+    const double uy = grid_coord(y, g.box, g.inv);
+    const double uz = grid_coord(z, g.box, g.inv);
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const double sh = gi ? 0.5 : 0.0;
+      int cx[P], cy[P], cz[P];
+      float wx[P], wy[P], wz[P];
+      stencil_1d<P>(ux + sh, n, cx, wx);
+      stencil_1d<P>(uy + sh, n, cy, wy);
+      stencil_1d<P>(uz + sh, n, cz, wz);
+      int lx[P], ly[P], lz[P];
+      unsigned mx = 0, my = 0, mz = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        lx[i] = (cx[i] - t0x) & (n - 1);
+        ly[i] = (cy[i] - t0y) & (n - 1);
+        lz[i] = (cz[i] - t0z) & (n - 1);
+        mx |= (lx[i] < T) ? (1u << i) : 0u;
+        my |= (ly[i] < T) ? (1u << i) : 0u;
+        mz |= (lz[i] < T) ? (1u << i) : 0u;
+      }
+      if (!mx || !my || !mz) continue;
+      float* a = acc + gi * T3;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        if (!(mx & (1u << i))) continue;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          if (!(my & (1u << k))) continue;
+          const float wxy = wx[i] * wy[k];
+          const int rowi = (lx[i] * T + ly[k]) * T;
+#pragma unroll
+          for (int l = 0; l < P; ++l) {
+            if (!(mz & (1u << l))) continue;
+            atomicAdd(&a[rowi + lz[l]], wxy * wz[l]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const int64_t n3 = (int64_t)n * n * n;
+  for (int i = threadIdx.x; i < T3; i += blockDim.x) {
+    const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
+    const int64_t cidx = mock * n3 + ((int64_t)(t0x + lx) * n + (t0y + ly)) * n + (t0z + lz);
+    if constexpr (IL) {
+      reinterpret_cast<float2*>(grid)[cidx] = make_float2(acc[i], acc[T3 + i]);
+    } else {
+      grid[cidx] = acc[i];
+    }
+  }
+}
+
+template <int P, bool IL>
+static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, int threads,
+                               hipStream_t s) {
+  const int tpa = g.n / g.tile;
+  const unsigned blocks = (unsigned)((int64_t)g.batch * tpa * tpa * tpa);
+  if (dt == EST_F32)
+    hipLaunchKernelGGL((k_deposit<P, IL, float>), dim3(blocks), dim3(threads), 0, s,
+                       (const float*)b.sorted, b.boff, (float*)b.grid, g);
+  else
+    hipLaunchKernelGGL((k_deposit<P, IL, double>), dim3(blocks), dim3(threads), 0, s,
+                       (const double*)b.sorted, b.boff, (float*)b.grid, g);
+}
+
+template <int P>
+static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, int threads,
+                               hipStream_t s) {
+  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, threads, s);
+  else dispatch_deposit_t<P, false>(g, dt, b, threads, s);
+}
+
+hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
+                          hipStream_t s) {
+  int threads = tu.dep_threads;
+  if (threads != 128 && threads != 256 && threads != 512) threads = 256;
+  switch (g.order) {
+    case 1: dispatch_deposit_p<1>(g, dt, b, threads, s); break;
+    case 2: dispatch_deposit_p<2>(g, dt, b, threads, s); break;
+    case 3: dispatch_deposit_p<3>(g, dt, b, threads, s); break;
+    default: dispatch_deposit_p<4>(g, dt, b, threads, s); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ test hook
+__global__ void k_copy_grid(const float* grid, Geom g, int which, int mock, float* dst) {
+  const int64_t n3 = (int64_t)g.n * g.n * g.n;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n3; i += stride) {
+    if (g.il)
+      dst[i] = grid[2 * (mock * n3 + i) + (which - 1)];
+    else
+      dst[i] = grid[mock * n3 + i];
+  }
+}
+
+hipError_t launch_copy_grid(const Geom& g, const Buffers& b, int which, int mock, float* dst,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_grid, dim3(4096), dim3(256), 0, s, (const float*)b.grid, g, which,
+                     mock, dst);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ adjoint gather
+// dL/dx_{j,alpha} = -(N/L) sum_a sum_{g in stencil_a} G_a(g) W'(s_alpha) prod_{beta != alpha} W(s_beta)
+// where G_a = dL/drho_a sits in the grid buffer with the deposit's layout.
+template <int P, bool IL, typename TP>
+__global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos, int64_t n_total,
+                                                     const int64_t* __restrict__ offsets,
+                                                     const float* __restrict__ grid, Geom g,
+                                                     TP* __restrict__ grad) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_total) return;
+  double x, y, z;
+  load_pos(pos, j, x, y, z);
+  const int mock = mock_of(offsets, g.batch, j);
+  const int n = g.n;
+  const int64_t n3 = (int64_t)n * n * n;
+  const double u[3] = {grid_coord(x, g.box, g.inv), grid_coord(y, g.box, g.inv),
+                       grid_coord(z, g.box, g.inv)};
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  constexpr int NG = IL ? 2 : 1;
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    const double sh = gi ? 0.5 : 0.0;
+    int c[3][P];
+    float w[3][P], d[3][P];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      stencil_1d<P>(u[ax] + sh, n, c[ax], w[ax]);
+      stencil_1d_deriv<P>(u[ax] + sh, d[ax]);
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+      for (int bq = 0; bq < P; ++bq) {
+        const int64_t row = mock * n3 + ((int64_t)c[0][a] * n + c[1][bq]) * n;
+#pragma unroll
+        for (int cq = 0; cq < P; ++cq) {
+          const int64_t idx = row + c[2][cq];
+          const float gv = IL ? grid[2 * idx + gi] : grid[idx];
+          gx += gv * d[0][a] * w[1][bq] * w[2][cq];
+          gy += gv * w[0][a] * d[1][bq] * w[2][cq];
+          gz += gv * w[0][a] * w[1][bq] * d[2][cq];
+        }
+      }
+    }
+  }
+  const double sc = -(double)n / g.box;
+  grad[3 * j + 0] = (TP)(sc * gx);
+  grad[3 * j + 1] = (TP)(sc * gy);
+  grad[3 * j + 2] = (TP)(sc * gz);
+}
+
+template <int P>
+static void dispatch_gather(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                            int64_t n_total, const Buffers& b, void* grad, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n_total + 255) / 256);
+  if (dt == EST_F32) {
+    if (g.il)
+      hipLaunchKernelGGL((k_gather_grad<P, true, float>), dim3(blocks), dim3(256), 0, s,
+                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, (float*)grad);
+    else
+      hipLaunchKernelGGL((k_gather_grad<P, false, float>), dim3(blocks), dim3(256), 0, s,
+                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, (float*)grad);
+  } else {
+    if (g.il)
+      hipLaunchKernelGGL((k_gather_grad<P, true, double>), dim3(blocks), dim3(256), 0, s,
+                         (const double*)pos, n_total, offsets, (const float*)b.grid, g,
+                         (double*)grad);
+    else
+      hipLaunchKernelGGL((k_gather_grad<P, false, double>), dim3(blocks), dim3(256), 0, s,
+                         (const double*)pos, n_total, offsets, (const float*)b.grid, g,
+                         (double*)grad);
+  }
+}
+
+hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                              int64_t n_total, const Buffers& b, void* grad, hipStream_t s) {
+  switch (g.order) {
+    case 1: dispatch_gather<1>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    case 2: dispatch_gather<2>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    case 3: dispatch_gather<3>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    default: dispatch_gather<4>(g, pos, dt, offsets, n_total, b, grad, s); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fsest

@@ -1,0 +1,145 @@
+// 3D complex FFT passes over the grid (Sec. 2.3: one forward transform per
+// grid; the two real grids travel as one complex grid rho1 + i rho2, or as a
+// real grid packed pairwise along z when there is no interlacing).
+//
+// The grid is [batch][N][N][nz] complex, z contiguous.  One pass per axis:
+//   z (contiguous): k_fft_rows, LPB rows per workgroup, padded rows in LDS;
+//   x, y (strided): k_fft_cols, C adjacent lines per workgroup so that every
+//                   global access is a run of C complex values (C*8 bytes),
+//                   lines interleaved in LDS.
+// Every workgroup owns its lines, so the passes run in place.
+#include "fft_line.hpp"
+#include "fsest_internal.hpp"
+
+namespace fsest {
+
+template <int L>
+struct RowShape {
+  static constexpr int TPL = LinePlan<L>::TPL;
+  static constexpr int LPB = (256 / TPL) > 0 ? (256 / TPL) : 1;
+};
+
+template <int L, int DIR>
+__global__ __launch_bounds__(RowShape<L>::LPB * RowShape<L>::TPL) void k_fft_rows(
+    float2* __restrict__ data, int64_t nrows, const float2* __restrict__ tw) {
+  constexpr int TPL = RowShape<L>::TPL;
+  constexpr int LPB = RowShape<L>::LPB;
+  constexpr int EPT = LinePlan<L>::EPT;
+  constexpr int ROWP = LdsLine<L>::padded;
+  __shared__ float2 lds[LPB * ROWP];
+  const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const int64_t row = (int64_t)blockIdx.x * LPB + line;
+  const bool valid = row < nrows;
+  float2* p = data + row * L;
+  float2 v[EPT];
+  static_for<0, EPT>([&](auto e) { v[e] = valid ? p[t + e * TPL] : make_float2(0.f, 0.f); });
+  line_fft<L, DIR, 1>(v, t, lds + line * ROWP, tw);
+  if (valid) static_for<0, EPT>([&](auto e) { p[t + e * TPL] = v[e]; });
+}
+
+template <int L, int DIR, int C>
+__global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols(
+    float2* __restrict__ data, int64_t elem_stride, int64_t chunks_per_outer, int64_t outer_stride,
+    const float2* __restrict__ tw) {
+  constexpr int TPL = LinePlan<L>::TPL;
+  constexpr int EPT = LinePlan<L>::EPT;
+  extern __shared__ float2 lds_dyn[];
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t outer = blockIdx.x / chunks_per_outer;
+  const int64_t ic = blockIdx.x % chunks_per_outer;
+  float2* p = data + outer * outer_stride + ic * C + c;
+  float2 v[EPT];
+  static_for<0, EPT>([&](auto e) { v[e] = p[(int64_t)(t + e * TPL) * elem_stride]; });
+  line_fft<L, DIR, C>(v, t, lds_dyn + c, tw);
+  static_for<0, EPT>([&](auto e) { p[(int64_t)(t + e * TPL) * elem_stride] = v[e]; });
+}
+
+template <int L, int DIR>
+static hipError_t rows_t(float2* data, int64_t nrows, const float2* tw, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nrows + RowShape<L>::LPB - 1) / RowShape<L>::LPB);
+  hipLaunchKernelGGL((k_fft_rows<L, DIR>), dim3(blocks), dim3(RowShape<L>::LPB * RowShape<L>::TPL),
+                     0, s, data, nrows, tw);
+  return hipGetLastError();
+}
+
+template <int L, int DIR, int C>
+static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                          int64_t outer_stride, const float2* tw, hipStream_t s) {
+  const int64_t chunks = inner / C;
+  const size_t lds = sizeof(float2) * (size_t)L * C;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_fft_cols<L, DIR, C>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_fft_cols<L, DIR, C>), dim3((unsigned)(chunks * outer)),
+                     dim3(C * LinePlan<L>::TPL), lds, s, data, elem_stride, chunks, outer_stride, tw);
+  return hipGetLastError();
+}
+
+template <int L, int DIR>
+static hipError_t cols_t(float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                         int64_t outer_stride, int c, const float2* tw, hipStream_t s) {
+  if (c >= 16 && inner % 16 == 0) return cols_tc<L, DIR, 16>(data, elem_stride, inner, outer, outer_stride, tw, s);
+  if (c >= 8 && inner % 8 == 0) return cols_tc<L, DIR, 8>(data, elem_stride, inner, outer, outer_stride, tw, s);
+  return cols_tc<L, DIR, 4>(data, elem_stride, inner, outer, outer_stride, tw, s);
+}
+
+template <int DIR>
+static hipError_t rows_dir(int L, float2* data, int64_t nrows, const float2* tw, hipStream_t s) {
+  switch (L) {
+    case 4: return rows_t<4, DIR>(data, nrows, tw, s);
+    case 8: return rows_t<8, DIR>(data, nrows, tw, s);
+    case 16: return rows_t<16, DIR>(data, nrows, tw, s);
+    case 32: return rows_t<32, DIR>(data, nrows, tw, s);
+    case 64: return rows_t<64, DIR>(data, nrows, tw, s);
+    case 128: return rows_t<128, DIR>(data, nrows, tw, s);
+    case 256: return rows_t<256, DIR>(data, nrows, tw, s);
+    case 512: return rows_t<512, DIR>(data, nrows, tw, s);
+    case 1024: return rows_t<1024, DIR>(data, nrows, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DIR>
+static hipError_t cols_dir(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                           int64_t outer_stride, int c, const float2* tw, hipStream_t s) {
+  switch (L) {
+    case 8: return cols_t<8, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 16: return cols_t<16, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 32: return cols_t<32, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 64: return cols_t<64, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 128: return cols_t<128, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 256: return cols_t<256, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 512: return cols_t<512, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    case 1024: return cols_t<1024, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch, int nz_len,
+                           const float2* tw_axis, const Tune& tu, hipStream_t s) {
+  const int64_t n = g.n, nz = nz_len;
+  if (axis == 2) {
+    const int64_t nrows = (int64_t)batch * n * n;
+    return dir < 0 ? rows_dir<-1>((int)nz, data, nrows, tw_axis, s)
+                   : rows_dir<+1>((int)nz, data, nrows, tw_axis, s);
+  }
+  int64_t elem_stride, inner, outer, outer_stride;
+  if (axis == 0) {
+    elem_stride = n * nz;
+    inner = n * nz;
+    outer = batch;
+    outer_stride = n * n * nz;
+  } else {
+    elem_stride = nz;
+    inner = nz;
+    outer = (int64_t)batch * n;
+    outer_stride = n * nz;
+  }
+  return dir < 0 ? cols_dir<-1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s)
+                 : cols_dir<+1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s);
+}
+
+}  // namespace fsest

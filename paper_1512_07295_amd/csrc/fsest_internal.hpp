@@ -1,0 +1,113 @@
+// Internal declarations shared by the HIP translation units of libfsest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/fsest.h"
+
+namespace fsest {
+
+constexpr int kBucket = 4;      // bucket edge in cells (particles sorted by bucket)
+constexpr int kTileMax = 16;    // deposit tile edge in cells (LDS-resident)
+constexpr int kMaxBins = 512;   // largest n_bins (N / 2 at N = 1024)
+constexpr int kMaxBinBlocks = 2048;  // upper bound of P(k) reduction blocks per set
+
+// Geometry and per-call constants that device code needs.
+struct Geom {
+  int n;          // N
+  int nz;         // complex length of the contiguous axis: N (interlaced) or N/2
+  int order;      // p
+  int il;         // interlacing on/off
+  int batch;
+  int nb;         // buckets per axis = N / kBucket
+  int tile;       // deposit tile edge
+  double box;     // L
+  double inv;     // fl64(N / L)
+};
+
+// Work buffers carved out of the caller's workspace.
+struct Buffers {
+  float2* grid;            // batch * N * N * nz complex (rho1 + i rho2, or packed reals)
+  void* sorted;            // max_particles * 3 * 8 bytes
+  uint32_t* rank;          // max_particles
+  uint32_t* boff;          // batch * nb^3 + 1 bucket offsets
+  uint32_t* scan_tmp;      // scan block sums
+  float2* tw_n;            // exp(-2 pi i n / N)
+  float2* tw_nz;           // exp(-2 pi i n / nz)
+  float* inv_w2;           // 1 / W_1D(m(i))^2 for FFT index i (N entries)
+  float* win1;             // W_1D(m(i)) for FFT index i (N entries)
+  float2* phase;           // exp(+i pi s / N), s = 0..2N-1
+  double* partials;        // batch * kMaxBinBlocks * kMaxBins
+  int64_t* mode_n;         // kMaxBins
+  double* mode_k;          // kMaxBins
+  int64_t* np;             // batch particle counts
+  double* coef;            // batch * kMaxBins adjoint coefficients
+  uint64_t* mode_partials_n;  // kMaxBinBlocks * kMaxBins
+  double* mode_partials_k;    // kMaxBinBlocks * kMaxBins
+};
+
+// Launch shapes chosen per handle (the autotuner changes them).
+struct Tune {
+  int cols_c = 16;        // lines per workgroup of the strided FFT passes
+  int bin_blocks = 1024;  // reduction workgroups per set in the fused P(k) pass
+  int dep_threads = 256;  // threads per deposit workgroup
+};
+
+// Device helper: wrap one float64 coordinate into [0, L) with the fixed
+// operation sequence x - L floor(x/L), +L if negative, -L if >= L, and 0 for
+// anything left outside [0, L) (also NaN).
+__device__ __forceinline__ double wrap_coord(double x, double box) {
+#pragma clang fp contract(off)
+  if (x >= 0.0 && x < box) return x;  // x - L*floor(x/L) == x exactly here
+  double q = floor(x / box);
+  double xw = x - q * box;
+  if (xw < 0.0) xw = xw + box;
+  if (xw >= box) xw = xw - box;
+  if (!(xw >= 0.0 && xw < box)) xw = 0.0;
+  return xw;
+}
+
+__device__ __forceinline__ double grid_coord(double x, double box, double inv) {
+#pragma clang fp contract(off)
+  return wrap_coord(x, box) * inv;
+}
+
+// ---- launchers (return hipError_t of the last launch) ----
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
+                             hipStream_t s);
+hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                       int64_t n_total, const Buffers& b, hipStream_t s);
+hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
+                          hipStream_t s);
+hipError_t launch_copy_grid(const Geom& g, const Buffers& b, int which, int mock, float* dst,
+                            hipStream_t s);
+hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                              int64_t n_total, const Buffers& b, void* grad, hipStream_t s);
+
+hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s);
+// direction: -1 forward, +1 inverse.  axis 0 = x (stride N*nz), 1 = y (stride nz), 2 = z (rows).
+hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch,
+                           int nz_len, const float2* tw_axis, const Tune& tu, hipStream_t s);
+hipError_t launch_mode_table(const Geom& g, const Buffers& b, int n_dk, int n_bins, hipStream_t s);
+// fused last-axis forward FFT (if do_fft) + interlace + deconvolve + shell sums + finalize
+hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do_fft, int n_dk,
+                        int n_bins, int subtract_shot, double* k, double* p, int64_t* nmodes,
+                        hipStream_t s);
+// adjoint: coefficients from dL/dP, then fused z-forward, gradient spectrum, z-inverse
+hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& tu,
+                                   const double* dldp, int n_dk, int n_bins, hipStream_t s);
+hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,
+                               int64_t n, double* out, hipStream_t s);
+// bispectrum
+hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
+                             bool counts_only, float2* out, hipStream_t s);
+hipError_t launch_triple_sums(int64_t npts, const float2* ipairs, const float2* jpairs, int n_bins,
+                              const int32_t* tri, int64_t n_tri, double* part, int n_xr,
+                              hipStream_t s);
+hipError_t launch_bispec_finalize(const double* part, int n_xr, int64_t n_tri, double vol,
+                                  double n3, double* bk, double* ntri, hipStream_t s);
+
+}  // namespace fsest

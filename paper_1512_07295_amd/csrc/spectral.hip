@@ -1,0 +1,665 @@
+// Fourier-space stages: interlacing (eq. intdelta), window deconvolution
+// (eqs. windowcorrection, intkerFT), |k|-shell sums for P(k) (eq. ps and the
+// estimator of Sec. 2.2), the adjoint spectrum, and the FFT-shell bispectrum
+// (Sec. 4.1, eqs. Best2, IntI).
+//
+// The grid holds Z = FFT(rho1 + i rho2) (interlaced) or Z = FFT of the real
+// grid packed pairwise along z (h = N/2 complex columns).  Either way the
+// transforms of the real grids at m need Z(m) and Z(-m) together, so the last
+// axis is processed by pairs of rows (x, y) and (-x, -y): a workgroup runs
+// the z FFT of both rows, keeps them in LDS and finishes every half-space mode
+// of the pair without writing the spectrum back.
+#include "fft_line.hpp"
+#include "fsest_internal.hpp"
+
+namespace fsest {
+
+// ------------------------------------------------------------------ tables
+__global__ void k_tables(Geom g, float2* tw_n, float2* tw_nz, float* inv_w2, float* win1,
+                         float2* phase) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  if (i < n) {
+    double s, c;
+    sincospi(-2.0 * i / n, &s, &c);
+    tw_n[i] = make_float2((float)c, (float)s);
+    const int m = (i <= n / 2) ? i : i - n;
+    double w = 1.0;
+    if (m != 0) {
+      const double x = (double)m / n;
+      w = sinpi(x) / (M_PI * x);
+    }
+    double wp = 1.0;
+    for (int k = 0; k < g.order; ++k) wp *= w;
+    win1[i] = (float)wp;
+    inv_w2[i] = (float)(1.0 / (wp * wp));
+  }
+  if (i < g.nz) {
+    double s, c;
+    sincospi(-2.0 * i / g.nz, &s, &c);
+    tw_nz[i] = make_float2((float)c, (float)s);
+  }
+  if (i < 2 * n) {
+    double s, c;
+    sincospi((double)i / n, &s, &c);
+    phase[i] = make_float2((float)c, (float)s);
+  }
+}
+
+hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s) {
+  const int n = 2 * g.n;
+  hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, g, b.tw_n, b.tw_nz,
+                     b.inv_w2, b.win1, b.phase);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int signed_freq(int i, int n) { return (i <= n / 2) ? i : i - n; }
+
+// shell b with (2b-1)^2 n^2 <= 4 m2 < (2b+1)^2 n^2 (b = 0 below the first shell)
+__device__ __forceinline__ int shell_of(int m2, int n_dk) {
+  const int x = 4 * m2;
+  int r = (int)sqrtf((float)x);
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return ((r / n_dk) + 1) >> 1;
+}
+
+// Row pair q of one set: rows (x, y) and (-x, -y); q < N^2/2 + 2.
+__device__ __forceinline__ void pair_rows(int64_t q, int n, int& x, int& y) {
+  const int h1 = n / 2 + 1;
+  if (q < h1) { x = 0; y = (int)q; return; }
+  q -= h1;
+  const int64_t mid = (int64_t)(n / 2 - 1) * n;
+  if (q < mid) { x = 1 + (int)(q / n); y = (int)(q % n); return; }
+  q -= mid;
+  x = n / 2;
+  y = (int)q;
+}
+
+// Transforms of the real grids at half-space mode (row, mz) from the pair
+// (Za, Zb) = (Z(k), Z(-k)), combined per eq. intdelta: returns C(m).
+template <bool IL>
+__device__ __forceinline__ float2 combined_mode(float2 za, float2 zb, int mx, int my, int mz,
+                                                const float2* __restrict__ phase, int n) {
+  // first and second real transforms: (za + conj zb)/2 and (za - conj zb)/(2i)
+  const float2 f1 = make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y));
+  const float2 f2 = make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x));
+  if constexpr (IL) {
+    const float2 ph = phase[(mx + my + mz) & (2 * n - 1)];  // exp(+i pi (mx+my+mz)/N)
+    return cscale(cadd(f1, cmul(ph, f2)), 0.5f);
+  } else {
+    // even/odd z samples: F = E + exp(-2 pi i mz/N) O
+    const float2 ph = cconj(phase[(2 * mz) & (2 * n - 1)]);
+    return cadd(f1, cmul(ph, f2));
+  }
+}
+
+template <int L>
+struct PairShape {
+  static constexpr int TPL = LinePlan<L>::TPL;
+  static constexpr int PPB = (256 / (2 * TPL)) > 0 ? (256 / (2 * TPL)) : 1;
+  static constexpr int THREADS = PPB * 2 * TPL;
+  static constexpr int ROWP = LdsLine<L>::padded;
+};
+
+// MODE 0: forward z FFT + P(k) shell sums; MODE 1: shell sums of a stored
+// spectrum; MODE 2: forward z FFT, adjoint spectrum, inverse z FFT, write.
+template <int L, bool IL, int MODE>
+__global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
+    float2* __restrict__ data, Geom g, const float2* __restrict__ tw,
+    const float2* __restrict__ phase, const float* __restrict__ inv_w2, int n_dk, int n_bins,
+    double* __restrict__ partials, const double* __restrict__ coef) {
+  constexpr int TPL = PairShape<L>::TPL;
+  constexpr int PPB = PairShape<L>::PPB;
+  constexpr int ROWP = PairShape<L>::ROWP;
+  constexpr int EPT = LinePlan<L>::EPT;
+  __shared__ float2 rows[2 * PPB * ROWP];
+  __shared__ double hist[kMaxBins];
+
+  const int n = g.n;
+  const int mock = blockIdx.y;
+  const int ps = threadIdx.x / (2 * TPL);
+  const int r = (threadIdx.x / TPL) & 1;
+  const int t = threadIdx.x % TPL;
+  const int64_t npairs = (int64_t)n * n / 2 + 2;
+  const int64_t ngroups = (npairs + PPB - 1) / PPB;
+  float2* own_lds = rows + (2 * ps + r) * ROWP;
+  const float2* par_lds = rows + (2 * ps + (r ^ 1)) * ROWP;
+
+  if constexpr (MODE != 2)
+    for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
+
+  for (int64_t pg = blockIdx.x; pg < ngroups; pg += gridDim.x) {
+    const int64_t q = pg * PPB + ps;
+    const bool valid = q < npairs;
+    int xa = 0, ya = 0;
+    if (valid) pair_rows(q, n, xa, ya);
+    const int xb = (n - xa) & (n - 1), yb = (n - ya) & (n - 1);
+    const bool self = (xa == xb) && (ya == yb);
+    const int xr = r ? xb : xa, yr = r ? yb : ya;
+    float2* gp = data + (((int64_t)mock * n + xr) * n + yr) * L;
+    float2 v[EPT];
+    static_for<0, EPT>([&](auto e) { v[e] = valid ? gp[t + e * TPL] : make_float2(0.f, 0.f); });
+    if constexpr (MODE != 1) line_fft<L, -1, 1>(v, t, own_lds, tw);
+    static_for<0, EPT>([&](auto e) { own_lds[lds_index<1>(t + e * TPL)] = v[e]; });
+    __syncthreads();
+
+    const int mxr = signed_freq(xr, n), myr = signed_freq(yr, n);
+    if constexpr (MODE != 2) {
+      if (valid && !(r == 1 && self)) {
+        const int nm = n / 2 + 1;
+        const int per = (nm + TPL - 1) / TPL;
+        const int z0 = t * per;
+        const int z1 = min(z0 + per, nm);
+        const float wxy = inv_w2[xr] * inv_w2[yr];
+        const int r2 = mxr * mxr + myr * myr;
+        int cur_b = -1;
+        float cur = 0.0f;
+        for (int mz = z0; mz < z1; ++mz) {
+          const int m2 = r2 + mz * mz;
+          if (m2 == 0) continue;
+          const int b = shell_of(m2, n_dk);
+          if (b < 1 || b > n_bins) continue;
+          float2 za, zb;
+          if constexpr (IL) {
+            za = own_lds[lds_index<1>(mz)];
+            zb = par_lds[lds_index<1>((n - mz) & (n - 1))];
+          } else {
+            const int h = n / 2;
+            const int kz = mz & (h - 1);
+            za = own_lds[lds_index<1>(kz)];
+            zb = par_lds[lds_index<1>((h - kz) & (h - 1))];
+          }
+          const float2 c = combined_mode<IL>(za, zb, mxr, myr, mz, phase, n);
+          const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
+          const float val = wgt * (c.x * c.x + c.y * c.y) * wxy * inv_w2[mz];
+          if (b != cur_b) {
+            if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)cur);
+            cur_b = b;
+            cur = 0.0f;
+          }
+          cur += val;
+        }
+        if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)cur);
+      }
+      __syncthreads();
+    } else {
+      // gradient of the loss with respect to Z at this thread's elements
+      const double* cf = coef + (int64_t)mock * n_bins;
+      const int xp = r ? xa : xb, yp = r ? ya : yb;  // partner row
+      const int mxp = signed_freq(xp, n), myp = signed_freq(yp, n);
+      float2 out[EPT];
+      static_for<0, EPT>([&](auto e) {
+        const int j = t + e * TPL;
+        float2 acc = make_float2(0.f, 0.f);
+        if (valid) {
+          if constexpr (IL) {
+            const float2 z1 = own_lds[lds_index<1>(j)];
+            const float2 z2 = par_lds[lds_index<1>((n - j) & (n - 1))];
+            // (a) mode (own row, j) holds Z(m) = z1
+            if (j <= n / 2) {
+              const int m2 = mxr * mxr + myr * myr + j * j;
+              const int b = m2 ? shell_of(m2, n_dk) : 0;
+              if (b >= 1 && b <= n_bins) {
+                const float2 c = combined_mode<true>(z1, z2, mxr, myr, j, phase, n);
+                const float wgt = (j == 0 || j == n / 2) ? 1.0f : 2.0f;
+                const float s = wgt * (float)cf[b - 1] * inv_w2[xr] * inv_w2[yr] * inv_w2[j];
+                const float2 gc = cscale(c, s);
+                const float2 ph = cconj(phase[(mxr + myr + j) & (2 * n - 1)]);
+                const float2 gf1 = cscale(gc, 0.5f);
+                const float2 gf2 = cscale(cmul(ph, gc), 0.5f);
+                // dZ(m): 1/2 gF1 + (i/2) gF2
+                acc = cadd(acc, make_float2(0.5f * (gf1.x - gf2.y), 0.5f * (gf1.y + gf2.x)));
+              }
+            }
+            // (b) mode (partner row, -j) holds Z(-m') = z1
+            const int jp = (n - j) & (n - 1);
+            if (jp <= n / 2) {
+              const int m2 = mxp * mxp + myp * myp + jp * jp;
+              const int b = m2 ? shell_of(m2, n_dk) : 0;
+              if (b >= 1 && b <= n_bins) {
+                const float2 c = combined_mode<true>(z2, z1, mxp, myp, jp, phase, n);
+                const float wgt = (jp == 0 || jp == n / 2) ? 1.0f : 2.0f;
+                const float s = wgt * (float)cf[b - 1] * inv_w2[xp] * inv_w2[yp] * inv_w2[jp];
+                const float2 gc = cscale(c, s);
+                const float2 ph = cconj(phase[(mxp + myp + jp) & (2 * n - 1)]);
+                const float2 gf1 = cscale(gc, 0.5f);
+                const float2 gf2 = cscale(cmul(ph, gc), 0.5f);
+                // dZ(-m'): 1/2 conj(gF1) + (i/2) conj(gF2)
+                acc = cadd(acc, make_float2(0.5f * (gf1.x + gf2.y), 0.5f * (-gf1.y + gf2.x)));
+              }
+            }
+          } else {
+            const int h = n / 2;
+            const float2 z1 = own_lds[lds_index<1>(j)];
+            const float2 z2 = par_lds[lds_index<1>((h - j) & (h - 1))];
+            // direct sources: modes (own row, mz) with mz = j (and mz = h when j = 0)
+            for (int k = 0; k < ((j == 0) ? 2 : 1); ++k) {
+              const int mz = k ? h : j;
+              const int m2 = mxr * mxr + myr * myr + mz * mz;
+              const int b = m2 ? shell_of(m2, n_dk) : 0;
+              if (b >= 1 && b <= n_bins) {
+                const float2 c = combined_mode<false>(z1, z2, mxr, myr, mz, phase, n);
+                const float wgt = (mz == 0 || mz == h) ? 1.0f : 2.0f;
+                const float s = wgt * (float)cf[b - 1] * inv_w2[xr] * inv_w2[yr] * inv_w2[mz];
+                const float2 gf = cscale(c, s);
+                const float2 ph = phase[(2 * mz) & (2 * n - 1)];  // (cos, sin) of 2 pi mz/N
+                // conj(a) = ((1 - sin), cos) / 2
+                const float2 ca = make_float2(0.5f * (1.0f - ph.y), 0.5f * ph.x);
+                acc = cadd(acc, cmul(ca, gf));
+              }
+            }
+            // conjugate sources: modes (partner row, mz') with -mz' = j mod h (and h when j = 0)
+            for (int k = 0; k < ((j == 0) ? 2 : 1); ++k) {
+              const int mz = k ? h : ((h - j) & (h - 1));
+              const int m2 = mxp * mxp + myp * myp + mz * mz;
+              const int b = m2 ? shell_of(m2, n_dk) : 0;
+              if (b >= 1 && b <= n_bins) {
+                const float2 c = combined_mode<false>(z2, z1, mxp, myp, mz, phase, n);
+                const float wgt = (mz == 0 || mz == h) ? 1.0f : 2.0f;
+                const float s = wgt * (float)cf[b - 1] * inv_w2[xp] * inv_w2[yp] * inv_w2[mz];
+                const float2 gf = cscale(c, s);
+                const float2 ph = phase[(2 * mz) & (2 * n - 1)];
+                // b = ((1 + sin), cos) / 2
+                const float2 bb = make_float2(0.5f * (1.0f + ph.y), 0.5f * ph.x);
+                acc = cadd(acc, cmul(bb, cconj(gf)));
+              }
+            }
+          }
+        }
+        out[e] = acc;
+      });
+      __syncthreads();
+      line_fft<L, +1, 1>(out, t, own_lds, tw);
+      if (valid && !(r == 1 && self))
+        static_for<0, EPT>([&](auto e) { gp[t + e * TPL] = out[e]; });
+      __syncthreads();
+    }
+  }
+
+  if constexpr (MODE != 2) {
+    __syncthreads();
+    double* dst = partials + ((int64_t)mock * gridDim.x + blockIdx.x) * n_bins;
+    for (int i = threadIdx.x; i < n_bins; i += blockDim.x) dst[i] = hist[i];
+  }
+}
+
+// P_b = V S_b / (N_P^2 N_b) [- V/N_P], k_b = k_f K_b / N_b
+__global__ void k_power_finalize(const double* __restrict__ partials, int nblk, int n_bins,
+                                 const int64_t* __restrict__ mode_n, const double* __restrict__ mode_k,
+                                 const int64_t* __restrict__ np, double box, int subtract,
+                                 double* k, double* p, int64_t* nmodes) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mock = blockIdx.y;
+  if (b >= n_bins) return;
+  const double* src = partials + (int64_t)mock * nblk * n_bins + b;
+  double s = 0.0;
+  for (int i = 0; i < nblk; ++i) s += src[(int64_t)i * n_bins];
+  const double vol = box * box * box;
+  const double nb = (double)mode_n[b];
+  const double npart = (double)np[mock];
+  double pk = vol * s / (npart * npart * nb);
+  if (subtract) pk -= vol / npart;
+  if (np[mock] <= 0) pk = __builtin_nan("");
+  const int64_t o = (int64_t)mock * n_bins + b;
+  p[o] = pk;
+  k[o] = (2.0 * M_PI / box) * mode_k[b] / nb;
+  nmodes[o] = mode_n[b];
+}
+
+// coefficient 2 g_b V / (N_b N_P^2) of the adjoint spectrum
+__global__ void k_adjoint_coef(const double* __restrict__ dldp, int n_bins, const int64_t* __restrict__ mode_n,
+                               const int64_t* __restrict__ np, double box, double* coef) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mock = blockIdx.y;
+  if (b >= n_bins) return;
+  const double vol = box * box * box;
+  const double npart = (double)np[mock];
+  const int64_t o = (int64_t)mock * n_bins + b;
+  coef[o] = (np[mock] > 0) ? 2.0 * dldp[o] * vol / ((double)mode_n[b] * npart * npart) : 0.0;
+}
+
+template <int L, bool IL, int MODE>
+static hipError_t pairs_t(const Geom& g, const Buffers& b, int nblk, int n_dk, int n_bins,
+                          const float2* tw, hipStream_t s) {
+  hipLaunchKernelGGL((k_pairs<L, IL, MODE>), dim3(nblk, g.batch), dim3(PairShape<L>::THREADS), 0, s,
+                     b.grid, g, tw, b.phase, b.inv_w2, n_dk, n_bins, b.partials, b.coef);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t pairs_dispatch(const Geom& g, const Buffers& b, int nblk, int n_dk, int n_bins,
+                                 hipStream_t s) {
+  const float2* tw = b.tw_nz;
+#define FSEST_PAIRS_CASE(LL)                                                     \
+  case LL:                                                                       \
+    return g.il ? pairs_t<LL, true, MODE>(g, b, nblk, n_dk, n_bins, tw, s)       \
+                : pairs_t<LL, false, MODE>(g, b, nblk, n_dk, n_bins, tw, s);
+  switch (g.nz) {
+    FSEST_PAIRS_CASE(4)
+    FSEST_PAIRS_CASE(8)
+    FSEST_PAIRS_CASE(16)
+    FSEST_PAIRS_CASE(32)
+    FSEST_PAIRS_CASE(64)
+    FSEST_PAIRS_CASE(128)
+    FSEST_PAIRS_CASE(256)
+    FSEST_PAIRS_CASE(512)
+    FSEST_PAIRS_CASE(1024)
+    default: return hipErrorInvalidValue;
+  }
+#undef FSEST_PAIRS_CASE
+}
+
+static int pair_blocks(const Geom& g, const Tune& tu) {
+  // interlaced rows hold N complex values, packed rows N/2
+  int64_t npairs = (int64_t)g.n * g.n / 2 + 2;
+  int ppb;
+  switch (g.nz) {
+    case 4: ppb = PairShape<4>::PPB; break;
+    case 8: ppb = PairShape<8>::PPB; break;
+    case 16: ppb = PairShape<16>::PPB; break;
+    case 32: ppb = PairShape<32>::PPB; break;
+    case 64: ppb = PairShape<64>::PPB; break;
+    case 128: ppb = PairShape<128>::PPB; break;
+    case 256: ppb = PairShape<256>::PPB; break;
+    case 512: ppb = PairShape<512>::PPB; break;
+    default: ppb = PairShape<1024>::PPB; break;
+  }
+  int64_t groups = (npairs + ppb - 1) / ppb;
+  int64_t nblk = tu.bin_blocks;
+  if (nblk > groups) nblk = groups;
+  if (nblk > kMaxBinBlocks) nblk = kMaxBinBlocks;
+  if (nblk < 1) nblk = 1;
+  return (int)nblk;
+}
+
+hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do_fft, int n_dk,
+                        int n_bins, int subtract_shot, double* k, double* p, int64_t* nmodes,
+                        hipStream_t s) {
+  const int nblk = pair_blocks(g, tu);
+  hipError_t e = do_fft ? pairs_dispatch<0>(g, b, nblk, n_dk, n_bins, s)
+                        : pairs_dispatch<1>(g, b, nblk, n_dk, n_bins, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_power_finalize, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s,
+                     b.partials, nblk, n_bins, b.mode_n, b.mode_k, b.np, g.box, subtract_shot, k, p,
+                     nmodes);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& tu,
+                                   const double* dldp, int n_dk, int n_bins, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_coef, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s, dldp,
+                     n_bins, b.mode_n, b.np, g.box, b.coef);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nblk = pair_blocks(g, tu);
+  return pairs_dispatch<2>(g, b, nblk, n_dk, n_bins, s);
+}
+
+// ------------------------------------------------------------------ mode table
+__global__ __launch_bounds__(256) void k_mode_table(Geom g, int n_dk, int n_bins,
+                                                    uint64_t* __restrict__ pn, double* __restrict__ pk) {
+  __shared__ unsigned long long hn[kMaxBins];
+  __shared__ double hk[kMaxBins];
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) { hn[i] = 0ull; hk[i] = 0.0; }
+  __syncthreads();
+  const int n = g.n, nm = n / 2 + 1;
+  constexpr int CH = 16;
+  const int chunks = (nm + CH - 1) / CH;
+  const int64_t items = (int64_t)n * n * chunks;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = it / chunks;
+    const int ch = (int)(it % chunks);
+    const int mx = signed_freq((int)(row / n), n), my = signed_freq((int)(row % n), n);
+    const int r2 = mx * mx + my * my;
+    int cur_b = -1;
+    unsigned long long cn = 0;
+    double ck = 0.0;
+    for (int mz = ch * CH; mz < min(ch * CH + CH, nm); ++mz) {
+      const int m2 = r2 + mz * mz;
+      if (m2 == 0) continue;
+      const int b = shell_of(m2, n_dk);
+      if (b < 1 || b > n_bins) continue;
+      const int w = (mz == 0 || mz == n / 2) ? 1 : 2;
+      if (b != cur_b) {
+        if (cur_b > 0) { atomicAdd(&hn[cur_b - 1], cn); atomicAdd(&hk[cur_b - 1], ck); }
+        cur_b = b; cn = 0; ck = 0.0;
+      }
+      cn += w;
+      ck += w * sqrt((double)m2);
+    }
+    if (cur_b > 0) { atomicAdd(&hn[cur_b - 1], cn); atomicAdd(&hk[cur_b - 1], ck); }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) {
+    pn[(int64_t)blockIdx.x * n_bins + i] = hn[i];
+    pk[(int64_t)blockIdx.x * n_bins + i] = hk[i];
+  }
+}
+
+__global__ void k_mode_finalize(const uint64_t* pn, const double* pk, int nblk, int n_bins,
+                                int64_t* mode_n, double* mode_k) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  uint64_t c = 0;
+  double kk = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    c += pn[(int64_t)i * n_bins + b];
+    kk += pk[(int64_t)i * n_bins + b];
+  }
+  mode_n[b] = (int64_t)c;
+  mode_k[b] = kk;
+}
+
+hipError_t launch_mode_table(const Geom& g, const Buffers& b, int n_dk, int n_bins, hipStream_t s) {
+  const int nblk = 512;
+  hipLaunchKernelGGL(k_mode_table, dim3(nblk), dim3(256), 0, s, g, n_dk, n_bins,
+                     b.mode_partials_n, b.mode_partials_k);
+  hipLaunchKernelGGL(k_mode_finalize, dim3((n_bins + 127) / 128), dim3(128), 0, s,
+                     b.mode_partials_n, b.mode_partials_k, nblk, n_bins, b.mode_n, b.mode_k);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sampled delta
+// delta(m) = C(m) / (N_P W(m)) at signed modes, from the stored full spectrum.
+__global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock,
+                               const int32_t* __restrict__ modes, int64_t nm,
+                               const int64_t* __restrict__ np, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nm) return;
+  const int n = g.n;
+  const int mx = modes[3 * i], my = modes[3 * i + 1], mz = modes[3 * i + 2];
+  const int x = mx & (n - 1), y = my & (n - 1);
+  const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
+  const int L = g.nz;
+  const int z = mz & (L - 1), zm = (L - z) & (L - 1);
+  const float2* base = data + (int64_t)mock * n * n * L;
+  const float2 za = base[((int64_t)x * n + y) * L + z];
+  const float2 zb = base[((int64_t)xm * n + ym) * L + zm];
+  const double f1r = 0.5 * ((double)za.x + zb.x), f1i = 0.5 * ((double)za.y - zb.y);
+  const double f2r = 0.5 * ((double)za.y + zb.y), f2i = 0.5 * ((double)zb.x - za.x);
+  double cr, ci;
+  if (g.il) {
+    double s, c;
+    sincospi((double)(mx + my + mz) / n, &s, &c);
+    cr = 0.5 * (f1r + c * f2r - s * f2i);
+    ci = 0.5 * (f1i + c * f2i + s * f2r);
+  } else {
+    double s, c;
+    sincospi(-2.0 * mz / n, &s, &c);
+    cr = f1r + c * f2r - s * f2i;
+    ci = f1i + c * f2i + s * f2r;
+  }
+  double w = 1.0;
+  const int mm[3] = {mx, my, mz};
+  for (int a = 0; a < 3; ++a) {
+    if (mm[a] != 0) {
+      const double xx = (double)mm[a] / n;
+      const double sc = sinpi(xx) / (M_PI * xx);
+      for (int k = 0; k < g.order; ++k) w *= sc;
+    }
+  }
+  const double d = (double)np[mock] * w;
+  out[2 * i] = cr / d;
+  out[2 * i + 1] = ci / d;
+}
+
+hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,
+                               int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_delta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.grid, g,
+                     mock, modes, n, b.np, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ bispectrum
+// Y(m) = S_b1(m) d(m) + i S_b2(m) d(m) on the full N^3 grid, d = delta (or 1
+// for the counts), so that one inverse complex FFT gives I_b1 + i I_b2 (eq. IntI).
+__global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ data, Geom g, int mock,
+                                                    int n_dk, int b1, int b2, int counts_only,
+                                                    const float2* __restrict__ phase,
+                                                    const float* __restrict__ win1,
+                                                    const int64_t* __restrict__ np,
+                                                    float2* __restrict__ out) {
+  const int n = g.n;
+  const int64_t n3 = (int64_t)n * n * n;
+  const int L = g.nz;
+  const float2* base = data + (int64_t)mock * n * n * L;
+  const float inv_np = 1.0f / (float)np[mock];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i / ((int64_t)n * n)), y = (int)((i / n) % n), z = (int)(i % n);
+    const int mx = signed_freq(x, n), my = signed_freq(y, n), mz = signed_freq(z, n);
+    const int m2 = mx * mx + my * my + mz * mz;
+    const int b = m2 ? shell_of(m2, n_dk) : 0;
+    float2 res = make_float2(0.f, 0.f);
+    if (b != 0 && (b == b1 || b == b2)) {
+      float2 d;
+      if (counts_only) {
+        d = make_float2(1.f, 0.f);
+      } else {
+        const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
+        const int zz = mz & (L - 1), zm = (L - zz) & (L - 1);
+        const float2 za = base[((int64_t)x * n + y) * L + zz];
+        const float2 zb = base[((int64_t)xm * n + ym) * L + zm];
+        float2 c;
+        if (g.il) c = combined_mode<true>(za, zb, mx, my, mz, phase, n);
+        else c = combined_mode<false>(za, zb, mx, my, mz, phase, n);
+        const float w = win1[x] * win1[y] * win1[z];
+        d = cscale(c, inv_np / w);
+      }
+      if (b == b1) res = cadd(res, d);
+      if (b == b2) res = cadd(res, make_float2(-d.y, d.x));
+    }
+    out[i] = res;
+  }
+}
+
+hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
+                             bool counts_only, float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_shell_pair, dim3(8192), dim3(256), 0, s, b.grid, g, mock, n_dk, b1, b2,
+                     counts_only ? 1 : 0, b.phase, b.win1, b.np, out);
+  return hipGetLastError();
+}
+
+// sum_x F_b1 F_b2 F_b3 for blocks of 256 triangles over x-ranges; fields b
+// live in pair buffers (b-1)/2 as the real (b odd) or imaginary part.
+constexpr int kTriXC = 64;
+
+__global__ __launch_bounds__(256) void k_triple(int64_t npts, const float2* __restrict__ ip,
+                                                const float2* __restrict__ jp, int n_bins,
+                                                const int32_t* __restrict__ tri, int64_t n_tri,
+                                                double* __restrict__ part, int n_xr) {
+  extern __shared__ float sh[];
+  float* fi = sh;
+  float* fj = sh + n_bins * (kTriXC + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b1 = 0, b2 = 0, b3 = 0;
+  const bool valid = t < n_tri;
+  if (valid) {
+    b1 = tri[3 * t] - 1;
+    b2 = tri[3 * t + 1] - 1;
+    b3 = tri[3 * t + 2] - 1;
+  }
+  const int npairs = (n_bins + 1) / 2;
+  const int64_t per = (npts + n_xr - 1) / n_xr;
+  const int64_t x0 = (int64_t)blockIdx.y * per;
+  const int64_t x1 = min(npts, x0 + per);
+  double ai = 0.0, aj = 0.0;
+  for (int64_t c0 = x0; c0 < x1; c0 += kTriXC) {
+    const int cl = (int)min((int64_t)kTriXC, x1 - c0);
+    for (int idx = threadIdx.x; idx < npairs * kTriXC; idx += blockDim.x) {
+      const int pr = idx / kTriXC, xo = idx % kTriXC;
+      float2 vi = make_float2(0.f, 0.f), vj = make_float2(0.f, 0.f);
+      if (xo < cl) {
+        vi = ip[(int64_t)pr * npts + c0 + xo];
+        vj = jp[(int64_t)pr * npts + c0 + xo];
+      }
+      fi[(2 * pr) * (kTriXC + 1) + xo] = vi.x;
+      fj[(2 * pr) * (kTriXC + 1) + xo] = vj.x;
+      if (2 * pr + 1 < n_bins) {
+        fi[(2 * pr + 1) * (kTriXC + 1) + xo] = vi.y;
+        fj[(2 * pr + 1) * (kTriXC + 1) + xo] = vj.y;
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      const float* i1 = fi + b1 * (kTriXC + 1);
+      const float* i2 = fi + b2 * (kTriXC + 1);
+      const float* i3 = fi + b3 * (kTriXC + 1);
+      const float* j1 = fj + b1 * (kTriXC + 1);
+      const float* j2 = fj + b2 * (kTriXC + 1);
+      const float* j3 = fj + b3 * (kTriXC + 1);
+      float si = 0.f, sj = 0.f;
+      for (int xo = 0; xo < cl; ++xo) {
+        si += i1[xo] * i2[xo] * i3[xo];
+        sj += j1[xo] * j2[xo] * j3[xo];
+      }
+      ai += si;
+      aj += sj;
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    part[((int64_t)blockIdx.y * n_tri + t) * 2] = ai;
+    part[((int64_t)blockIdx.y * n_tri + t) * 2 + 1] = aj;
+  }
+}
+
+hipError_t launch_triple_sums(int64_t npts, const float2* ipairs, const float2* jpairs, int n_bins,
+                              const int32_t* tri, int64_t n_tri, double* part, int n_xr,
+                              hipStream_t s) {
+  const unsigned tb = (unsigned)((n_tri + 255) / 256);
+  const size_t lds = sizeof(float) * 2 * (size_t)n_bins * (kTriXC + 1);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k_triple, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_triple, dim3(tb, n_xr), dim3(256), lds, s, npts, ipairs, jpairs, n_bins, tri,
+                     n_tri, part, n_xr);
+  return hipGetLastError();
+}
+
+__global__ void k_bispec_finalize(const double* __restrict__ part, int n_xr, int64_t n_tri, double vol,
+                                  double n3, double* bk, double* ntri) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  double si = 0.0, sj = 0.0;
+  for (int i = 0; i < n_xr; ++i) {
+    si += part[((int64_t)i * n_tri + t) * 2];
+    sj += part[((int64_t)i * n_tri + t) * 2 + 1];
+  }
+  bk[t] = (sj > 0.5) ? vol * vol * si / sj : __builtin_nan("");
+  ntri[t] = sj / n3;
+}
+
+hipError_t launch_bispec_finalize(const double* part, int n_xr, int64_t n_tri, double vol, double n3,
+                                  double* bk, double* ntri, hipStream_t s) {
+  hipLaunchKernelGGL(k_bispec_finalize, dim3((unsigned)((n_tri + 255) / 256)), dim3(256), 0, s, part,
+                     n_xr, n_tri, vol, n3, bk, ntri);
+  return hipGetLastError();
+}
+
+}  // namespace fsest

@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every symbol declared in include/fsest.h, and
+reject invalid arguments on the host before touching the device.
+"""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsest.h")
+
+fsest = pytest.importorskip("paper_1512_07295_amd", reason="libfsest.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(estimator_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(fsest.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", fsest.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = set(re.findall(r"\s[TW]\s+(\S+)$", out, flags=re.M))
+    for name in _declared():
+        assert name in syms, name
+        assert getattr(fsest._lib, name) is not None
+
+
+def _cfg(**kw):
+    base = dict(n_grid=32, box=1000.0, order=4, interlace=1, batch=1, max_particles=1000)
+    base.update(kw)
+    return fsest.make_config(**base)
+
+
+def test_workspace_bytes_valid_and_monotone():
+    a = fsest.estimator_workspace_bytes(_cfg(n_grid=16))
+    b = fsest.estimator_workspace_bytes(_cfg(n_grid=32))
+    c = fsest.estimator_workspace_bytes(_cfg(n_grid=32, interlace=0))
+    d = fsest.estimator_workspace_bytes(_cfg(n_grid=32, batch=4))
+    assert 0 < a < b and c < b < d
+    big = fsest.estimator_workspace_bytes(_cfg(n_grid=1024, max_particles=512 ** 3))
+    # two float32 grids of 1024^3 dominate
+    assert big > 2 * 4 * 1024 ** 3
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(order=0), fsest.EST_EINVAL),
+    (dict(order=5), fsest.EST_EINVAL),
+    (dict(interlace=2), fsest.EST_EINVAL),
+    (dict(batch=0), fsest.EST_EINVAL),
+    (dict(box=0.0), fsest.EST_EINVAL),
+    (dict(box=-1.0), fsest.EST_EINVAL),
+    (dict(box=float("inf")), fsest.EST_EINVAL),
+    (dict(box=float("nan")), fsest.EST_EINVAL),
+    (dict(max_particles=0), fsest.EST_EINVAL),
+    (dict(max_particles=1 << 31), fsest.EST_EINVAL),
+    (dict(flags=1), fsest.EST_EINVAL),
+    (dict(n_grid=100), fsest.EST_EUNSUPPORTED),
+    (dict(n_grid=4), fsest.EST_EUNSUPPORTED),
+    (dict(n_grid=2048), fsest.EST_EUNSUPPORTED),
+    (dict(n_grid=1024, batch=300), fsest.EST_EINVAL),
+])
+def test_invalid_config_rejected_on_host(kw, status):
+    with pytest.raises(fsest.FsestError) as ei:
+        fsest.estimator_workspace_bytes(_cfg(**kw))
+    assert ei.value.status == status
+    assert fsest.estimator_last_error() != ""
+
+
+def test_create_rejects_bad_workspace_without_gpu():
+    cfg = _cfg()
+    need = fsest.estimator_workspace_bytes(cfg)
+    with pytest.raises(fsest.FsestError) as ei:
+        fsest.estimator_create(cfg, None, need)
+    assert ei.value.status == fsest.EST_EINVAL
+    with pytest.raises(fsest.FsestError) as ei:
+        fsest.estimator_create(cfg, 4096 * 1024, need - 1)
+    assert ei.value.status == fsest.EST_ENOMEM
+    with pytest.raises(fsest.FsestError) as ei:
+        fsest.estimator_create(cfg, 4096 * 1024 + 8, need)
+    assert ei.value.status == fsest.EST_EINVAL
+    assert "aligned" in fsest.estimator_last_error()
+
+
+def test_null_handle_calls_fail_cleanly():
+    fsest.estimator_destroy(None)  # always safe
+    for call in (lambda: fsest.estimator_transform(None),
+                 lambda: fsest.estimator_graph_launch(None),
+                 lambda: fsest.estimator_deposit(None, 1, 0, None, 1),
+                 lambda: fsest.estimator_power(None, 1, 1, 0, 1, 1, 1)):
+        with pytest.raises(fsest.FsestError) as ei:
+            call()
+        assert ei.value.status == fsest.EST_EINVAL
+
+
+def test_product_path_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_1512_07295_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f

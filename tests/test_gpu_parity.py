@@ -1,0 +1,240 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Same seeded inputs on both sides (the generators in ``synth``); the GPU reads
+the float32 (or float64) positions the oracle promotes to float64.
+Tolerances: mode counts bit-exact; k to 1e-12; P(k) (raw, float32 grids) to
+1e-5 relative; grids to 2e-6 of their peak; delta(m) to 1e-5 of the largest
+|delta| sampled.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import assign, spectrum
+import synth
+from gpu_common import rel_err, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+P_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _est(torch, n, box, p, il, batch=1, maxp=1 << 16):
+    from paper_1512_07295_amd.estimator import Estimator
+    return Estimator(n, box, p, il, batch, maxp)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("il", [False, True])
+def test_grid_parity(torch, n, p, il):
+    box = 500.0
+    pos = synth.uniform(3000, box, 10 + p, np.float32)
+    est = _est(torch, n, box, p, il, maxp=len(pos))
+    est.deposit(to_dev(torch, pos))
+    r1, r2 = assign.deposit(pos, box, n, p, il)
+    g1 = est.copy_grid(1).cpu().numpy()
+    assert np.max(np.abs(g1 - r1)) <= 2e-6 * max(1.0, r1.max())
+    assert abs(g1.astype(np.float64).sum() - len(pos)) < 1e-3
+    if il:
+        g2 = est.copy_grid(2).cpu().numpy()
+        assert np.max(np.abs(g2 - r2)) <= 2e-6 * max(1.0, r2.max())
+    est.close()
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("il", [False, True])
+def test_power_parity_uniform(torch, n, p, il):
+    box = 1000.0
+    pos = synth.uniform(20000, box, 100 + n + p, np.float32)
+    est = _est(torch, n, box, p, il, maxp=len(pos))
+    k, pk, nm = est.power(to_dev(torch, pos))
+    k0, p0, n0 = oracle.power(pos, box, n, p, il)
+    assert np.array_equal(nm.cpu().numpy()[0], n0)
+    assert rel_err(k.cpu().numpy()[0], k0) < 1e-12
+    assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
+@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, True), (1, False)])
+def test_power_parity_zeldovich_f32(torch, p, il):
+    box = 1000.0
+    pos = synth.zeldovich(32, box, 2, dtype=np.float32)
+    n = 64
+    est = _est(torch, n, box, p, il, maxp=len(pos))
+    k, pk, nm = est.power(to_dev(torch, pos))
+    k0, p0, n0 = oracle.power(pos, box, n, p, il)
+    assert np.array_equal(nm.cpu().numpy()[0], n0)
+    assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
+def test_power_parity_f64_positions_cic(torch):
+    """Config-1 shape: 32^3 uniform float64 particles, 32^3 grid, CIC, no interlacing."""
+    box = 1000.0
+    pos = synth.uniform(32 ** 3, box, 1, np.float64)
+    est = _est(torch, 32, box, 2, False, maxp=len(pos))
+    for sub in (False, True):
+        est.deposit(to_dev(torch, pos))
+        est.transform()
+        k, pk, nm = est.power_only(1, 16, sub)
+        k0, p0, n0 = oracle.power(pos, box, 32, 2, False, 1, 16, subtract_shot=sub)
+        assert np.array_equal(nm.cpu().numpy()[0], n0)
+        if sub:
+            # compare raw power; the subtracted constant is exact on both sides
+            assert np.allclose(pk.cpu().numpy()[0] - p0, 0, atol=P_TOL * (p0 + box ** 3 / len(pos)).max())
+        else:
+            assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
+@pytest.mark.parametrize("n_dk,n_bins", [(2, 8), (3, 5), (1, 7), (4, 4)])
+def test_power_bins_options(torch, n_dk, n_bins):
+    box = 300.0
+    pos = synth.zeldovich(16, box, 5, dtype=np.float32)
+    est = _est(torch, 32, box, 4, True, maxp=len(pos))
+    k, pk, nm = est.power(to_dev(torch, pos), n_dk=n_dk, n_bins=n_bins)
+    k0, p0, n0 = oracle.power(pos, box, 32, 4, True, n_dk, n_bins)
+    assert np.array_equal(nm.cpu().numpy()[0], n0)
+    assert rel_err(k.cpu().numpy()[0], k0) < 1e-12
+    assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    # power can be called again on the same transform
+    k2, pk2, _ = est.power_only(n_dk, n_bins)
+    assert rel_err(pk2.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
+@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, False), (1, True)])
+def test_sampled_delta(torch, p, il):
+    box, n = 200.0, 32
+    pos = synth.zeldovich(16, box, 8, dtype=np.float32)
+    est = _est(torch, n, box, p, il, maxp=len(pos))
+    est.deposit(to_dev(torch, pos))
+    est.transform()
+    rng = np.random.default_rng(3)
+    modes = np.stack([rng.integers(-n // 2 + 1, n // 2 + 1, 200), rng.integers(-n // 2 + 1, n // 2 + 1, 200),
+                      rng.integers(0, n // 2 + 1, 200)], axis=1)
+    modes[:4] = [[n // 2, 0, 0], [0, n // 2, n // 2], [n // 2, n // 2, n // 2], [1, -1, 0]]
+    d = est.sample_delta(modes).cpu().numpy()
+    delta, _ = spectrum.delta_half(pos, box, n, p, il)
+    ref = delta[modes[:, 0] % n, modes[:, 1] % n, modes[:, 2]]
+    assert np.max(np.abs(d - ref)) <= 1e-5 * np.max(np.abs(ref))
+    est.close()
+
+
+def test_edge_positions(torch):
+    box, n = 100.0, 16
+    h = box / n
+    special = np.array([[0.0, 0.0, 0.0], [box, box, box], [-box / 2, 1.5 * box, 3 * box],
+                        [h, 2 * h, 3 * h], [0.5 * h, 1.5 * h, 2.5 * h], [box - 1e-5, 1e-7, box / 2],
+                        [-1e-6, -h, 7.0 * h]], dtype=np.float32)
+    rng = np.random.default_rng(1)
+    pos = np.concatenate([special, rng.uniform(-box, 2 * box, (500, 3)).astype(np.float32)])
+    for p in (1, 2, 3, 4):
+        est = _est(torch, n, box, p, True, maxp=len(pos))
+        est.deposit(to_dev(torch, pos))
+        r1, r2 = assign.deposit(pos, box, n, p, True)
+        assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+        assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+        k, pk, nm = est.power(to_dev(torch, pos))
+        assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, p, True)[1]) < P_TOL
+        est.close()
+
+
+def test_single_particle_and_nonfinite(torch):
+    box, n = 50.0, 8
+    one = np.array([[3.3, 47.1, 0.2]], dtype=np.float32)
+    est = _est(torch, n, box, 4, True, maxp=16)
+    k, pk, nm = est.power(to_dev(torch, one))
+    assert rel_err(pk.cpu().numpy()[0], oracle.power(one, box, n, 4, True)[1]) < P_TOL
+    bad = np.array([[np.nan, 1.0, 2.0], [np.inf, -np.inf, 3.0], [1.0, 2.0, 3.0]], dtype=np.float32)
+    est.deposit(to_dev(torch, bad))
+    g = est.copy_grid(1).cpu().numpy()
+    assert np.isfinite(g).all() and abs(g.sum() - 3.0) < 1e-5
+    est.close()
+
+
+def test_batched_sets_match_single(torch):
+    box, n = 400.0, 32
+    parts = [synth.uniform(5000, box, 40, np.float32), np.zeros((0, 3), np.float32),
+             synth.uniform(777, box, 42, np.float32), synth.zeldovich(12, box, 43, dtype=np.float32),
+             synth.uniform(1, box, 44, np.float32)]
+    counts = [len(q) for q in parts]
+    pos = np.concatenate(parts)
+    offs = np.zeros(len(counts) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(counts)
+    est = _est(torch, n, box, 4, True, batch=len(counts), maxp=len(pos))
+    k, pk, nm = est.power(to_dev(torch, pos), offsets=to_dev(torch, offs))
+    pk = pk.cpu().numpy()
+    for i, part in enumerate(parts):
+        if len(part) == 0:
+            assert np.all(np.isnan(pk[i]))
+            continue
+        _, p0, n0 = oracle.power(part, box, n, 4, True)
+        assert np.array_equal(nm.cpu().numpy()[i], n0)
+        assert rel_err(pk[i], p0) < P_TOL
+    est.close()
+
+
+def test_graph_replay_matches_eager(torch):
+    box, n = 400.0, 32
+    pos, offs = synth.mocks(4, box, 7, n_min=2000, n_max=20000)
+    est = _est(torch, n, box, 4, True, batch=4, maxp=len(pos))
+    dpos, doffs = to_dev(torch, pos), to_dev(torch, offs)
+    _, eager, _ = est.power(dpos, offsets=doffs)
+    eager = eager.cpu().numpy()
+    k, pk, nm = est.capture(dpos, offsets=doffs)
+    for rep in range(3):
+        est.replay()
+        torch.cuda.synchronize()
+        got = pk.cpu().numpy()
+        assert rel_err(got, eager) < 1e-6, rep
+        # unrelated eager work between replays
+        est.power(dpos, offsets=doffs)
+        torch.cuda.synchronize()
+    for i in range(4):
+        part = pos[offs[i]:offs[i + 1]]
+        assert rel_err(eager[i], oracle.power(part, box, n, 4, True)[1]) < P_TOL
+    est.close()
+
+
+def test_autotune_keeps_results(torch):
+    box, n = 400.0, 32
+    pos = synth.zeldovich(16, box, 3, dtype=np.float32)
+    est = _est(torch, n, box, 4, True, maxp=len(pos))
+    dpos = to_dev(torch, pos)
+    choice = est.autotune(dpos, iters=1)
+    assert 0 <= choice < 12
+    _, pk, _ = est.power(dpos)
+    assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
+    est.close()
+
+
+def test_call_order_errors(torch):
+    import paper_1512_07295_amd as F
+    est = _est(torch, 16, 100.0, 4, True, maxp=10)
+    with pytest.raises(F.FsestError) as ei:
+        est.transform()
+    assert ei.value.status == F.EST_ESTATE
+    with pytest.raises(F.FsestError) as ei:
+        est.power_only()
+    assert ei.value.status == F.EST_ESTATE
+    pos = to_dev(torch, synth.uniform(10, 100.0, 1, np.float32))
+    with pytest.raises(F.FsestError) as ei:
+        F.estimator_deposit(est.h, pos, F.EST_F32, None, 11)
+    assert ei.value.status == F.EST_EINVAL
+    est.deposit(pos)
+    est.transform()
+    with pytest.raises(F.FsestError) as ei:
+        est.power_only(1, 9)
+    assert ei.value.status == F.EST_EINVAL
+    with pytest.raises(F.FsestError):
+        est.transform()
+    est.close()
