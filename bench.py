@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Throughput of the interlaced PCS P(k) estimator on one MI355X.
+
+Headline workload: 512^3 Zel'dovich-displaced particles (L = 2000 Mpc/h,
+float32) -> PCS deposit on a 1024^3 grid and on the grid shifted by H/2 ->
+3D FFT -> interlace + deconvolve -> P(k) in dk = k_f shells to Nyquist
+(512 bins).  A step is one deposit -> transform -> power over the resident
+particles.  Beside it (same JSON line): a batch of 64 uneven mocks on 128^3
+grids replayed as one HIP graph, and forward + backward of a P(k) loss for
+128^3 particles on a 256^3 grid.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(label, n_particles, n, nz, n_grids, nkeys):
+    """Bytes a kernel group must move per launch (float32 positions)."""
+    cells = n * n * nz
+    return {
+        # positions read twice (count, scatter), rank written and read,
+        # sorted positions written, bucket counters filled/counted/scanned/read
+        "bucket_sort": 44 * n_particles + 16 * nkeys,
+        # sorted positions read once, every grid written once
+        "deposit": 12 * n_particles + 4 * n_grids * n * n * n,
+        # complex grid read and written once per pass
+        "fft_x": 16 * cells,
+        "fft_y": 16 * cells,
+        # complex grid read once (last-axis FFT, interlace, deconvolve, bin)
+        "power_fused_z": 8 * cells,
+    }.get(label)
+
+
+def headline(args, torch, F, est_mod, synth):
+    n_side, box, n = 512, 2000.0, 1024
+    t0 = time.time()
+    pos_h = synth.zeldovich(n_side, box, 3, dtype=np.float32)
+    log("generated %d Zel'dovich particles in %.1f s" % (len(pos_h), time.time() - t0))
+    pos = torch.as_tensor(pos_h, device="cuda")
+    del pos_h
+    npart = pos.shape[0]
+    est = est_mod.Estimator(n, box, 4, True, 1, npart)
+    n_bins = n // 2
+    k = torch.empty((1, n_bins), dtype=torch.float64, device="cuda")
+    pk = torch.empty_like(k)
+    nm = torch.empty((1, n_bins), dtype=torch.int64, device="cuda")
+
+    def step():
+        F.estimator_deposit(est.h, pos, F.EST_F32, None, npart)
+        F.estimator_transform(est.h)
+        F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+    F.estimator_profile(est.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F.estimator_profile(est.h, 0)
+    prof = F.profile_table(est.h)
+    log("timed %d steps: %.3f ms/step" % (args.steps, 1e3 * dt / args.steps))
+    for name, (ms, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        log("  %-16s %9.3f ms/launch  (%d launches)" % (name, ms / cnt, cnt))
+    # dominant kernel group and its roofline
+    nkeys = (n // 4) ** 3 + 1
+    dom = max((kv for kv in prof.items() if algorithmic_bytes(kv[0], npart, n, n, 2, nkeys)),
+              key=lambda kv: kv[1][0])
+    name, (ms, cnt) = dom
+    per_launch_ms = ms / cnt
+    bytes_per = algorithmic_bytes(name, npart, n, n, 2, nkeys)
+    achieved = bytes_per / (per_launch_ms * 1e-3) / 1e9
+    stages = {kname: round(v[0] / v[1], 4) for kname, v in prof.items()}
+    roof_all = {}
+    for kname, (kms, kcnt) in prof.items():
+        b = algorithmic_bytes(kname, npart, n, n, 2, nkeys)
+        if b:
+            roof_all[kname] = round(b / (kms / kcnt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    result = {
+        "value": npart * args.steps / dt / 1e6,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "npart": npart,
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": bytes_per,
+                     "ms_per_launch": round(per_launch_ms, 4)},
+        "stage_ms": stages,
+        "stage_hbm_frac": roof_all,
+        "p_first_bins": [float(x) for x in pk[0, :4].cpu().numpy()],
+    }
+    est.close()
+    del pos
+    torch.cuda.empty_cache()
+    return result
+
+
+def batched(args, torch, F, est_mod, synth):
+    box, n, n_mocks = 500.0, 128, 64
+    t0 = time.time()
+    pos_h, offs_h = synth.mocks(n_mocks, box, 100)
+    log("generated %d mocks (%d particles) in %.1f s" % (n_mocks, len(pos_h), time.time() - t0))
+    pos = torch.as_tensor(pos_h, device="cuda")
+    offs = torch.as_tensor(offs_h, device="cuda")
+    npart = len(pos_h)
+    est = est_mod.Estimator(n, box, 4, True, n_mocks, npart)
+    choice = est.autotune(pos, offsets=offs, iters=2)
+    log("autotuner picked candidate %d" % choice)
+    est.capture(pos, offsets=offs)
+    for _ in range(args.warmup):
+        est.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        est.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("batched: %.3f ms per graph replay" % (1e3 * dt / args.steps))
+    est.close()
+    return {"value": npart * args.steps / dt / 1e6, "unit": "Mparticles/s",
+            "ms_per_step": 1e3 * dt / args.steps, "autotune_choice": choice,
+            "config": {"workload": "64 mocks, Poisson counts around log-uniform means in [1e5, 4e6] "
+                                   "(even uniform, odd Zel'dovich), L=500, 128^3 grids, PCS + "
+                                   "interlacing, one HIP graph replay per step",
+                       "n_particles": npart}}
+
+
+def fwd_bwd(args, torch, F, est_mod, synth):
+    box, n, n_bins = 1000.0, 256, 128
+    pos = torch.as_tensor(synth.zeldovich(128, box, 5, dtype=np.float32), device="cuda")
+    tgt = torch.as_tensor(synth.zeldovich(128, box, 6, dtype=np.float32), device="cuda")
+    npart = pos.shape[0]
+    est = est_mod.Estimator(n, box, 4, True, 1, npart)
+    _, target, counts = est.power(tgt, n_bins=n_bins)
+    sigma2 = 2 * target ** 2 / counts.double()
+
+    def step():
+        x = pos.detach().requires_grad_(True)
+        p = est_mod.PowerSpectrumFn.apply(x, est, 1, n_bins, None)
+        loss = ((p - target) ** 2 / sigma2).sum()
+        loss.backward()
+        return x.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("fwd+bwd: %.3f ms per step" % (1e3 * dt / args.steps))
+    est.close()
+    return {"value": npart * args.steps / dt / 1e6, "unit": "Mparticles/s",
+            "ms_per_step": 1e3 * dt / args.steps,
+            "config": {"workload": "128^3 Zel'dovich particles, L=1000, 256^3 grid, PCS + interlacing, "
+                                   "chi^2 loss of 128 P(k) bins vs a second seed, forward + adjoint",
+                       "n_particles": npart}}
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample: the same kind of workload at 1/64 size."""
+    import oracle
+    import synth
+    workers = len(os.sched_getaffinity(0))
+    pos = synth.zeldovich(128, 500.0, 3, dtype=np.float32)
+    t0 = time.perf_counter()
+    oracle.power(pos, 500.0, 256, 4, True, 1, 128, workers=workers)
+    dt = time.perf_counter() - t0
+    log("cpu oracle sample: %.1f s" % dt)
+    return {"value": round(len(pos) / dt / 1e6, 4), "unit": "Mparticles/s", "cores": workers,
+            "kind": "oracle",
+            "sample": "128^3 Zel'dovich particles (L=500) on a 256^3 grid, PCS + interlacing, "
+                      "P(k) to Nyquist: 1/64 of the headline particles and cells at the same "
+                      "cell size; FP64 numpy deposit on one core, scipy FFT on %d threads; "
+                      "%.1f s" % (workers, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import paper_1512_07295_amd as F
+    from paper_1512_07295_amd import estimator as est_mod
+    import synth
+
+    head = headline(args, torch, F, est_mod, synth)
+    extra = {}
+    if not args.no_extra:
+        extra["batched"] = batched(args, torch, F, est_mod, synth)
+        extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth)
+    out = {
+        "metric": "Mparticles/s end-to-end P(k), PCS+interlace 1024^3 grid; fwd+bwd & batched vs plain",
+        "value": round(head["value"], 2),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 Zel'dovich particles (P(k) ~ k^-1.5, rms displacement 0.3 "
+                               "lattice spacing, L=2000 Mpc/h, float32) -> 1024^3 grid, PCS (p=4) "
+                               "+ interlacing, P(k) in k_f shells to Nyquist (512 bins)",
+                   "n_particles": head["npart"], "n_grid": 1024, "order": 4, "interlace": True,
+                   "parallelism": "single GPU"},
+        "roofline": head["roofline"],
+        "stage_ms": head["stage_ms"],
+        "stage_hbm_frac": head["stage_hbm_frac"],
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

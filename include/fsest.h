@@ -183,6 +183,21 @@ est_status estimator_sample_delta(est_handle h, int32_t mock,
                                   const int32_t* modes, int64_t n,
                                   double* out);
 
+/* Per-kernel-group timing (tracing).  enable = 1 clears the accumulators
+ * and from then on brackets every kernel group a call launches (bucket sort,
+ * deposit, each FFT pass, the fused P(k) pass, ...) with HIP events on the
+ * handle's stream; enable = 0 stops.  Recording is asynchronous; it is
+ * skipped inside graph capture. */
+est_status estimator_profile(est_handle h, int32_t enable);
+
+/* Synchronise the handle's stream and report label `idx` (0-based): its
+ * name (NUL-terminated, truncated to name_len), total milliseconds and
+ * number of launches since profiling was enabled.  *n_labels receives the
+ * number of labels; EINVAL if idx is out of range (after setting it). */
+est_status estimator_profile_read(est_handle h, int32_t idx, char* name,
+                                  size_t name_len, double* total_ms,
+                                  int64_t* launches, int32_t* n_labels);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* estimator_last_error(void);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfsest.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libfsest.so is not built (%s); run `python -m paper_1512_07295_amd.build`" % LIB_PATH)
+        "libfsest.so is not built (%s); run `python paper_1512_07295_amd/build.py`" % LIB_PATH)
 _lib = ctypes.CDLL(LIB_PATH)
 
 EST_OK, EST_EINVAL, EST_ENOMEM, EST_ESTATE, EST_EDEVICE, EST_EUNSUPPORTED = range(6)
@@ -34,7 +34,7 @@ EXPORTS = [
     "estimator_bispectrum_workspace_bytes", "estimator_bispectrum",
     "estimator_backward", "estimator_graph_capture", "estimator_graph_launch",
     "estimator_autotune", "estimator_copy_grid", "estimator_sample_delta",
-    "estimator_last_error",
+    "estimator_profile", "estimator_profile_read", "estimator_last_error",
 ]
 
 
@@ -77,6 +77,9 @@ _SIGS = {
     "estimator_autotune": [_P, _P, _I32, _P, _I64, _I32, _I32, _I32, ctypes.POINTER(_I32)],
     "estimator_copy_grid": [_P, _I32, _I32, _P],
     "estimator_sample_delta": [_P, _I32, _P, _I64, _P],
+    "estimator_profile": [_P, _I32],
+    "estimator_profile_read": [_P, _I32, ctypes.c_char_p, _SZ, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -181,3 +184,29 @@ def estimator_copy_grid(h, which, mock, dst):
 
 def estimator_sample_delta(h, mock, modes, n, out):
     _check(_lib.estimator_sample_delta(h, int(mock), _ptr(modes), int(n), _ptr(out)))
+
+
+def estimator_profile(h, enable):
+    _check(_lib.estimator_profile(h, int(enable)))
+
+
+def estimator_profile_read(h, idx):
+    """(name, total_ms, launches, n_labels) of profiling label ``idx``."""
+    name = ctypes.create_string_buffer(64)
+    ms = ctypes.c_double(0.0)
+    cnt = _I64(0)
+    nl = _I32(0)
+    _check(_lib.estimator_profile_read(h, int(idx), name, 64, ctypes.byref(ms), ctypes.byref(cnt),
+                                       ctypes.byref(nl)))
+    return name.value.decode(), float(ms.value), int(cnt.value), int(nl.value)
+
+
+def profile_table(h):
+    """{label: (total_ms, launches)} for every label with at least one launch."""
+    first = estimator_profile_read(h, 0)
+    out = {}
+    for i in range(first[3]):
+        name, ms, cnt, _ = estimator_profile_read(h, i)
+        if cnt:
+            out[name] = (ms, cnt)
+    return out

@@ -1,6 +1,7 @@
 """Build libfsest.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_1512_07295_amd.build  (or build() from Python).
+Usage: python paper_1512_07295_amd/build.py   (run as a script: importing the
+package itself needs the built library).
 """
 
 import os

@@ -38,6 +38,20 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
+enum ProfLabel {
+  kPSort = 0, kPDeposit, kPFftX, kPFftY, kPFftZ, kPPower, kPAdjoint, kPIfftY, kPIfftX, kPGather,
+  kPModes, kPBispec, kPNumLabels
+};
+static const char* kProfNames[kPNumLabels] = {
+    "bucket_sort", "deposit", "fft_x", "fft_y", "fft_z", "power_fused_z", "adjoint_fused_z",
+    "ifft_y", "ifft_x", "gather_grad", "mode_table", "bispectrum"};
+
+struct ProfRec {
+  double total_ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
 struct est_ctx {
   est_config cfg;
   Geom g;
@@ -50,9 +64,59 @@ struct est_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* tune_out = nullptr;
+  bool prof = false;
+  bool capturing = false;
+  ProfRec rec[kPNumLabels];
+  std::vector<hipEvent_t> pool;
 };
 
 namespace {
+
+hipEvent_t prof_event(est_ctx* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one kernel group with events when profiling.
+struct ProfScope {
+  est_ctx* h;
+  int label;
+  hipEvent_t a = nullptr;
+  ProfScope(est_ctx* hh, int l) : h(hh), label(l) {
+    if (h->prof && !h->capturing) {
+      a = prof_event(h);
+      if (a) hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(h);
+    if (!b) return;
+    hipEventRecord(b, h->stream);
+    h->rec[label].pending.emplace_back(a, b);
+  }
+};
+
+void prof_fold(est_ctx* h) {
+  for (auto& r : h->rec) {
+    for (auto& pr : r.pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        r.total_ms += ms;
+        r.launches += 1;
+      }
+      h->pool.push_back(pr.first);
+      h->pool.push_back(pr.second);
+    }
+    r.pending.clear();
+  }
+}
 
 est_status check_config(const est_config* c) {
   if (!c) return fail(EST_EINVAL, "config is NULL");
@@ -153,6 +217,7 @@ est_status check_bins(est_handle h, int32_t n_dk, int32_t n_bins) {
 
 est_status ensure_modes(est_handle h, int n_dk, int n_bins) {
   if (h->mode_dk == n_dk && h->mode_nbins == n_bins) return ok();
+  ProfScope ps(h, kPModes);
   est_status st = dev_err(launch_mode_table(h->g, h->b, n_dk, n_bins, h->stream), "mode table");
   if (st != EST_OK) return st;
   h->mode_dk = n_dk;
@@ -162,28 +227,42 @@ est_status ensure_modes(est_handle h, int n_dk, int n_bins) {
 
 est_status run_deposit(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
                        int64_t n_total) {
-  est_status st = dev_err(launch_set_counts(offsets, n_total, h->g.batch, h->b.np, h->stream), "counts");
-  if (st) return st;
-  st = dev_err(launch_sort(h->g, pos, dt, offsets, n_total, h->b, h->stream), "bucket sort");
-  if (st) return st;
+  est_status st;
+  {
+    ProfScope ps(h, kPSort);
+    st = dev_err(launch_set_counts(offsets, n_total, h->g.batch, h->b.np, h->stream), "counts");
+    if (st) return st;
+    st = dev_err(launch_sort(h->g, pos, dt, offsets, n_total, h->b, h->stream), "bucket sort");
+    if (st) return st;
+  }
+  ProfScope ps(h, kPDeposit);
   return dev_err(launch_deposit(h->g, dt, h->b, h->tu, h->stream), "deposit");
 }
 
 est_status run_xy(est_handle h, int dir) {
   est_status st;
   if (dir < 0) {
-    st = dev_err(launch_fft_axis(h->g, h->b.grid, 0, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft x");
-    if (st) return st;
+    {
+      ProfScope ps(h, kPFftX);
+      st = dev_err(launch_fft_axis(h->g, h->b.grid, 0, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft x");
+      if (st) return st;
+    }
+    ProfScope ps(h, kPFftY);
     return dev_err(launch_fft_axis(h->g, h->b.grid, 1, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft y");
   }
-  st = dev_err(launch_fft_axis(h->g, h->b.grid, 1, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft y");
-  if (st) return st;
+  {
+    ProfScope ps(h, kPIfftY);
+    st = dev_err(launch_fft_axis(h->g, h->b.grid, 1, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft y");
+    if (st) return st;
+  }
+  ProfScope ps(h, kPIfftX);
   return dev_err(launch_fft_axis(h->g, h->b.grid, 0, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft x");
 }
 
 est_status to_spectrum(est_handle h) {
   if (h->state == kSpectrum) return ok();
   if (h->state != kXY) return fail(EST_ESTATE, "needs estimator_transform first");
+  ProfScope ps(h, kPFftZ);
   est_status st = dev_err(launch_fft_axis(h->g, h->b.grid, 2, -1, h->g.batch, h->g.nz, h->b.tw_nz, h->tu, h->stream), "fft z");
   if (st) return st;
   h->state = kSpectrum;
@@ -197,6 +276,7 @@ est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_
   if (st) return st;
   st = run_xy(h, -1);
   if (st) return st;
+  ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, true, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
 }
 
@@ -243,6 +323,12 @@ est_status estimator_create(const est_config* cfg, void* workspace, size_t works
 
 est_status estimator_destroy(est_handle h) {
   if (!h) return ok();
+  for (auto& r : h->rec)
+    for (auto& pr : r.pending) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : h->pool) hipEventDestroy(e);
   if (h->exec) hipGraphExecDestroy(h->exec);
   if (h->graph) hipGraphDestroy(h->graph);
   delete h;
@@ -279,6 +365,7 @@ est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins, int32_t s
   if (h->state != kXY && h->state != kSpectrum)
     return fail(EST_ESTATE, "estimator_power needs estimator_transform first");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, h->state == kXY, n_dk, n_bins, subtract_shot, k, p,
                               nmodes, h->stream),
                  "power");
@@ -367,6 +454,7 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
       }
     }
   }
+  ProfScope ps(h, kPBispec);
   const int nx = bispec_xranges(n_tri);
   if ((st = dev_err(launch_triple_sums((int64_t)n3, ip, jp, n_bins, tri_dev, n_tri, part, nx, h->stream), "triple sums")))
     return st;
@@ -388,11 +476,17 @@ est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype, co
   h->state = kCreated;
   if ((st = run_deposit(h, pos, dtype, offsets, n_total))) return st;
   if ((st = run_xy(h, -1))) return st;
-  if ((st = dev_err(launch_adjoint_spectrum(h->g, h->b, h->tu, dldp, n_dk, n_bins, h->stream), "adjoint spectrum")))
-    return st;
+  {
+    ProfScope ps(h, kPAdjoint);
+    if ((st = dev_err(launch_adjoint_spectrum(h->g, h->b, h->tu, dldp, n_dk, n_bins, h->stream), "adjoint spectrum")))
+      return st;
+  }
   if ((st = run_xy(h, +1))) return st;
-  if ((st = dev_err(launch_gather_grad(h->g, pos, dtype, offsets, n_total, h->b, grad, h->stream), "gather")))
-    return st;
+  {
+    ProfScope ps(h, kPGather);
+    if ((st = dev_err(launch_gather_grad(h->g, pos, dtype, offsets, n_total, h->b, grad, h->stream), "gather")))
+      return st;
+  }
   h->state = kCreated;  // the grid now holds dL/drho, not a density
   return ok();
 }
@@ -417,6 +511,7 @@ est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtyp
   if ((st = dev_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return st;
   hipStream_t saved = h->stream;
   h->stream = cs;
+  h->capturing = true;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, subtract_shot, k, p, nmodes);
@@ -433,6 +528,7 @@ est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtyp
     st = dev_err(e, "begin capture");
   }
   h->stream = saved;
+  h->capturing = false;
   hipStreamDestroy(cs);
   h->state = (st == EST_OK) ? kXY : kCreated;
   return st;
@@ -518,6 +614,39 @@ est_status estimator_sample_delta(est_handle h, int32_t mock, const int32_t* mod
   if (!modes || !out || n < 1) return fail(EST_EINVAL, "modes/out missing");
   if ((st = to_spectrum(h))) return st;
   return dev_err(launch_sample_delta(h->g, h->b, mock, modes, n, out, h->stream), "sample delta");
+}
+
+est_status estimator_profile(est_handle h, int32_t enable) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (enable != 0 && enable != 1) return fail(EST_EINVAL, "enable must be 0 or 1");
+  if (enable) {
+    if ((st = dev_err(hipStreamSynchronize(h->stream), "synchronize"))) return st;
+    prof_fold(h);
+    for (auto& r : h->rec) {
+      r.total_ms = 0.0;
+      r.launches = 0;
+    }
+  }
+  h->prof = enable != 0;
+  return ok();
+}
+
+est_status estimator_profile_read(est_handle h, int32_t idx, char* name, size_t name_len,
+                                  double* total_ms, int64_t* launches, int32_t* n_labels) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (n_labels) *n_labels = kPNumLabels;
+  if (idx < 0 || idx >= kPNumLabels) return fail(EST_EINVAL, "label index out of range");
+  if ((st = dev_err(hipStreamSynchronize(h->stream), "synchronize"))) return st;
+  prof_fold(h);
+  if (name && name_len > 0) {
+    strncpy(name, kProfNames[idx], name_len - 1);
+    name[name_len - 1] = '\0';
+  }
+  if (total_ms) *total_ms = h->rec[idx].total_ms;
+  if (launches) *launches = h->rec[idx].launches;
+  return ok();
 }
 
 }  // extern "C"
