@@ -285,17 +285,22 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   }
 }
 
-// P_b = V S_b / (N_P^2 N_b) [- V/N_P], k_b = k_f K_b / N_b
-__global__ void k_power_finalize(const double* __restrict__ partials, int nblk, int n_bins,
-                                 const int64_t* __restrict__ mode_n, const double* __restrict__ mode_k,
-                                 const int64_t* __restrict__ np, double box, int subtract,
-                                 double* k, double* p, int64_t* nmodes) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// P_b = V S_b / (N_P^2 N_b) [- V/N_P], k_b = k_f K_b / N_b; one wave per
+// (bin, set) sums the per-workgroup partials in a fixed order.
+__global__ __launch_bounds__(64) void k_power_finalize(const double* __restrict__ partials, int nblk,
+                                                       int n_bins, const int64_t* __restrict__ mode_n,
+                                                       const double* __restrict__ mode_k,
+                                                       const int64_t* __restrict__ np, double box,
+                                                       int subtract, double* k, double* p,
+                                                       int64_t* nmodes) {
+  const int b = blockIdx.x;
   const int mock = blockIdx.y;
-  if (b >= n_bins) return;
   const double* src = partials + (int64_t)mock * nblk * n_bins + b;
   double s = 0.0;
-  for (int i = 0; i < nblk; ++i) s += src[(int64_t)i * n_bins];
+  for (int i = threadIdx.x; i < nblk; i += 64) s += src[(int64_t)i * n_bins];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (threadIdx.x != 0) return;
   const double vol = box * box * box;
   const double nb = (double)mode_n[b];
   const double npart = (double)np[mock];
@@ -381,7 +386,7 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
   hipError_t e = do_fft ? pairs_dispatch<0>(g, b, nblk, n_dk, n_bins, s)
                         : pairs_dispatch<1>(g, b, nblk, n_dk, n_bins, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_power_finalize, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s,
+  hipLaunchKernelGGL(k_power_finalize, dim3(n_bins, g.batch), dim3(64), 0, s,
                      b.partials, nblk, n_bins, b.mode_n, b.mode_k, b.np, g.box, subtract_shot, k, p,
                      nmodes);
   return hipGetLastError();
