@@ -63,6 +63,9 @@ def headline(args, torch, F, est_mod, synth):
         F.estimator_transform(est.h)
         F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
 
+    t0 = time.time()
+    choice = est.autotune(pos, n_bins=n_bins, iters=2)
+    log("autotuner picked launch shapes %d in %.1f s" % (choice, time.time() - t0))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -103,6 +106,7 @@ def headline(args, torch, F, est_mod, synth):
                      "ms_per_launch": round(per_launch_ms, 4)},
         "stage_ms": stages,
         "stage_hbm_frac": roof_all,
+        "launch_choice": choice,
         "p_first_bins": [float(x) for x in pk[0, :4].cpu().numpy()],
     }
     est.close()
@@ -180,16 +184,18 @@ def cpu_baseline():
     import synth
     workers = len(os.sched_getaffinity(0))
     pos = synth.zeldovich(128, 500.0, 3, dtype=np.float32)
+    reps = 3
     t0 = time.perf_counter()
-    oracle.power(pos, 500.0, 256, 4, True, 1, 128, workers=workers)
-    dt = time.perf_counter() - t0
+    for _ in range(reps):
+        oracle.power(pos, 500.0, 256, 4, True, 1, 128, workers=workers)
+    dt = (time.perf_counter() - t0) / reps
     log("cpu oracle sample: %.1f s" % dt)
     return {"value": round(len(pos) / dt / 1e6, 4), "unit": "Mparticles/s", "cores": workers,
             "kind": "oracle",
             "sample": "128^3 Zel'dovich particles (L=500) on a 256^3 grid, PCS + interlacing, "
                       "P(k) to Nyquist: 1/64 of the headline particles and cells at the same "
                       "cell size; FP64 numpy deposit on one core, scipy FFT on %d threads; "
-                      "%.1f s" % (workers, dt)}
+                      "mean of %d runs, %.1f s each" % (workers, reps, dt)}
 
 
 def main():
@@ -199,6 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -208,6 +216,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy:
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import paper_1512_07295_amd as F
     from paper_1512_07295_amd import estimator as est_mod
@@ -239,6 +255,7 @@ def main():
         "roofline": head["roofline"],
         "stage_ms": head["stage_ms"],
         "stage_hbm_frac": head["stage_hbm_frac"],
+        "launch_choice": head["launch_choice"],
     }
     out.update(extra)
     if not args.no_cpu_baseline:

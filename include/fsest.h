@@ -162,13 +162,21 @@ est_status estimator_graph_capture(est_handle h, const void* pos,
 /* Replay the captured graph on the handle's stream.  ESTATE if none. */
 est_status estimator_graph_launch(est_handle h);
 
-/* Time candidate launch shapes for this handle on the given input (which
- * is deposited, transformed and binned `iters` times per candidate) and keep
- * the fastest; returns its index in *choice.  Host-synchronising. */
+/* Pick this handle's launch shapes (strided-FFT lines per workgroup, P(k)
+ * reduction workgroups, deposit workgroup size, 32- or 64-bit fixed-point
+ * deposit, branch-free footprint loop) by timing the whole pipeline on the
+ * given input `iters` times per candidate, one parameter at a time.  Returns
+ * the chosen combination as an index in [0, 48) in *choice.  Results do not
+ * depend on the choice beyond rounding.  Host-synchronising. */
 est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype,
                               const int64_t* offsets, int64_t n_total,
                               int32_t n_dk, int32_t n_bins, int32_t iters,
                               int32_t* choice);
+
+/* Set the launch shapes directly from an index returned by
+ * estimator_autotune (e.g. one cached from an earlier run).  EINVAL outside
+ * [0, 48). */
+est_status estimator_set_launch(est_handle h, int32_t choice);
 
 /* Test hook: copy grid `which` (1 = primary, 2 = interlaced) of set `mock`
  * as float32 [N][N][N] (z fastest) to dst (device).  ESTATE unless the last

@@ -33,7 +33,7 @@ EXPORTS = [
     "estimator_deposit", "estimator_transform", "estimator_power",
     "estimator_bispectrum_workspace_bytes", "estimator_bispectrum",
     "estimator_backward", "estimator_graph_capture", "estimator_graph_launch",
-    "estimator_autotune", "estimator_copy_grid", "estimator_sample_delta",
+    "estimator_autotune", "estimator_set_launch", "estimator_copy_grid", "estimator_sample_delta",
     "estimator_profile", "estimator_profile_read", "estimator_last_error",
 ]
 
@@ -75,6 +75,7 @@ _SIGS = {
     "estimator_graph_capture": [_P, _P, _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P],
     "estimator_graph_launch": [_P],
     "estimator_autotune": [_P, _P, _I32, _P, _I64, _I32, _I32, _I32, ctypes.POINTER(_I32)],
+    "estimator_set_launch": [_P, _I32],
     "estimator_copy_grid": [_P, _I32, _I32, _P],
     "estimator_sample_delta": [_P, _I32, _P, _I64, _P],
     "estimator_profile": [_P, _I32],
@@ -176,6 +177,10 @@ def estimator_autotune(h, pos, dtype, offsets, n_total, n_dk, n_bins, iters):
     _check(_lib.estimator_autotune(h, _ptr(pos), int(dtype), _ptr(offsets), int(n_total),
                                    int(n_dk), int(n_bins), int(iters), ctypes.byref(choice)))
     return int(choice.value)
+
+
+def estimator_set_launch(h, choice):
+    _check(_lib.estimator_set_launch(h, int(choice)))
 
 
 def estimator_copy_grid(h, which, mock, dst):

@@ -167,6 +167,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
   bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
   bb.scan_tmp = (uint32_t*)take(((nkeys + 2047) / 2048 + 1) * sizeof(uint32_t));
+  bb.stats = (uint32_t*)take(64 * sizeof(uint32_t));
   bb.tw_n = (float2*)take(n * sizeof(float2));
   bb.tw_nz = (float2*)take((size_t)g.nz * sizeof(float2));
   bb.inv_w2 = (float*)take(n * sizeof(float));
@@ -543,6 +544,33 @@ est_status estimator_graph_launch(est_handle h) {
   return ok();
 }
 
+static Tune tune_from_index(const int* id) {
+  static const int vals_cols[2] = {8, 16};
+  static const int vals_bins[3] = {256, 1024, 2048};
+  static const int vals_dep[2] = {512, 1024};
+  Tune t;
+  t.cols_c = vals_cols[id[0]];
+  t.bin_blocks = vals_bins[id[1]];
+  t.dep_threads = vals_dep[id[2]];
+  t.dep_narrow = id[3];
+  t.dep_branchfree = id[4];
+  return t;
+}
+
+est_status estimator_set_launch(est_handle h, int32_t choice) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (choice < 0 || choice >= 48) return fail(EST_EINVAL, "launch choice must be in [0, 48)");
+  int id[5];
+  id[4] = choice % 2;
+  id[3] = (choice / 2) % 2;
+  id[2] = (choice / 4) % 2;
+  id[1] = (choice / 8) % 3;
+  id[0] = choice / 24;
+  h->tu = tune_from_index(id);
+  return ok();
+}
+
 est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, const int64_t* offsets,
                               int64_t n_total, int32_t n_dk, int32_t n_bins, int32_t iters, int32_t* choice) {
   est_status st = check_handle(h);
@@ -551,19 +579,9 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
   if ((st = check_bins(h, n_dk, n_bins))) return st;
   if (iters < 1 || iters > 1000) return fail(EST_EINVAL, "iters must be 1..1000");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
-  std::vector<Tune> cands;
-  const int cols[2] = {8, 16};
-  const int bins[3] = {256, 1024, 2048};
-  const int dep[2] = {256, 512};
-  for (int a : cols)
-    for (int bb : bins)
-      for (int d : dep) {
-        Tune t;
-        t.cols_c = a;
-        t.bin_blocks = bb;
-        t.dep_threads = d;
-        cands.push_back(t);
-      }
+  // coordinate descent over the launch-shape parameters: each parameter in
+  // turn takes the value with the shortest measured pipeline, the others
+  // fixed at their current best
   const size_t per = (size_t)h->g.batch * n_bins;
   double* kk = (double*)h->tune_out;
   double* pp = kk + per;
@@ -571,28 +589,43 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
   hipEvent_t e0, e1;
   if ((st = dev_err(hipEventCreate(&e0), "event"))) return st;
   if ((st = dev_err(hipEventCreate(&e1), "event"))) { hipEventDestroy(e0); return st; }
-  int best = 0;
-  float best_ms = 1e30f;
   const Tune saved = h->tu;
-  for (size_t i = 0; i < cands.size() && st == EST_OK; ++i) {
-    h->tu = cands[i];
-    st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);  // warm-up
-    if (st) break;
+  auto measure = [&](const Tune& t, float* ms) -> est_status {
+    h->tu = t;
+    est_status s2 = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
+    if (s2) return s2;
     hipEventRecord(e0, h->stream);
-    for (int it = 0; it < iters && st == EST_OK; ++it)
-      st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
+    for (int it = 0; it < iters && s2 == EST_OK; ++it)
+      s2 = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
     hipEventRecord(e1, h->stream);
-    if (st) break;
-    if ((st = dev_err(hipEventSynchronize(e1), "synchronize"))) break;
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) { best_ms = ms; best = (int)i; }
+    if (s2) return s2;
+    if ((s2 = dev_err(hipEventSynchronize(e1), "synchronize"))) return s2;
+    hipEventElapsedTime(ms, e0, e1);
+    return EST_OK;
+  };
+  int idx[5] = {1, 1, 1, 1, 0};  // start from the defaults
+  auto make = [&](const int* id) { return tune_from_index(id); };
+  const int nvals[5] = {2, 3, 2, 2, 2};
+  float best_ms = 1e30f;
+  if (st == EST_OK) st = measure(make(idx), &best_ms);
+  for (int p = 0; p < 5 && st == EST_OK; ++p) {
+    int best_v = idx[p];
+    for (int v = 0; v < nvals[p] && st == EST_OK; ++v) {
+      if (v == idx[p]) continue;
+      int trial[5];
+      for (int q = 0; q < 5; ++q) trial[q] = idx[q];
+      trial[p] = v;
+      float ms = 0.f;
+      st = measure(make(trial), &ms);
+      if (st == EST_OK && ms < best_ms) { best_ms = ms; best_v = v; }
+    }
+    idx[p] = best_v;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  h->tu = (st == EST_OK) ? cands[best] : saved;
+  h->tu = (st == EST_OK) ? make(idx) : saved;
   h->state = (st == EST_OK) ? kXY : kCreated;
-  if (st == EST_OK && choice) *choice = best;
+  if (st == EST_OK && choice) *choice = (((idx[0] * 3 + idx[1]) * 2 + idx[2]) * 2 + idx[3]) * 2 + idx[4];
   return st;
 }
 

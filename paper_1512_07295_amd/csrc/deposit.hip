@@ -9,6 +9,8 @@
 // and the grid needs no clearing.  A particle whose base cell is c reaches
 // cells c-1 .. c+3 of either grid for every p <= 4, so the buckets holding
 // cells t0-3 .. t0+T are enough.
+#include <type_traits>
+
 #include "fsest_internal.hpp"
 
 namespace fsest {
@@ -123,18 +125,23 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(uint32_t* data, size_t n, uint32_t* sums) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(uint32_t* data, size_t n, uint32_t* sums,
+                                                           uint32_t* maxcount) {
   __shared__ uint32_t sh[kScanThreads];
   const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
-  uint32_t run = 0;
+  uint32_t run = 0, mx = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     v[i] = (base + i < n) ? data[base + i] : 0u;
     uint32_t c = v[i];
+    mx = max(mx, c);
     v[i] = run;
     run += c;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxcount, mx);
   uint32_t total;
   uint32_t pre = block_exclusive_scan(run, sh, total);
 #pragma unroll
@@ -168,6 +175,7 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
   const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
   hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
   if (e != hipSuccess) return e;
+  if ((e = launch_fill_u32(b.stats, 1, 0u, s)) != hipSuccess) return e;
   const unsigned pblocks = (unsigned)((n_total + 255) / 256);
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
@@ -178,7 +186,8 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t n = nkeys + 1;
   const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp,
+                     b.stats);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, b.scan_tmp, nblk);
   hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -255,15 +264,29 @@ __device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
 }
 
 // ------------------------------------------------------------------ deposit
-// Fixed-point accumulation: LDS float atomics are ~40x slower than integer
-// ones on gfx950, so each workgroup sums its tile in unsigned 64-bit
-// integers with 32 fractional bits (kFix = 2^32 - 2^8 per unit weight).  A
-// weight product w in [0, 1] becomes trunc(w * kFix) < 2^32; a grid sums to
-// N_P < 2^31 units, so no cell can overflow, and the integer sums make the
-// deposit bitwise deterministic.
-constexpr float kFix = 4294967040.0f;
-constexpr double kInvFix = 1.0 / 4294967040.0;
+// Fixed-point accumulation.  LDS float atomics are ~20x slower than integer
+// ones on gfx950, so a workgroup sums its tile in unsigned integers: a weight
+// product w in [0, 1] adds round(w * S).  Two formats:
+//  * wide (64-bit): S = 2^32 - 2^8; a grid sums to N_P < 2^31 units, so no
+//    cell can overflow;
+//  * narrow (32-bit): S = 2^F with F chosen on the device from the largest
+//    bucket count M of this deposit.  A cell only receives particles whose
+//    base cell lies in a 5^3 block, which meets at most 8 buckets, so its sum
+//    is at most B = 8 M units plus half a unit per contribution; F is the
+//    largest value with B (2^F + 1) < 2^32.  When F < 24 (coarser than the
+//    float32 resolution of a unit weight) the wide kernel runs
+//    instead (both are launched; the one not selected returns at once).
+// Integer sums are exact, so deposits are bitwise reproducible.
+constexpr float kFixWide = 4294967040.0f;  // 2^32 - 2^8
+constexpr int kNarrowMinBits = 24;
 constexpr int kListCap = 2048;  // LDS list of particles that reach the tile
+
+__device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
+  const double bound = 8.0 * (double)(maxcount > 0 ? maxcount : 1);
+  int f = 0;
+  while (f < 31 && bound * (ldexp(1.0, f + 1) + 1.0) < 4294967295.0) ++f;
+  return f;
+}
 
 struct DepRanges {
   uint32_t start[72];
@@ -278,10 +301,20 @@ __device__ __forceinline__ bool axis_reaches(int c, int t0, int T, int n) {
   return lo < T || lo > n - 5;
 }
 
-template <int P, bool IL, typename TP>
+// ... and does it lie inside [t0, t0 + T)?
+__device__ __forceinline__ bool axis_inside(int c, int t0, int T, int n) {
+  const int lo = (c - 1 - t0) & (n - 1);
+  return T == n || lo <= T - 5;
+}
+
+// Adds one particle's footprint (both grids) to the tile.  INTERIOR: the
+// footprint is known to lie inside the tile (no masks).  Otherwise cells
+// outside the tile are skipped, either by branches or (BRANCHFREE) by adding
+// 0 to this lane's own dummy slot acc[dummy].
+template <int P, bool IL, typename TP, typename AT, bool INTERIOR, bool BRANCHFREE>
 __device__ __forceinline__ void deposit_particle(const TP* __restrict__ sorted, uint32_t j, const Geom& g,
-                                                 int t0x, int t0y, int t0z, int T,
-                                                 unsigned long long* acc) {
+                                                 int t0x, int t0y, int t0z, int T, AT* acc,
+                                                 int dummy, float scale) {
   constexpr int NG = IL ? 2 : 1;
   const int n = g.n;
   const int T3 = T * T * T;
@@ -299,49 +332,73 @@ __device__ __forceinline__ void deposit_particle(const TP* __restrict__ sorted, 
     stencil_1d<P>(uy + sh, n, cy, wy);
     stencil_1d<P>(uz + sh, n, cz, wz);
     int lx[P], ly[P], lz[P];
+    bool ix[P], iy[P], iz[P];
     unsigned mx = 0, my = 0, mz = 0;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       lx[i] = (cx[i] - t0x) & (n - 1);
       ly[i] = (cy[i] - t0y) & (n - 1);
       lz[i] = (cz[i] - t0z) & (n - 1);
-      mx |= (lx[i] < T) ? (1u << i) : 0u;
-      my |= (ly[i] < T) ? (1u << i) : 0u;
-      mz |= (lz[i] < T) ? (1u << i) : 0u;
+      ix[i] = lx[i] < T;
+      iy[i] = ly[i] < T;
+      iz[i] = lz[i] < T;
+      mx |= ix[i] ? (1u << i) : 0u;
+      my |= iy[i] ? (1u << i) : 0u;
+      mz |= iz[i] ? (1u << i) : 0u;
     }
-    if (!mx || !my || !mz) continue;
-    unsigned long long* a = acc + gi * T3;
+    if constexpr (!INTERIOR && !BRANCHFREE)
+      if (!mx || !my || !mz) continue;
+    const int base = gi * T3;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      if (!(mx & (1u << i))) continue;
+      if constexpr (!INTERIOR && !BRANCHFREE)
+        if (!(mx & (1u << i))) continue;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        if (!(my & (1u << k))) continue;
-        const float wxy = wx[i] * wy[k] * kFix;
-        const int rowi = (lx[i] * T + ly[k]) * T;
+        if constexpr (!INTERIOR && !BRANCHFREE)
+          if (!(my & (1u << k))) continue;
+        const float wxy = wx[i] * wy[k] * scale;
+        const int rowi = base + (lx[i] * T + ly[k]) * T;
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-          if (!(mz & (1u << l))) continue;
-          const unsigned q = __float2uint_rz(wxy * wz[l]);
-          atomicAdd(&a[rowi + lz[l]], (unsigned long long)q);
+          if constexpr (INTERIOR) {
+            atomicAdd(&acc[rowi + lz[l]], (AT)__float2uint_rn(wxy * wz[l]));
+          } else if constexpr (BRANCHFREE) {
+            const bool in = ix[i] && iy[k] && iz[l];
+            const unsigned q = in ? __float2uint_rn(wxy * wz[l]) : 0u;
+            atomicAdd(&acc[in ? rowi + lz[l] : dummy], (AT)q);
+          } else {
+            if (!(mz & (1u << l))) continue;
+            atomicAdd(&acc[rowi + lz[l]], (AT)__float2uint_rn(wxy * wz[l]));
+          }
         }
       }
     }
   }
 }
 
-template <int P, bool IL, typename TP>
-__global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
-                                                 const uint32_t* __restrict__ boff, float* grid,
-                                                 Geom g) {
+template <int P, bool IL, typename TP, bool WIDE, bool BRANCHFREE>
+__global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
+                                                  const uint32_t* __restrict__ boff, float* grid,
+                                                  Geom g, const uint32_t* __restrict__ stats,
+                                                  int exclusive) {
+  using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int TM = kTileMax;
   constexpr int NG = IL ? 2 : 1;
-  constexpr int MAXW = 8;  // waves per workgroup (512 threads)
-  __shared__ unsigned long long acc[NG * TM * TM * TM];
+  constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
+  __shared__ AT acc[NG * TM * TM * TM + 64];  // + one dummy slot per lane
   __shared__ DepRanges rg;
   __shared__ uint32_t list[kListCap];
-  __shared__ int wave_cnt[MAXW];
-  __shared__ int list_fill;
+  __shared__ int wave_cnt[2 * MAXW];
+  __shared__ int fill_in, fill_edge;
+
+  // fixed-point format for this deposit (uniform over the grid)
+  const int nbits = narrow_bits(stats[0]);
+  if (!WIDE && nbits < kNarrowMinBits) return;          // the wide kernel does it
+  if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
+  const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
+  const double inv_scale = 1.0 / (double)scale;
+
   const int n = g.n, T = g.tile, nb = g.nb;
   const int tpa = n / T;  // tiles per axis
   const int64_t tid_all = blockIdx.x;
@@ -354,8 +411,11 @@ __global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (nthreads + 63) >> 6;
 
-  for (int i = threadIdx.x; i < NG * T3; i += nthreads) acc[i] = 0ull;
-  if (threadIdx.x == 0) list_fill = 0;
+  for (int i = threadIdx.x; i < NG * T3 + 64; i += nthreads) acc[i] = 0;
+  if (threadIdx.x == 0) {
+    fill_in = 0;
+    fill_edge = 0;
+  }
 
   // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
   int cnt = T / kBucket + 2;
@@ -363,43 +423,55 @@ __global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
   const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - 1 + nb) % nb;
   const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - 1 + nb) % nb;
   const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - 1 + nb) % nb;
-  const int ncomb = cnt * cnt;
+  const int ncomb = cnt * cnt;  // <= 36
   const int64_t mbase = (int64_t)mock * nb * nb * nb;
-  if ((int)threadIdx.x < ncomb) {
-    const int ix = threadIdx.x / cnt, iy = threadIdx.x % cnt;
-    const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
-    const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
-    const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
-    uint32_t s0, e0, s1 = 0, e1 = 0;
-    if (z1 <= nb) {
-      s0 = boff[row + b0z];
-      e0 = boff[row + z1];
-    } else {
-      s0 = boff[row + b0z];
-      e0 = boff[row + nb];
-      s1 = boff[row];
-      e1 = boff[row + (z1 - nb)];
+  if (wave == 0) {
+    uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
+    if (lane < ncomb) {
+      const int ix = lane / cnt, iy = lane % cnt;
+      const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
+      const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
+      const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
+      if (z1 <= nb) {
+        s0 = boff[row + b0z];
+        e0 = boff[row + z1];
+      } else {
+        s0 = boff[row + b0z];
+        e0 = boff[row + nb];
+        s1 = boff[row];
+        e1 = boff[row + (z1 - nb)];
+      }
     }
-    rg.start[2 * threadIdx.x] = s0;
-    rg.pref[2 * threadIdx.x + 1] = e0 - s0;
-    rg.start[2 * threadIdx.x + 1] = s1;
-    rg.pref[2 * threadIdx.x + 2] = e1 - s1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    rg.pref[0] = 0;
-    for (int i = 1; i <= 2 * ncomb; ++i) rg.pref[i] += rg.pref[i - 1];
-    rg.count = 2 * ncomb;
+    // exclusive prefix of the per-lane lengths across the wave
+    const uint32_t la = e0 - s0, lb = e1 - s1;
+    uint32_t incl = la + lb;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    const uint32_t excl = incl - la - lb;
+    if (lane < ncomb) {
+      rg.start[2 * lane] = s0;
+      rg.start[2 * lane + 1] = s1;
+      rg.pref[2 * lane + 1] = excl + la;
+      rg.pref[2 * lane + 2] = excl + la + lb;
+    }
+    if (lane == 0) {
+      rg.pref[0] = 0;
+      rg.count = 2 * ncomb;
+    }
   }
   __syncthreads();
   const uint32_t total = rg.pref[rg.count];
   const int nr = rg.count;
 
-  // rounds of nthreads items: keep the particles that reach the tile in an
-  // LDS list; deposit the list whenever another round might not fit
+  // rounds of nthreads items: particles that reach the tile go to an LDS
+  // list (fully inside ones from the front, the others from the back); the
+  // list is deposited whenever another round might not fit
   for (uint32_t r0 = 0; r0 < total; r0 += nthreads) {
     const uint32_t item = r0 + threadIdx.x;
-    bool useful = false;
+    bool useful = false, inside = false;
     uint32_t j = 0;
     if (item < total) {
       int lo = 0, hi = nr;  // pref[lo] <= item < pref[hi]
@@ -415,31 +487,47 @@ __global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
       const int cz = base_cell(grid_coord(z, g.box, g.inv), n);
       useful = axis_reaches(cx, t0x, T, n) && axis_reaches(cy, t0y, T, n) &&
                axis_reaches(cz, t0z, T, n);
+      inside = useful && axis_inside(cx, t0x, T, n) && axis_inside(cy, t0y, T, n) &&
+               axis_inside(cz, t0z, T, n);
     }
-    const unsigned long long bal = __ballot(useful);
-    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    const bool edge = useful && !inside;
+    const unsigned long long bal_in = __ballot(inside);
+    const unsigned long long bal_ed = __ballot(edge);
+    if (lane == 0) {
+      wave_cnt[wave] = __popcll(bal_in);
+      wave_cnt[MAXW + wave] = __popcll(bal_ed);
+    }
     __syncthreads();
-    int before = 0, round_total = 0;
+    int before_in = 0, before_ed = 0, tot_in = 0, tot_ed = 0;
     for (int w = 0; w < nwaves; ++w) {
-      const int c = wave_cnt[w];
-      before += (w < wave) ? c : 0;
-      round_total += c;
+      const int ci = wave_cnt[w], ce = wave_cnt[MAXW + w];
+      before_in += (w < wave) ? ci : 0;
+      before_ed += (w < wave) ? ce : 0;
+      tot_in += ci;
+      tot_ed += ce;
     }
-    const int fill0 = list_fill;
-    if (useful) {
-      const int my = fill0 + before + __popcll(bal & ((1ull << lane) - 1ull));
-      list[my] = j;
-    }
+    const int fi0 = fill_in, fe0 = fill_edge;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (inside) list[fi0 + before_in + __popcll(bal_in & below)] = j;
+    if (edge) list[kListCap - 1 - (fe0 + before_ed + __popcll(bal_ed & below))] = j;
     __syncthreads();
-    const int fill = fill0 + round_total;
+    const int fi = fi0 + tot_in, fe = fe0 + tot_ed;
     const bool last = r0 + nthreads >= total;
-    if (fill > kListCap - nthreads || last) {
-      for (int e = threadIdx.x; e < fill; e += nthreads)
-        deposit_particle<P, IL>(sorted, list[e], g, t0x, t0y, t0z, T, acc);
+    if (fi + fe > kListCap - nthreads || last) {
+      for (int e = threadIdx.x; e < fi; e += nthreads)
+        deposit_particle<P, IL, TP, AT, true, false>(sorted, list[e], g, t0x, t0y, t0z, T, acc,
+                                                     NG * T3 + lane, scale);
+      for (int e = threadIdx.x; e < fe; e += nthreads)
+        deposit_particle<P, IL, TP, AT, false, BRANCHFREE>(sorted, list[kListCap - 1 - e], g, t0x,
+                                                           t0y, t0z, T, acc, NG * T3 + lane, scale);
       __syncthreads();
-      if (threadIdx.x == 0) list_fill = 0;
+      if (threadIdx.x == 0) {
+        fill_in = 0;
+        fill_edge = 0;
+      }
     } else if (threadIdx.x == 0) {
-      list_fill = fill;
+      fill_in = fi;
+      fill_edge = fe;
     }
     __syncthreads();
   }
@@ -448,9 +536,9 @@ __global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
   for (int i = threadIdx.x; i < T3; i += nthreads) {
     const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
     const int64_t cidx = mock * n3 + ((int64_t)(t0x + lx) * n + (t0y + ly)) * n + (t0z + lz);
-    const float v1 = (float)((double)acc[i] * kInvFix);
+    const float v1 = (float)((double)acc[i] * inv_scale);
     if constexpr (IL) {
-      const float v2 = (float)((double)acc[T3 + i] * kInvFix);
+      const float v2 = (float)((double)acc[T3 + i] * inv_scale);
       reinterpret_cast<float2*>(grid)[cidx] = make_float2(v1, v2);
     } else {
       grid[cidx] = v1;
@@ -458,35 +546,46 @@ __global__ __launch_bounds__(512) void k_deposit(const TP* __restrict__ sorted,
   }
 }
 
-template <int P, bool IL>
-static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, int threads,
-                               hipStream_t s) {
+template <int P, bool IL, typename TP, bool BF>
+static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, hipStream_t s) {
   const int tpa = g.n / g.tile;
   const unsigned blocks = (unsigned)((int64_t)g.batch * tpa * tpa * tpa);
-  if (dt == EST_F32)
-    hipLaunchKernelGGL((k_deposit<P, IL, float>), dim3(blocks), dim3(threads), 0, s,
-                       (const float*)b.sorted, b.boff, (float*)b.grid, g);
-  else
-    hipLaunchKernelGGL((k_deposit<P, IL, double>), dim3(blocks), dim3(threads), 0, s,
-                       (const double*)b.sorted, b.boff, (float*)b.grid, g);
+  if (narrow)
+    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, BF>), dim3(blocks), dim3(threads), 0, s,
+                       (const TP*)b.sorted, b.boff, (float*)b.grid, g, b.stats, 0);
+  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, BF>), dim3(blocks), dim3(threads), 0, s,
+                     (const TP*)b.sorted, b.boff, (float*)b.grid, g, b.stats, narrow ? 0 : 1);
+}
+
+template <int P, bool IL>
+static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
+                               int threads, hipStream_t s) {
+  const bool narrow = tu.dep_narrow != 0;
+  if (dt == EST_F32) {
+    if (tu.dep_branchfree) deposit_launch<P, IL, float, true>(g, b, threads, narrow, s);
+    else deposit_launch<P, IL, float, false>(g, b, threads, narrow, s);
+  } else {
+    if (tu.dep_branchfree) deposit_launch<P, IL, double, true>(g, b, threads, narrow, s);
+    else deposit_launch<P, IL, double, false>(g, b, threads, narrow, s);
+  }
 }
 
 template <int P>
-static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, int threads,
-                               hipStream_t s) {
-  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, threads, s);
-  else dispatch_deposit_t<P, false>(g, dt, b, threads, s);
+static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
+                               int threads, hipStream_t s) {
+  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, tu, threads, s);
+  else dispatch_deposit_t<P, false>(g, dt, b, tu, threads, s);
 }
 
 hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
                           hipStream_t s) {
   int threads = tu.dep_threads;
-  if (threads != 128 && threads != 256 && threads != 512) threads = 256;
+  if (threads != 256 && threads != 512 && threads != 1024) threads = 1024;
   switch (g.order) {
-    case 1: dispatch_deposit_p<1>(g, dt, b, threads, s); break;
-    case 2: dispatch_deposit_p<2>(g, dt, b, threads, s); break;
-    case 3: dispatch_deposit_p<3>(g, dt, b, threads, s); break;
-    default: dispatch_deposit_p<4>(g, dt, b, threads, s); break;
+    case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, s); break;
+    case 2: dispatch_deposit_p<2>(g, dt, b, tu, threads, s); break;
+    case 3: dispatch_deposit_p<3>(g, dt, b, tu, threads, s); break;
+    default: dispatch_deposit_p<4>(g, dt, b, tu, threads, s); break;
   }
   return hipGetLastError();
 }

@@ -11,7 +11,7 @@ import torch
 from . import (EST_F32, EST_F64, estimator_autotune, estimator_backward, estimator_bispectrum,
                estimator_bispectrum_workspace_bytes, estimator_copy_grid, estimator_create,
                estimator_deposit, estimator_destroy, estimator_graph_capture,
-               estimator_graph_launch, estimator_power, estimator_sample_delta,
+               estimator_graph_launch, estimator_power, estimator_sample_delta, estimator_set_launch,
                estimator_transform, estimator_workspace_bytes, make_config)
 
 
@@ -142,6 +142,9 @@ class Estimator:
         n_bins = n_bins or self.default_bins(n_dk)
         return estimator_autotune(self.h, pos, _dtype_code(pos), offsets, pos.shape[0], n_dk,
                                   n_bins, iters)
+
+    def set_launch(self, choice):
+        estimator_set_launch(self.h, choice)
 
     # ---- test hooks
     def copy_grid(self, which=1, mock=0):

@@ -211,7 +211,7 @@ def test_autotune_keeps_results(torch):
     est = _est(torch, n, box, 4, True, maxp=len(pos))
     dpos = to_dev(torch, pos)
     choice = est.autotune(dpos, iters=1)
-    assert 0 <= choice < 12
+    assert 0 <= choice < 48
     _, pk, _ = est.power(dpos)
     assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
     est.close()
@@ -237,4 +237,54 @@ def test_call_order_errors(torch):
     assert ei.value.status == F.EST_EINVAL
     with pytest.raises(F.FsestError):
         est.transform()
+    est.close()
+
+
+@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 7, 13, 24, 47])
+def test_every_launch_variant_matches_oracle(torch, choice):
+    """Each autotuner candidate (FFT lines per workgroup, reduction blocks,
+    deposit workgroup size, 32/64-bit fixed point, branch-free loop)."""
+    box, n = 300.0, 32
+    pos = synth.zeldovich(16, box, 11, dtype=np.float32)
+    est = _est(torch, n, box, 4, True, maxp=len(pos))
+    est.set_launch(choice)
+    est.deposit(to_dev(torch, pos))
+    r1, r2 = assign.deposit(pos, box, n, 4, True)
+    assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+    assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+    _, pk, _ = est.power(to_dev(torch, pos))
+    assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
+    est.close()
+
+
+def test_clustered_input_uses_wide_fixed_point(torch):
+    """A dense clump (thousands of particles in one bucket) exceeds the 32-bit
+    fixed-point bound and must go through the 64-bit path."""
+    box, n = 100.0, 32
+    rng = np.random.default_rng(4)
+    clump = (37.1 + 0.3 * rng.random((6000, 3))).astype(np.float32)
+    pos = np.concatenate([clump, synth.uniform(4000, box, 5, np.float32)])
+    for choice in (0, 2):
+        est = _est(torch, n, box, 4, True, maxp=len(pos))
+        est.set_launch(choice)
+        est.deposit(to_dev(torch, pos))
+        r1, r2 = assign.deposit(pos, box, n, 4, True)
+        assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+        assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+        _, pk, _ = est.power(to_dev(torch, pos))
+        assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
+        est.close()
+
+
+def test_deposit_is_bitwise_reproducible(torch):
+    box, n = 200.0, 32
+    pos = to_dev(torch, synth.uniform(50000, box, 6, np.float32))
+    est = _est(torch, n, box, 4, True, maxp=50000)
+    est.deposit(pos)
+    a = est.copy_grid(1).cpu().numpy().copy()
+    b = est.copy_grid(2).cpu().numpy().copy()
+    for _ in range(3):
+        est.deposit(pos)
+        assert np.array_equal(est.copy_grid(1).cpu().numpy(), a)
+        assert np.array_equal(est.copy_grid(2).cpu().numpy(), b)
     est.close()
