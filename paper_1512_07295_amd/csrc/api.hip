@@ -147,6 +147,8 @@ Geom make_geom(const est_config& c) {
   g.tile = c.n_grid < kTileMax ? c.n_grid : kTileMax;
   g.box = c.box;
   g.inv = (double)c.n_grid / c.box;
+  const int64_t plane = (int64_t)g.n * g.nz;
+  g.ps = plane + (plane >= 65536 ? 512 : 0);
   return g;
 }
 
@@ -162,7 +164,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   };
   const size_t nkeys = batch * (size_t)g.nb * g.nb * g.nb + 1;
   Buffers bb;
-  bb.grid = (float2*)take(batch * n * n * (size_t)g.nz * sizeof(float2));
+  bb.grid = (float2*)take(batch * n * (size_t)g.ps * sizeof(float2));
   bb.sorted = take((size_t)c.max_particles * 3 * sizeof(double));
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
   bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
@@ -443,6 +445,7 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
   Geom gf = g;
   gf.nz = g.n;
   gf.batch = 1;
+  gf.ps = (int64_t)g.n * g.n;  // the shell fields are unpadded N^3 arrays
   for (int q = 0; q < npairs; ++q) {
     const int b1 = 2 * q + 1, b2 = (2 * q + 2 <= n_bins) ? 2 * q + 2 : 0;
     for (int which = 0; which < 2; ++which) {

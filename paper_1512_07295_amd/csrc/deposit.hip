@@ -532,16 +532,15 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     __syncthreads();
   }
 
-  const int64_t n3 = (int64_t)n * n * n;
   for (int i = threadIdx.x; i < T3; i += nthreads) {
     const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-    const int64_t cidx = mock * n3 + ((int64_t)(t0x + lx) * n + (t0y + ly)) * n + (t0z + lz);
     const float v1 = (float)((double)acc[i] * inv_scale);
     if constexpr (IL) {
       const float v2 = (float)((double)acc[T3 + i] * inv_scale);
-      reinterpret_cast<float2*>(grid)[cidx] = make_float2(v1, v2);
+      reinterpret_cast<float2*>(grid)[complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] =
+          make_float2(v1, v2);
     } else {
-      grid[cidx] = v1;
+      grid[real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] = v1;
     }
   }
 }
@@ -592,14 +591,16 @@ hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const T
 
 // ------------------------------------------------------------------ test hook
 __global__ void k_copy_grid(const float* grid, Geom g, int which, int mock, float* dst) {
-  const int64_t n3 = (int64_t)g.n * g.n * g.n;
+  const int n = g.n;
+  const int64_t n3 = (int64_t)n * n * n;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n3; i += stride) {
+    const int x = (int)(i / ((int64_t)n * n)), y = (int)((i / n) % n), z = (int)(i % n);
     if (g.il)
-      dst[i] = grid[2 * (mock * n3 + i) + (which - 1)];
+      dst[i] = grid[2 * complex_index(g, mock, x, y, z) + (which - 1)];
     else
-      dst[i] = grid[mock * n3 + i];
+      dst[i] = grid[real_cell_index(g, mock, x, y, z)];
   }
 }
 
@@ -624,7 +625,6 @@ __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos,
   load_pos(pos, j, x, y, z);
   const int mock = mock_of(offsets, g.batch, j);
   const int n = g.n;
-  const int64_t n3 = (int64_t)n * n * n;
   const double u[3] = {grid_coord(x, g.box, g.inv), grid_coord(y, g.box, g.inv),
                        grid_coord(z, g.box, g.inv)};
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
@@ -643,11 +643,10 @@ __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos,
     for (int a = 0; a < P; ++a) {
 #pragma unroll
       for (int bq = 0; bq < P; ++bq) {
-        const int64_t row = mock * n3 + ((int64_t)c[0][a] * n + c[1][bq]) * n;
 #pragma unroll
         for (int cq = 0; cq < P; ++cq) {
-          const int64_t idx = row + c[2][cq];
-          const float gv = IL ? grid[2 * idx + gi] : grid[idx];
+          const float gv = IL ? grid[2 * complex_index(g, mock, c[0][a], c[1][bq], c[2][cq]) + gi]
+                              : grid[real_cell_index(g, mock, c[0][a], c[1][bq], c[2][cq])];
           gx += gv * d[0][a] * w[1][bq] * w[2][cq];
           gy += gv * w[0][a] * d[1][bq] * w[2][cq];
           gz += gv * w[0][a] * w[1][bq] * d[2][cq];

@@ -21,7 +21,8 @@ struct RowShape {
 
 template <int L, int DIR>
 __global__ __launch_bounds__(RowShape<L>::LPB * RowShape<L>::TPL) void k_fft_rows(
-    float2* __restrict__ data, int64_t nrows, const float2* __restrict__ tw) {
+    float2* __restrict__ data, int64_t nrows, int rows_per_plane, int64_t plane_stride,
+    const float2* __restrict__ tw) {
   constexpr int TPL = RowShape<L>::TPL;
   constexpr int LPB = RowShape<L>::LPB;
   constexpr int EPT = LinePlan<L>::EPT;
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(RowShape<L>::LPB * RowShape<L>::TPL) void k_fft_row
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const int64_t row = (int64_t)blockIdx.x * LPB + line;
   const bool valid = row < nrows;
-  float2* p = data + row * L;
+  float2* p = data + (row / rows_per_plane) * plane_stride + (row % rows_per_plane) * L;
   float2 v[EPT];
   static_for<0, EPT>([&](auto e) { v[e] = valid ? p[t + e * TPL] : make_float2(0.f, 0.f); });
   line_fft<L, DIR, 1>(v, t, lds + line * ROWP, tw);
@@ -55,10 +56,11 @@ __global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols(
 }
 
 template <int L, int DIR>
-static hipError_t rows_t(float2* data, int64_t nrows, const float2* tw, hipStream_t s) {
+static hipError_t rows_t(float2* data, int64_t nrows, int rpp, int64_t ps, const float2* tw,
+                         hipStream_t s) {
   const unsigned blocks = (unsigned)((nrows + RowShape<L>::LPB - 1) / RowShape<L>::LPB);
   hipLaunchKernelGGL((k_fft_rows<L, DIR>), dim3(blocks), dim3(RowShape<L>::LPB * RowShape<L>::TPL),
-                     0, s, data, nrows, tw);
+                     0, s, data, nrows, rpp, ps, tw);
   return hipGetLastError();
 }
 
@@ -87,17 +89,18 @@ static hipError_t cols_t(float2* data, int64_t elem_stride, int64_t inner, int64
 }
 
 template <int DIR>
-static hipError_t rows_dir(int L, float2* data, int64_t nrows, const float2* tw, hipStream_t s) {
+static hipError_t rows_dir(int L, float2* data, int64_t nrows, int rpp, int64_t ps,
+                           const float2* tw, hipStream_t s) {
   switch (L) {
-    case 4: return rows_t<4, DIR>(data, nrows, tw, s);
-    case 8: return rows_t<8, DIR>(data, nrows, tw, s);
-    case 16: return rows_t<16, DIR>(data, nrows, tw, s);
-    case 32: return rows_t<32, DIR>(data, nrows, tw, s);
-    case 64: return rows_t<64, DIR>(data, nrows, tw, s);
-    case 128: return rows_t<128, DIR>(data, nrows, tw, s);
-    case 256: return rows_t<256, DIR>(data, nrows, tw, s);
-    case 512: return rows_t<512, DIR>(data, nrows, tw, s);
-    case 1024: return rows_t<1024, DIR>(data, nrows, tw, s);
+    case 4: return rows_t<4, DIR>(data, nrows, rpp, ps, tw, s);
+    case 8: return rows_t<8, DIR>(data, nrows, rpp, ps, tw, s);
+    case 16: return rows_t<16, DIR>(data, nrows, rpp, ps, tw, s);
+    case 32: return rows_t<32, DIR>(data, nrows, rpp, ps, tw, s);
+    case 64: return rows_t<64, DIR>(data, nrows, rpp, ps, tw, s);
+    case 128: return rows_t<128, DIR>(data, nrows, rpp, ps, tw, s);
+    case 256: return rows_t<256, DIR>(data, nrows, rpp, ps, tw, s);
+    case 512: return rows_t<512, DIR>(data, nrows, rpp, ps, tw, s);
+    case 1024: return rows_t<1024, DIR>(data, nrows, rpp, ps, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -120,23 +123,23 @@ static hipError_t cols_dir(int L, float2* data, int64_t elem_stride, int64_t inn
 
 hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch, int nz_len,
                            const float2* tw_axis, const Tune& tu, hipStream_t s) {
-  const int64_t n = g.n, nz = nz_len;
+  const int64_t n = g.n, nz = nz_len, ps = g.ps;
   if (axis == 2) {
     const int64_t nrows = (int64_t)batch * n * n;
-    return dir < 0 ? rows_dir<-1>((int)nz, data, nrows, tw_axis, s)
-                   : rows_dir<+1>((int)nz, data, nrows, tw_axis, s);
+    return dir < 0 ? rows_dir<-1>((int)nz, data, nrows, (int)n, ps, tw_axis, s)
+                   : rows_dir<+1>((int)nz, data, nrows, (int)n, ps, tw_axis, s);
   }
   int64_t elem_stride, inner, outer, outer_stride;
   if (axis == 0) {
-    elem_stride = n * nz;
+    elem_stride = ps;
     inner = n * nz;
     outer = batch;
-    outer_stride = n * n * nz;
+    outer_stride = n * ps;
   } else {
     elem_stride = nz;
     inner = nz;
     outer = (int64_t)batch * n;
-    outer_stride = n * nz;
+    outer_stride = ps;
   }
   return dir < 0 ? cols_dir<-1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s)
                  : cols_dir<+1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s);

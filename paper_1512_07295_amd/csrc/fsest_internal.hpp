@@ -25,7 +25,20 @@ struct Geom {
   int tile;       // deposit tile edge
   double box;     // L
   double inv;     // fl64(N / L)
+  int64_t ps;     // complex elements between consecutive x planes: N*nz plus
+                  // a pad that breaks the power-of-two stride of the x pass
 };
+
+// float index of real-grid cell (x, y, z) of set `mock` (plane stride ps
+// complex = 2 ps floats; without interlacing the N^3 reals are packed two per
+// complex element along z, so a row of N floats is nz = N/2 complex)
+__device__ __forceinline__ int64_t real_cell_index(const Geom& g, int mock, int x, int y, int z) {
+  return 2 * (((int64_t)mock * g.n + x) * g.ps) + (int64_t)y * g.n + z;
+}
+// complex element (x, y, z) of set `mock`, z < nz
+__device__ __forceinline__ int64_t complex_index(const Geom& g, int mock, int x, int y, int z) {
+  return ((int64_t)mock * g.n + x) * g.ps + (int64_t)y * g.nz + z;
+}
 
 // Work buffers carved out of the caller's workspace.
 struct Buffers {

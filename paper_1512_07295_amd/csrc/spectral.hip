@@ -138,7 +138,7 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     const int xb = (n - xa) & (n - 1), yb = (n - ya) & (n - 1);
     const bool self = (xa == xb) && (ya == yb);
     const int xr = r ? xb : xa, yr = r ? yb : ya;
-    float2* gp = data + (((int64_t)mock * n + xr) * n + yr) * L;
+    float2* gp = data + ((int64_t)mock * n + xr) * g.ps + (int64_t)yr * L;
     float2 v[EPT];
     static_for<0, EPT>([&](auto e) { v[e] = valid ? gp[t + e * TPL] : make_float2(0.f, 0.f); });
     if constexpr (MODE != 1) line_fft<L, -1, 1>(v, t, own_lds, tw);
@@ -480,9 +480,8 @@ __global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock
   const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
   const int L = g.nz;
   const int z = mz & (L - 1), zm = (L - z) & (L - 1);
-  const float2* base = data + (int64_t)mock * n * n * L;
-  const float2 za = base[((int64_t)x * n + y) * L + z];
-  const float2 zb = base[((int64_t)xm * n + ym) * L + zm];
+  const float2 za = data[complex_index(g, mock, x, y, z)];
+  const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
   const double f1r = 0.5 * ((double)za.x + zb.x), f1i = 0.5 * ((double)za.y - zb.y);
   const double f2r = 0.5 * ((double)za.y + zb.y), f2i = 0.5 * ((double)zb.x - za.x);
   double cr, ci;
@@ -530,7 +529,6 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
   const int n = g.n;
   const int64_t n3 = (int64_t)n * n * n;
   const int L = g.nz;
-  const float2* base = data + (int64_t)mock * n * n * L;
   const float inv_np = 1.0f / (float)np[mock];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -546,8 +544,8 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
       } else {
         const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
         const int zz = mz & (L - 1), zm = (L - zz) & (L - 1);
-        const float2 za = base[((int64_t)x * n + y) * L + zz];
-        const float2 zb = base[((int64_t)xm * n + ym) * L + zm];
+        const float2 za = data[complex_index(g, mock, x, y, zz)];
+        const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
         float2 c;
         if (g.il) c = combined_mode<true>(za, zb, mx, my, mz, phase, n);
         else c = combined_mode<false>(za, zb, mx, my, mz, phase, n);
