@@ -22,6 +22,8 @@ in the paper's order:
                   particle positions (not in the paper; the derivative of the
                   forward computed here).
 * ``direct``    - direct-summation density (eq. deltaDS) and the footprint DFT.
+* ``native``    - the deposit and footprint DFT as plain C loops (same
+                  arithmetic) for inputs too large for numpy.
 * ``theory``    - closed forms used as pins: aliased white-noise spectra,
                   the residual factor F_res (eqs. res, Fres, res1Di, res1Dnoi).
 
@@ -33,6 +35,6 @@ against something other than itself (closed forms, brute force on tiny
 inputs, library routines for special cases); none is "parity unpinned".
 """
 
-from . import kernels, assign, spectrum, bispectrum, adjoint, direct, theory  # noqa: F401
+from . import kernels, assign, spectrum, bispectrum, adjoint, direct, theory, native  # noqa: F401
 from .spectrum import power  # noqa: F401
 from .bispectrum import bispectrum as bispectrum_fn  # noqa: F401

@@ -29,14 +29,23 @@ from .kernels import weight
 
 
 def wrap(x, box):
-    """Periodic wrap into [0, L) in float64 (fixed operation sequence)."""
-    x = np.asarray(x, dtype=np.float64)
-    q = np.floor(x / box)
-    xw = x - q * box
-    xw = np.where(xw < 0.0, xw + box, xw)
-    xw = np.where(xw >= box, xw - box, xw)
-    ok = (xw >= 0.0) & (xw < box)
-    return np.where(ok, xw, 0.0)
+    """Periodic wrap into [0, L) in float64 (fixed operation sequence).
+
+    x - L floor(x/L), +L if negative, -L if >= L, 0 if still outside [0, L).
+    For x already in [0, L) the sequence returns x itself, so only the other
+    entries are evaluated.
+    """
+    x = np.array(x, dtype=np.float64)
+    bad = ~((x >= 0.0) & (x < box))
+    if bad.any():
+        xb = x[bad]
+        q = np.floor(xb / box)
+        xw = xb - q * box
+        xw = np.where(xw < 0.0, xw + box, xw)
+        xw = np.where(xw >= box, xw - box, xw)
+        ok = (xw >= 0.0) & (xw < box)
+        x[bad] = np.where(ok, xw, 0.0)
+    return x
 
 
 def grid_coords(pos, box, n_grid):
@@ -94,3 +103,24 @@ def deposit(pos, box, n_grid, p, interlace):
     rho1 = deposit_u(u, p, n_grid)
     rho2 = deposit_u(u + 0.5, p, n_grid) if interlace else None
     return rho1, rho2
+
+
+def cell_values(pos, box, n_grid, p, cells, shift=0.0):
+    """rho at the given integer cells (k, 3) of the grid sampled at u + shift,
+    summing the stencil weights of every particle whose stencil holds the
+    cell (the same sum as ``deposit_u`` restricted to those cells)."""
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    u = grid_coords(pos, box, n_grid) + shift
+    out = np.zeros(len(cells), dtype=np.float64)
+    base = np.floor(u).astype(np.int64)
+    for i, g in enumerate(cells):
+        # stencils reach at most 3 cells from floor(u) on either side
+        d = np.mod(base - g, n_grid)
+        near = np.all((d <= 3) | (d >= n_grid - 3), axis=1)
+        un = u[near]
+        wsum = np.ones(len(un))
+        for ax in range(3):
+            c, w = stencil(un[:, ax], p, n_grid)
+            wsum *= np.where(c == g[ax], w, 0.0).sum(axis=1)
+        out[i] = wsum.sum()
+    return out

@@ -26,24 +26,26 @@ def delta_direct(pos, box, modes, chunk=1 << 16):
     return acc / len(pos)
 
 
-def footprint_dft(pos, box, n_grid, p, modes, shift=0.0, chunk=1 << 18):
+def footprint_dft(pos, box, n_grid, p, modes, shift=0.0, chunk=1 << 21):
     """DFT of the (shifted) deposit at integer modes, without a grid.
 
-    ``shift`` = 0 for the primary grid and 0.5 for the interlaced one.
+    ``shift`` = 0 for the primary grid and 0.5 for the interlaced one.  The
+    phase exp(-2 pi i m c / N) of an integer cell c is looked up in a table
+    of its N values.
     """
     modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
     out = np.zeros(len(modes), dtype=np.complex128)
     pos = np.asarray(pos)
+    c_all = np.arange(n_grid)
+    tables = [[np.exp(-2j * np.pi * ((m[ax] * c_all) % n_grid) / n_grid) for ax in range(3)]
+              for m in modes]
     for s in range(0, len(pos), chunk):
         u = grid_coords(pos[s:s + chunk], box, n_grid) + shift
-        per_axis = []
-        for ax in range(3):
-            cells, w = stencil(u[:, ax], p, n_grid)
-            per_axis.append((cells, w))
-        for i, m in enumerate(modes):
+        per_axis = [stencil(u[:, ax], p, n_grid) for ax in range(3)]
+        for i in range(len(modes)):
             f = np.ones(len(u), dtype=np.complex128)
             for ax in range(3):
                 cells, w = per_axis[ax]
-                f *= (w * np.exp(-2j * np.pi * m[ax] * cells / n_grid)).sum(axis=1)
+                f *= (w * tables[i][ax][cells]).sum(axis=1)
             out[i] += f.sum()
     return out

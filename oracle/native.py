@@ -1,0 +1,126 @@
+"""ctypes access to the plain-C loops of the oracle (oracle/csrc/oracle_loops.c).
+
+Test infrastructure only (see ``oracle/__init__.py``).  Same arithmetic as
+``assign.deposit``, ``assign.cell_values``, ``direct.footprint_dft`` and
+``spectrum.mode_table`` for inputs too large for the numpy forms; pinned
+against them by the CPU tests.  The library is built with
+gcc on first use (or by ``__graft_entry__.build()``).
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from .assign import grid_coords
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "csrc", "oracle_loops.c")
+LIB = os.path.join(_HERE, "_oracle_loops.so")
+_lib = None
+
+
+def build():
+    tmp = LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-shared", "-fPIC", "-o",
+                    tmp, SRC, "-lm"], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        lib = ctypes.CDLL(LIB)
+        d, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.oracle_deposit.argtypes = [d, i64, i64, i32, d]
+        lib.oracle_deposit.restype = None
+        lib.oracle_footprint_dft.argtypes = [d, i64, i64, i32, d, i64, d, d]
+        lib.oracle_footprint_dft.restype = None
+        lib.oracle_cell_values.argtypes = [d, i64, i64, i32, d, i64, d]
+        lib.oracle_cell_values.restype = None
+        lib.oracle_mode_table.argtypes = [i64, i64, i64, d, d]
+        lib.oracle_mode_table.restype = None
+        _lib = lib
+    return _lib
+
+
+def _u(pos, box, n, shift):
+    return np.ascontiguousarray(grid_coords(np.asarray(pos), box, n) + shift, dtype=np.float64)
+
+
+def deposit(pos, box, n, p, shift=0.0):
+    """Grid (N, N, N) float64 of the particles sampled at u + shift."""
+    u = _u(pos, box, n, shift)
+    rho = np.zeros(n * n * n, dtype=np.float64)
+    _load().oracle_deposit(u.ctypes.data, len(u), n, p, rho.ctypes.data)
+    return rho.reshape(n, n, n)
+
+
+def footprint_dft(pos, box, n, p, modes, shift=0.0):
+    """Same as ``direct.footprint_dft``."""
+    u = _u(pos, box, n, shift)
+    modes = np.ascontiguousarray(np.asarray(modes, dtype=np.int64).reshape(-1, 3))
+    re = np.zeros(len(modes))
+    im = np.zeros(len(modes))
+    _load().oracle_footprint_dft(u.ctypes.data, len(u), n, p, modes.ctypes.data, len(modes),
+                                 re.ctypes.data, im.ctypes.data)
+    return re + 1j * im
+
+
+def cell_values(pos, box, n, p, cells, shift=0.0):
+    """Same as ``assign.cell_values``."""
+    u = _u(pos, box, n, shift)
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros(len(cells))
+    _load().oracle_cell_values(u.ctypes.data, len(u), n, p, cells.ctypes.data, len(cells),
+                               out.ctypes.data)
+    return out
+
+
+def mode_table(n, n_dk, n_bins):
+    """Same as ``spectrum.mode_table``."""
+    counts = np.zeros(n_bins, dtype=np.int64)
+    ksum = np.zeros(n_bins)
+    _load().oracle_mode_table(n, n_dk, n_bins, counts.ctypes.data, ksum.ctypes.data)
+    return counts, ksum
+
+
+def delta_modes(pos, box, n, p, interlace_on, modes):
+    """delta(m) = C(m) / (N_P W(m)) at signed modes (the oracle's steps 1-3
+    evaluated mode by mode through the footprint DFT)."""
+    from .kernels import window_1d
+    modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
+    f1 = footprint_dft(pos, box, n, p, modes, 0.0)
+    if interlace_on:
+        f2 = footprint_dft(pos, box, n, p, modes, 0.5)
+        c = 0.5 * (f1 + np.exp(1j * np.pi * modes.sum(axis=1) / n) * f2)
+    else:
+        c = f1
+    w = np.prod(window_1d(p, modes, n), axis=1)
+    return c / (len(pos) * w)
+
+
+def delta_half(pos, box, n, p, interlace_on):
+    """Same as ``spectrum.delta_half`` with the deposit done by the C loops."""
+    from . import spectrum
+    pos = np.asarray(pos)
+    f1 = spectrum.fft_grid(deposit(pos, box, n, p, 0.0))
+    if interlace_on:
+        f2 = spectrum.fft_grid(deposit(pos, box, n, p, 0.5))
+        c = spectrum.interlace(f1, f2, n)
+    else:
+        c = f1
+    return c / (len(pos) * spectrum.window(n, p)), len(pos)
+
+
+def power(pos, box, n, p, interlace_on, n_dk=1, n_bins=None):
+    """The oracle P(k) with the deposit done by the C loops."""
+    from . import spectrum
+    if n_bins is None:
+        n_bins = spectrum.max_bins(n, n_dk)
+    delta, _ = delta_half(pos, box, n, p, interlace_on)
+    return spectrum.bin_power(delta, box, n, n_dk, n_bins)

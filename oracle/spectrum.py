@@ -103,17 +103,26 @@ def max_bins(n, n_dk):
     return n // (2 * n_dk)
 
 
-def mode_table(n, n_dk, n_bins):
-    """(N_b int64, sum_b w|m| float64) per bin, from the half spectrum."""
-    mx, my, mz = half_axes(n)
-    m2 = mx * mx + my * my + mz * mz
-    b = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
-    w = np.broadcast_to(half_weights(n), m2.shape)
-    sel = (m2 > 0) & (b >= 1) & (b <= n_bins)
-    counts = np.bincount(b[sel], weights=w[sel], minlength=n_bins + 1)
-    ksum = np.bincount(b[sel], weights=(w * np.sqrt(m2.astype(np.float64)))[sel],
-                       minlength=n_bins + 1)
-    return np.rint(counts[1:]).astype(np.int64), ksum[1:]
+def mode_table(n, n_dk, n_bins, planes=None):
+    """(N_b int64, sum_b w|m| float64) per bin, from the half spectrum.
+
+    ``planes`` processes that many x-planes at a time (memory bound for
+    large N); the result does not depend on it.
+    """
+    planes = n if planes is None else planes
+    mx_all, my, mz = half_axes(n)
+    counts = np.zeros(n_bins + 1, dtype=np.int64)
+    ksum = np.zeros(n_bins + 1, dtype=np.float64)
+    for x0 in range(0, n, planes):
+        mx = mx_all[x0:x0 + planes]
+        m2 = mx * mx + my * my + mz * mz
+        b = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
+        w = np.broadcast_to(half_weights(n), m2.shape)
+        sel = (m2 > 0) & (b >= 1) & (b <= n_bins)
+        counts += np.bincount(b[sel], weights=w[sel], minlength=n_bins + 1).astype(np.int64)
+        ksum += np.bincount(b[sel], weights=(w * np.sqrt(m2.astype(np.float64)))[sel],
+                            minlength=n_bins + 1)
+    return counts[1:], ksum[1:]
 
 
 def delta_half(pos, box, n, p, interlace_on, workers=None):

@@ -1,0 +1,150 @@
+"""Parity at the full workload sizes, in the launch configuration the bench
+times (autotuned the same way), on outputs the oracle can reach:
+
+* headline (512^3 Zel'dovich particles, L = 2000, 1024^3 grid, PCS +
+  interlacing): mode counts and mean k of all 512 shells (exact / 1e-10),
+  both grids at sampled cells (tile corners, faces, the periodic wrap), and
+  delta(m) at sampled modes including Bragg peaks of the particle lattice on
+  the Nyquist planes (1e-5 relative);
+* 256^3 particles on a 256^3 grid: all 128 P(k) shells (1e-5) and a
+  bispectrum subset (A14 tolerance);
+* 64 uneven mocks on 128^3 grids replayed as one graph: sampled mocks;
+* adjoint: 128^3 particles on a 256^3 grid.
+
+The oracle uses its C loops (oracle/native.py) for the large deposits and
+sampled sums.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, bispectrum, native, spectrum
+import synth
+from gpu_common import rel_err, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+P_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def headline(torch):
+    from paper_1512_07295_amd.estimator import Estimator
+    pos = synth.zeldovich(512, 2000.0, 3, dtype=np.float32)
+    dpos = to_dev(torch, pos)
+    est = Estimator(1024, 2000.0, 4, True, 1, len(pos))
+    est.autotune(dpos, n_bins=512, iters=1)
+    yield pos, dpos, est
+    est.close()
+
+
+def test_headline_mode_counts_and_k(torch, headline):
+    pos, dpos, est = headline
+    k, pk, nm = est.power(dpos, n_bins=512)
+    counts, ksum = native.mode_table(1024, 1, 512)
+    assert np.array_equal(nm.cpu().numpy()[0], counts)
+    # FP64 sums of up to 3.3M terms in different orders: |error| <= n eps ~ 4e-10
+    assert rel_err(k.cpu().numpy()[0], 2 * np.pi / 2000.0 * ksum / counts) < 1e-10
+    assert np.all(np.isfinite(pk.cpu().numpy()))
+
+
+def test_headline_sampled_cells(torch, headline):
+    pos, dpos, est = headline
+    rng = np.random.default_rng(0)
+    cells = np.concatenate([
+        np.array([[0, 0, 0], [1023, 1023, 1023], [15, 16, 31], [16, 15, 0], [512, 511, 1023],
+                  [0, 1023, 16], [31, 32, 47], [1008, 15, 16]]),
+        rng.integers(0, 1024, (8, 3))])
+    est.deposit(dpos)
+    for which, shift in ((1, 0.0), (2, 0.5)):
+        g = est.copy_grid(which)
+        got = g[cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy().astype(np.float64)
+        del g
+        ref = native.cell_values(pos, 2000.0, 1024, 4, cells, shift)
+        assert np.all(np.abs(got - ref) <= 1e-6 + 1e-6 * np.abs(ref)), (which, got - ref)
+
+
+def test_headline_sampled_modes(torch, headline):
+    pos, dpos, est = headline
+    est.deposit(dpos)
+    est.transform()
+    modes = np.array([[1, 0, 0], [3, -2, 5], [512, 0, 0], [0, 512, 512], [-7, 100, 33],
+                      [512, 512, 512]])
+    got = est.sample_delta(modes).cpu().numpy()
+    ref = native.delta_modes(pos, 2000.0, 1024, 4, True, modes)
+    assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-10), (got, ref)
+
+
+def test_c2_power_all_shells_and_bispectrum_subset(torch):
+    from paper_1512_07295_amd.estimator import Estimator
+    box, n = 1000.0, 256
+    pos = synth.zeldovich(256, box, 2, dtype=np.float32)
+    est = Estimator(n, box, 4, True, 1, len(pos))
+    dpos = to_dev(torch, pos)
+    est.autotune(dpos, iters=1)
+    k, pk, nm = est.power(dpos)
+    delta, _ = native.delta_half(pos, box, n, 4, True)
+    k0, p0, n0 = spectrum.bin_power(delta, box, n, 1, n // 2)
+    assert np.array_equal(nm.cpu().numpy()[0], n0)
+    assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    # bispectrum: every shell up to k_N/2 (32 shells of 2 k_f), 240 triangles
+    nb, n_dk = 32, 2
+    tri_all = bispectrum.closed_triangles(nb)
+    rng = np.random.default_rng(1)
+    tri = tri_all[np.sort(rng.choice(len(tri_all), 240, replace=False))]
+    tri[0] = (nb, nb, nb)
+    bk, nt = est.bispectrum(tri, n_dk, nb)
+    bk, nt = bk.cpu().numpy(), nt.cpu().numpy()
+    masks = bispectrum.shell_masks(n, n_dk, nb)
+    fi = bispectrum.shell_fields(delta, masks, n)
+    s_iii = bispectrum.triple_sums(fi, tri)
+    s_abs = bispectrum.triple_sums(np.abs(fi), tri)
+    del fi
+    fj = bispectrum.shell_fields(np.ones_like(delta), masks, n)
+    s_jjj = bispectrum.triple_sums(fj, tri)
+    del fj
+    b0 = box ** 6 * s_iii / s_jjj
+    scale = np.maximum(np.abs(b0), box ** 6 * s_abs / s_jjj)
+    assert np.all(np.abs(nt - s_jjj / n ** 3) <= 1e-5 * s_jjj / n ** 3 + 1e-3)
+    assert np.all(np.abs(bk - b0) <= 1e-5 * scale)
+    est.close()
+
+
+def test_c4_batched_graph_sampled_mocks(torch):
+    from paper_1512_07295_amd.estimator import Estimator
+    box, n, nm_ = 500.0, 128, 64
+    pos, offs = synth.mocks(nm_, box, 100)
+    est = Estimator(n, box, 4, True, nm_, len(pos))
+    dpos, doffs = to_dev(torch, pos), to_dev(torch, offs)
+    est.autotune(dpos, offsets=doffs, iters=1)
+    k, pk, nmodes = est.capture(dpos, offsets=doffs)
+    est.replay()
+    est.replay()
+    torch.cuda.synchronize()
+    pk = pk.cpu().numpy()
+    for i in (0, 1, 30, 63):
+        part = pos[offs[i]:offs[i + 1]]
+        _, p0, n0 = native.power(part, box, n, 4, True)
+        assert np.array_equal(nmodes.cpu().numpy()[i], n0)
+        assert rel_err(pk[i], p0) < P_TOL, i
+    est.close()
+
+
+def test_c5_adjoint_full(torch):
+    from paper_1512_07295_amd.estimator import Estimator
+    box, n, nb = 1000.0, 256, 128
+    pos = synth.zeldovich(128, box, 5, dtype=np.float32)
+    tgt = synth.zeldovich(128, box, 6, dtype=np.float32)
+    _, target, counts = native.power(tgt, box, n, 4, True, 1, nb)
+    _, p_now, _ = native.power(pos, box, n, 4, True, 1, nb)
+    _, dldp = adjoint.chi2_loss(p_now, target, counts)
+    est = Estimator(n, box, 4, True, 1, len(pos))
+    g = est.backward(to_dev(torch, pos), to_dev(torch, dldp[None, :]), n_bins=nb).cpu().numpy()
+    ref = adjoint.position_gradient(pos, box, n, 4, True, 1, nb, dldp)
+    assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+    est.close()

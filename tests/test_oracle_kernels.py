@@ -168,3 +168,44 @@ def test_wrap_edge_cases():
     assert np.all((w >= 0) & (w < box))
     assert w[2] == 0.0 and w[3] == 0.0
     assert w[5] == pytest.approx(0.5) and w[6] == pytest.approx(999.75)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_c_loops_match_numpy_oracle(p, shift):
+    from oracle import native
+    n, box = 16, 80.0
+    pos = synth.uniform(3000, box, 31 + p, np.float32)
+    ref = assign.deposit(pos, box, n, p, True)[0 if shift == 0.0 else 1]
+    assert np.allclose(native.deposit(pos, box, n, p, shift), ref, rtol=0, atol=1e-12)
+    modes = np.array([[0, 0, 0], [1, -3, 5], [8, 8, 8], [-7, 2, 0], [5, 8, 3]])
+    assert np.allclose(native.footprint_dft(pos, box, n, p, modes, shift),
+                       direct.footprint_dft(pos, box, n, p, modes, shift), atol=1e-9)
+
+
+def test_c_delta_modes_and_power_match_numpy_oracle():
+    from oracle import native
+    n, box = 16, 200.0
+    pos = synth.zeldovich(12, box, 4, dtype=np.float32)
+    delta, _ = spectrum.delta_half(pos, box, n, 4, True)
+    modes = np.array([[1, 0, 0], [8, 0, 0], [-3, 5, 7], [8, 8, 8], [0, 8, 2]])
+    d = native.delta_modes(pos, box, n, 4, True, modes)
+    assert np.allclose(d, delta[modes[:, 0] % n, modes[:, 1] % n, modes[:, 2]], rtol=1e-10, atol=1e-14)
+    k0, p0, n0 = spectrum.power(pos, box, n, 4, True)
+    k1, p1, n1 = native.power(pos, box, n, 4, True)
+    assert np.array_equal(n0, n1) and np.allclose(p0, p1, rtol=1e-12)
+
+
+def test_c_cell_values_and_mode_table_match_numpy_oracle():
+    from oracle import native
+    n, box = 16, 60.0
+    pos = synth.uniform(2000, box, 8, np.float64)
+    cells = np.array([[0, 0, 0], [15, 15, 15], [3, 9, 14], [8, 0, 1]])
+    for shift in (0.0, 0.5):
+        assert np.allclose(native.cell_values(pos, box, n, 4, cells, shift),
+                           assign.cell_values(pos, box, n, 4, cells, shift), atol=1e-12)
+    for nn, dk in ((32, 1), (24, 2), (16, 3)):
+        nb = spectrum.max_bins(nn, dk)
+        c0, k0 = spectrum.mode_table(nn, dk, nb)
+        c1, k1 = native.mode_table(nn, dk, nb)
+        assert np.array_equal(c0, c1) and np.allclose(k0, k1, rtol=1e-12)
