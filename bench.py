@@ -64,8 +64,13 @@ def headline(args, torch, F, est_mod, synth):
         F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
 
     t0 = time.time()
-    choice = est.autotune(pos, n_bins=n_bins, iters=2)
-    log("autotuner picked launch shapes %d in %.1f s" % (choice, time.time() - t0))
+    if args.launch_choice is None:
+        choice = est.autotune(pos, n_bins=n_bins, iters=2)
+        log("autotuner picked launch shapes %d in %.1f s" % (choice, time.time() - t0))
+    else:
+        choice = args.launch_choice
+        est.set_launch(choice)
+        log("launch shapes %d (given)" % choice)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -205,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-choice", type=int, default=None,
+                    help="headline launch shapes (0..47) instead of autotuning them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()

@@ -14,6 +14,12 @@ autograd) live in :mod:`paper_1512_07295_amd.estimator`.
 import ctypes
 import os
 
+# torch ships its own HIP runtime.  It must be loaded before libfsest.so so
+# that the library's libamdhip64 dependency resolves to that same runtime:
+# loaded first, the library would bring in a second HIP runtime, which then
+# sees no device, and stream handles would not be shared.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsest.so")
 

@@ -166,6 +166,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   Buffers bb;
   bb.grid = (float2*)take(batch * n * (size_t)g.ps * sizeof(float2));
   bb.sorted = take((size_t)c.max_particles * 3 * sizeof(double));
+  bb.cells = (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t));
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
   bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
   bb.scan_tmp = (uint32_t*)take(((nkeys + 2047) / 2048 + 1) * sizeof(uint32_t));
@@ -193,8 +194,14 @@ est_status dev_err(hipError_t e, const char* what) {
   return fail(EST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// HIP keeps the last error of any API call in the thread (the caller's own
+// included) until it is read; launch checks read it, so every entry point
+// clears what was left before it starts launching.
+void clear_stale_error() { (void)hipGetLastError(); }
+
 est_status check_handle(est_handle h) {
   if (!h) return fail(EST_EINVAL, "handle is NULL");
+  clear_stale_error();
   return ok();
 }
 
@@ -315,6 +322,7 @@ est_status estimator_create(const est_config* cfg, void* workspace, size_t works
   layout(*cfg, (char*)workspace, &h->b, &h->tune_out);
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  clear_stale_error();
   st = dev_err(launch_tables(h->g, h->b, h->stream), "tables");
   if (st) {
     delete h;
@@ -556,7 +564,7 @@ static Tune tune_from_index(const int* id) {
   t.bin_blocks = vals_bins[id[1]];
   t.dep_threads = vals_dep[id[2]];
   t.dep_narrow = id[3];
-  t.dep_branchfree = id[4];
+  t.dep_xcd = id[4];
   return t;
 }
 
@@ -606,7 +614,7 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
     hipEventElapsedTime(ms, e0, e1);
     return EST_OK;
   };
-  int idx[5] = {1, 1, 1, 1, 0};  // start from the defaults
+  int idx[5] = {1, 1, 0, 1, 1};  // start from the defaults
   auto make = [&](const int* id) { return tune_from_index(id); };
   const int nvals[5] = {2, 3, 2, 2, 2};
   float best_ms = 1e30f;

@@ -83,24 +83,49 @@ __global__ __launch_bounds__(256) void k_bucket_count(const TP* __restrict__ pos
   rank[j] = atomicAdd(&counts[key], 1u);
 }
 
+// Cell record of one particle, used by the deposit to decide which tiles a
+// particle's stencils reach without redoing the float64 cell arithmetic:
+// bits 16a .. 16a+15 hold the first-grid floor cell along axis a (floor(u)
+// for even p, floor(u + 1/2) for odd p; mod N), bit 48 + a holds the step
+// from it to the same floor on the grid shifted by H/2 (0 or 1).
+__device__ __forceinline__ uint64_t cell_record(double ux, double uy, double uz, const Geom& g) {
+  const bool even = (g.order % 2) == 0;
+  const double u[3] = {ux, uy, uz};
+  uint64_t rec = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
+    const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
+    const double f2 = even ? floor(u2) : floor(u2 + 0.5);
+    rec |= (uint64_t)((int)f1 & (g.n - 1)) << (16 * a);
+    rec |= (uint64_t)((int)(f2 - f1) & 1) << (48 + a);
+  }
+  return rec;
+}
+
 template <typename TP>
 __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ pos, int64_t n_total,
                                                         const int64_t* __restrict__ offsets, Geom g,
                                                         const uint32_t* __restrict__ boff,
                                                         const uint32_t* __restrict__ rank,
-                                                        TP* __restrict__ sorted) {
+                                                        TP* __restrict__ sorted,
+                                                        uint64_t* __restrict__ cells) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_total) return;
   TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
   const int mock = mock_of(offsets, g.batch, j);
-  const int bx = base_cell(grid_coord((double)px, g.box, g.inv), g.n) / kBucket;
-  const int by = base_cell(grid_coord((double)py, g.box, g.inv), g.n) / kBucket;
-  const int bz = base_cell(grid_coord((double)pz, g.box, g.inv), g.n) / kBucket;
+  const double ux = grid_coord((double)px, g.box, g.inv);
+  const double uy = grid_coord((double)py, g.box, g.inv);
+  const double uz = grid_coord((double)pz, g.box, g.inv);
+  const int bx = base_cell(ux, g.n) / kBucket;
+  const int by = base_cell(uy, g.n) / kBucket;
+  const int bz = base_cell(uz, g.n) / kBucket;
   const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
   const int64_t dst = (int64_t)boff[key] + rank[j];
   sorted[3 * dst + 0] = px;
   sorted[3 * dst + 1] = py;
   sorted[3 * dst + 2] = pz;
+  cells[dst] = cell_record(ux, uy, uz, g);
 }
 
 // exclusive scan of n items in place, 2048 items per block
@@ -175,7 +200,7 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
   const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
   hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_fill_u32(b.stats, 1, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(b.stats, 2, 0u, s)) != hipSuccess) return e;
   const unsigned pblocks = (unsigned)((n_total + 255) / 256);
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
@@ -193,11 +218,11 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
-                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted);
+                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3(pblocks), dim3(256), 0, s,
                        (const double*)pos, n_total, offsets, g, b.boff, b.rank,
-                       (double*)b.sorted);
+                       (double*)b.sorted, b.cells);
   return hipGetLastError();
 }
 
@@ -266,7 +291,7 @@ __device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
 // ------------------------------------------------------------------ deposit
 // Fixed-point accumulation.  LDS float atomics are ~20x slower than integer
 // ones on gfx950, so a workgroup sums its tile in unsigned integers: a weight
-// product w in [0, 1] adds round(w * S).  Two formats:
+// product w in [0, 1] adds floor(w * S + 1/2).  Two formats:
 //  * wide (64-bit): S = 2^32 - 2^8; a grid sums to N_P < 2^31 units, so no
 //    cell can overflow;
 //  * narrow (32-bit): S = 2^F with F chosen on the device from the largest
@@ -279,7 +304,6 @@ __device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
 // Integer sums are exact, so deposits are bitwise reproducible.
 constexpr float kFixWide = 4294967040.0f;  // 2^32 - 2^8
 constexpr int kNarrowMinBits = 24;
-constexpr int kListCap = 2048;  // LDS list of particles that reach the tile
 
 __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
   const double bound = 8.0 * (double)(maxcount > 0 ? maxcount : 1);
@@ -288,284 +312,522 @@ __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
   return f;
 }
 
+// LDS layout of a deposit workgroup, in 32-bit words:
+//   [0, kItemCap)            particle index of each work item
+//   [.., + kItemCap/4)       item meta bytes: bank class (6 bits) | grid << 6
+//   [.., + kItemCap/2)       item order after sorting by bank class (u16)
+//   [kAccWord, ...)          tile accumulators, one region of kGridWords
+//                            elements per grid
+// Each tile row holds kZHalo extra cells on both z sides, so every cell of a
+// stencil row that reaches the tile has an address: a stencil is added at
+// base + i*kPlane + k*kRow + l with compile-time offsets, rows outside the
+// tile in x or y are skipped, and halo cells are dropped (or, when the tile
+// is the whole periodic grid, folded back) at write-out.  kRow and kPlane
+// make the 64 offsets i*kPlane + k*kRow + l (i, k, l < 4) distinct mod 64,
+// so two stencils whose bases differ mod 64 never share an LDS bank in one
+// instruction; work items are ordered by that residue ("bank class") and
+// each wave takes items spread evenly over the order, which keeps the
+// classes of its 64 lanes distinct except where a class holds more items
+// than there are waves in the flush.
+constexpr int kZHalo = 3;
+constexpr int kRow = 28;
+constexpr int kPlane = 464;
+constexpr int kGridWords = kTileMax * kPlane;
+constexpr int kItemCap = 2048;
+constexpr int kAccWord = kItemCap + kItemCap / 4 + kItemCap / 2;
+
+constexpr bool offsets_cover_banks() {
+  bool seen[64] = {};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k)
+      for (int l = 0; l < 4; ++l) {
+        const int r = (i * kPlane + k * kRow + l) % 64;
+        if (seen[r]) return false;
+        seen[r] = true;
+      }
+  return true;
+}
+static_assert(offsets_cover_banks(), "stencil offsets must cover the 64 banks");
+static_assert(kRow >= kTileMax + 2 * kZHalo && kPlane >= kTileMax * kRow, "tile pitches");
+static_assert(kAccWord % 64 == 0 && kGridWords % 64 == 0, "regions start on bank 0");
+// the lowest element a stencil base can address lies kAccMargin below a region
+constexpr int kAccMargin = 3 * kPlane + 3 * kRow;
+static_assert(kAccWord / 2 >= kAccMargin, "base addresses stay non-negative (64-bit elements)");
+
 struct DepRanges {
   uint32_t start[72];
   uint32_t pref[73];
   int count;
 };
 
-// does the reach c-1 .. c+3 (both grids, every p <= 4) of base cell c touch
-// [t0, t0 + T) on a periodic axis of length n?
-__device__ __forceinline__ bool axis_reaches(int c, int t0, int T, int n) {
-  const int lo = (c - 1 - t0) & (n - 1);
-  return lo < T || lo > n - 5;
+// First cell of the p-point stencil along one axis (not wrapped) and its
+// weights times `scale`, for grid coordinate u (the cell choice of
+// stencil_1d, whose weights these are).
+template <int P>
+__device__ __forceinline__ int stencil_first(double u, float scale, float (&w)[P]) {
+  int cell[P];
+  stencil_1d<P>(u, 1 << 30, cell, w);
+  const double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
+#pragma unroll
+  for (int i = 0; i < P; ++i) w[i] *= scale;
+  return (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
 }
 
-// ... and does it lie inside [t0, t0 + T)?
-__device__ __forceinline__ bool axis_inside(int c, int t0, int T, int n) {
-  const int lo = (c - 1 - t0) & (n - 1);
-  return T == n || lo <= T - 5;
+template <int P>
+__device__ __forceinline__ int first_cell(double u) {
+  const double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
+  return (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
 }
 
-// Adds one particle's footprint (both grids) to the tile.  INTERIOR: the
-// footprint is known to lie inside the tile (no masks).  Otherwise cells
-// outside the tile are skipped, either by branches or (BRANCHFREE) by adding
-// 0 to this lane's own dummy slot acc[dummy].
-template <int P, bool IL, typename TP, typename AT, bool INTERIOR, bool BRANCHFREE>
-__device__ __forceinline__ void deposit_particle(const TP* __restrict__ sorted, uint32_t j, const Geom& g,
-                                                 int t0x, int t0y, int t0z, int T, AT* acc,
-                                                 int dummy, float scale) {
-  constexpr int NG = IL ? 2 : 1;
+// Position of a stencil's first cell relative to the tile origin t0.  For a
+// tile smaller than the grid the result lies in [-(P-1), n - P + 1) and the
+// stencil reaches the tile iff it is < T; for a tile that is the whole grid
+// it lies in [0, n).
+template <int P, bool PERIODIC>
+__device__ __forceinline__ int rel_first(int first, int t0, int n) {
+  const int r = (first - t0) & (n - 1);
+  if constexpr (PERIODIC) return r;
+  else return (r >= n - (P - 1)) ? r - n : r;
+}
+
+template <int P, bool PERIODIC>
+__device__ __forceinline__ bool reaches_tile(int rx, int ry, int rz) {
+  if constexpr (PERIODIC) return true;
+  else return rx < kTileMax && ry < kTileMax && rz < kTileMax;
+}
+
+__device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
+  return (rx * kPlane + ry * kRow + rz + kZHalo) & 63;
+}
+
+// Adds one grid's footprint of one particle to the tile.
+template <int P, typename AT, bool PERIODIC>
+__device__ __forceinline__ void deposit_item(double x, double y, double z, int gi, const Geom& g,
+                                             int t0x, int t0y, int t0z, AT* sm, float scale) {
   const int n = g.n;
-  const int T3 = T * T * T;
-  double x, y, z;
-  load_pos(sorted, (int64_t)j, x, y, z);
-  const double ux = grid_coord(x, g.box, g.inv);
-  const double uy = grid_coord(y, g.box, g.inv);
-  const double uz = grid_coord(z, g.box, g.inv);
-#pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const double sh = gi ? 0.5 : 0.0;
-    int cx[P], cy[P], cz[P];
-    float wx[P], wy[P], wz[P];
-    stencil_1d<P>(ux + sh, n, cx, wx);
-    stencil_1d<P>(uy + sh, n, cy, wy);
-    stencil_1d<P>(uz + sh, n, cz, wz);
-    int lx[P], ly[P], lz[P];
-    bool ix[P], iy[P], iz[P];
-    unsigned mx = 0, my = 0, mz = 0;
+  const double sh = gi ? 0.5 : 0.0;
+  float wx[P], wy[P], wz[P];
+  const int fx = stencil_first<P>(grid_coord(x, g.box, g.inv) + sh, scale, wx);
+  const int fy = stencil_first<P>(grid_coord(y, g.box, g.inv) + sh, 1.0f, wy);
+  const int fz = stencil_first<P>(grid_coord(z, g.box, g.inv) + sh, 1.0f, wz);
+  const int rx = rel_first<P, PERIODIC>(fx, t0x, n);
+  const int ry = rel_first<P, PERIODIC>(fy, t0y, n);
+  const int rz = rel_first<P, PERIODIC>(fz, t0z, n);
+  const int region = (kAccWord * 4 / (int)sizeof(AT)) + gi * kGridWords;
+  if constexpr (PERIODIC) {
+    // the tile is the whole grid (n <= kTileMax): x and y wrap, z runs into
+    // the upper halo and is folded back at write-out
+    AT* zrow = sm + region + rz + kZHalo;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      lx[i] = (cx[i] - t0x) & (n - 1);
-      ly[i] = (cy[i] - t0y) & (n - 1);
-      lz[i] = (cz[i] - t0z) & (n - 1);
-      ix[i] = lx[i] < T;
-      iy[i] = ly[i] < T;
-      iz[i] = lz[i] < T;
-      mx |= ix[i] ? (1u << i) : 0u;
-      my |= iy[i] ? (1u << i) : 0u;
-      mz |= iz[i] ? (1u << i) : 0u;
-    }
-    if constexpr (!INTERIOR && !BRANCHFREE)
-      if (!mx || !my || !mz) continue;
-    const int base = gi * T3;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      if constexpr (!INTERIOR && !BRANCHFREE)
-        if (!(mx & (1u << i))) continue;
+      const int xo = ((rx + i) & (n - 1)) * kPlane;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        if constexpr (!INTERIOR && !BRANCHFREE)
-          if (!(my & (1u << k))) continue;
-        const float wxy = wx[i] * wy[k] * scale;
-        const int rowi = base + (lx[i] * T + ly[k]) * T;
+        AT* row = zrow + xo + ((ry + k) & (n - 1)) * kRow;
+        const float wxy = wx[i] * wy[k];
 #pragma unroll
-        for (int l = 0; l < P; ++l) {
-          if constexpr (INTERIOR) {
-            atomicAdd(&acc[rowi + lz[l]], (AT)__float2uint_rn(wxy * wz[l]));
-          } else if constexpr (BRANCHFREE) {
-            const bool in = ix[i] && iy[k] && iz[l];
-            const unsigned q = in ? __float2uint_rn(wxy * wz[l]) : 0u;
-            atomicAdd(&acc[in ? rowi + lz[l] : dummy], (AT)q);
-          } else {
-            if (!(mz & (1u << l))) continue;
-            atomicAdd(&acc[rowi + lz[l]], (AT)__float2uint_rn(wxy * wz[l]));
-          }
-        }
+        for (int l = 0; l < P; ++l)
+          atomicAdd(&row[l], (AT)(uint32_t)__builtin_fmaf(wxy, wz[l], 0.5f));
+      }
+    }
+  } else {
+    AT* base = sm + region + rx * kPlane + ry * kRow + rz + kZHalo;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      if ((unsigned)(rx + i) >= (unsigned)kTileMax) continue;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        if ((unsigned)(ry + k) >= (unsigned)kTileMax) continue;
+        const float wxy = wx[i] * wy[k];
+#pragma unroll
+        for (int l = 0; l < P; ++l)
+          atomicAdd(&base[i * kPlane + k * kRow + l],
+                    (AT)(uint32_t)__builtin_fmaf(wxy, wz[l], 0.5f));
       }
     }
   }
 }
 
-template <int P, bool IL, typename TP, bool WIDE, bool BRANCHFREE>
+// Segment of each lane's candidate: a scalar search for the wave's first
+// item c0, then the few segment starts inside the wave's 64 items.
+__device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_t c0,
+                                            uint32_t item) {
+  int lo = 0, hi = nr;  // pref[lo] <= c0 < pref[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)rg.pref[mid]) <= c0) lo = mid;
+    else hi = mid;
+  }
+  int seg = lo;
+  for (int t = lo + 1; t < nr; ++t) {
+    const uint32_t pt = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.pref[t]);
+    if (pt > c0 + 63) break;
+    if (item >= pt) seg = t;
+  }
+  return seg;
+}
+
+// One workgroup owns one T^3 output tile (T = min(kTileMax, N)) of every
+// grid at a time.  Per tile: (1) the particles of the buckets that can
+// reach the tile are scanned in rounds of blockDim items; each grid whose
+// stencil reaches the tile becomes a work item in an LDS list and counts
+// towards its bank class; (2) whenever the list might overflow, it is
+// counting-sorted by class and deposited with LDS integer atomics, lane l of
+// virtual wave r taking sorted item r + l * W (W = virtual waves in the
+// flush); (3) the finished tile is scaled back to float and written once.
+// `dynamic`: tiles are taken from a global counter (stats[1], zeroed with
+// the sort) instead of one tile per workgroup.  `xcd`: consecutive tiles go
+// to the same XCD (workgroup b runs on XCD b mod 8), so the buckets that
+// neighbouring tiles share are read through one L2.
+template <int P, bool IL, typename TP, bool WIDE, bool PERIODIC>
 __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
+                                                  const uint64_t* __restrict__ cells,
                                                   const uint32_t* __restrict__ boff, float* grid,
-                                                  Geom g, const uint32_t* __restrict__ stats,
-                                                  int exclusive) {
+                                                  Geom g, uint32_t* __restrict__ stats,
+                                                  int exclusive, int dynamic, int xcd) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
-  constexpr int TM = kTileMax;
   constexpr int NG = IL ? 2 : 1;
   constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
-  __shared__ AT acc[NG * TM * TM * TM + 64];  // + one dummy slot per lane
+  constexpr int kWords = kAccWord + NG * kGridWords * (int)(sizeof(AT) / 4);
+  __shared__ __align__(16) uint32_t smem[kWords];
   __shared__ DepRanges rg;
-  __shared__ uint32_t list[kListCap];
-  __shared__ int wave_cnt[2 * MAXW];
-  __shared__ int fill_in, fill_edge;
+  __shared__ int wave_cnt[MAXW];
+  __shared__ int cls_cnt[64];
+  __shared__ int cls_cur[64];
+  __shared__ int fill, next_tile;
+  uint32_t* item_j = smem;
+  uint8_t* item_meta = reinterpret_cast<uint8_t*>(smem + kItemCap);
+  uint16_t* item_order = reinterpret_cast<uint16_t*>(smem + kItemCap + kItemCap / 4);
+  AT* sm = reinterpret_cast<AT*>(smem);
+  const int acc0 = kAccWord * 4 / (int)sizeof(AT);
 
   // fixed-point format for this deposit (uniform over the grid)
   const int nbits = narrow_bits(stats[0]);
-  if (!WIDE && nbits < kNarrowMinBits) return;          // the wide kernel does it
+  if (!WIDE && nbits < kNarrowMinBits) return;                // the wide kernel does it
   if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
   const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
   const double inv_scale = 1.0 / (double)scale;
 
   const int n = g.n, T = g.tile, nb = g.nb;
   const int tpa = n / T;  // tiles per axis
-  const int64_t tid_all = blockIdx.x;
-  const int mock = (int)(tid_all / ((int64_t)tpa * tpa * tpa));
-  const int trem = (int)(tid_all % ((int64_t)tpa * tpa * tpa));
-  const int tx = trem / (tpa * tpa), ty = (trem / tpa) % tpa, tz = trem % tpa;
-  const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
-  const int T3 = T * T * T;
+  const int64_t tiles_per_set = (int64_t)tpa * tpa * tpa;
+  const int64_t ntiles = (int64_t)g.batch * tiles_per_set;
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (nthreads + 63) >> 6;
+  const bool remap = xcd && !dynamic && (int64_t)gridDim.x == ntiles && (ntiles & 7) == 0;
 
-  for (int i = threadIdx.x; i < NG * T3 + 64; i += nthreads) acc[i] = 0;
-  if (threadIdx.x == 0) {
-    fill_in = 0;
-    fill_edge = 0;
+  int64_t b = blockIdx.x;
+  if (dynamic) {
+    if (threadIdx.x == 0) next_tile = (int)atomicAdd(&stats[1], 1u);
+    __syncthreads();
+    b = next_tile;
   }
+  while (b < ntiles) {
+    const int64_t tid_all = remap ? ((b & 7) * (ntiles >> 3) + (b >> 3)) : b;
+    const int mock = (int)(tid_all / tiles_per_set);
+    const int trem = (int)(tid_all % tiles_per_set);
+    const int tx = trem / (tpa * tpa), ty = (trem / tpa) % tpa, tz = trem % tpa;
+    const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
 
-  // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
-  int cnt = T / kBucket + 2;
-  if (cnt > nb) cnt = nb;
-  const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - 1 + nb) % nb;
-  const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - 1 + nb) % nb;
-  const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - 1 + nb) % nb;
-  const int ncomb = cnt * cnt;  // <= 36
-  const int64_t mbase = (int64_t)mock * nb * nb * nb;
-  if (wave == 0) {
-    uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
-    if (lane < ncomb) {
-      const int ix = lane / cnt, iy = lane % cnt;
-      const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
-      const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
-      const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
-      if (z1 <= nb) {
-        s0 = boff[row + b0z];
-        e0 = boff[row + z1];
-      } else {
-        s0 = boff[row + b0z];
-        e0 = boff[row + nb];
-        s1 = boff[row];
-        e1 = boff[row + (z1 - nb)];
+    if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) fill = 0;
+
+    // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
+    int cnt = T / kBucket + 2;
+    if (cnt > nb) cnt = nb;
+    const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - 1 + nb) % nb;
+    const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - 1 + nb) % nb;
+    const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - 1 + nb) % nb;
+    const int ncomb = cnt * cnt;  // <= 36
+    const int64_t mbase = (int64_t)mock * nb * nb * nb;
+    if (wave == 0) {
+      uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
+      if (lane < ncomb) {
+        const int ix = lane / cnt, iy = lane % cnt;
+        const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
+        const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
+        const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
+        if (z1 <= nb) {
+          s0 = boff[row + b0z];
+          e0 = boff[row + z1];
+        } else {
+          s0 = boff[row + b0z];
+          e0 = boff[row + nb];
+          s1 = boff[row];
+          e1 = boff[row + (z1 - nb)];
+        }
       }
-    }
-    // exclusive prefix of the per-lane lengths across the wave
-    const uint32_t la = e0 - s0, lb = e1 - s1;
-    uint32_t incl = la + lb;
+      // exclusive prefix of the per-lane lengths across the wave
+      const uint32_t la = e0 - s0, lb = e1 - s1;
+      uint32_t incl = la + lb;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
-      if (lane >= off) incl += o;
-    }
-    const uint32_t excl = incl - la - lb;
-    if (lane < ncomb) {
-      rg.start[2 * lane] = s0;
-      rg.start[2 * lane + 1] = s1;
-      rg.pref[2 * lane + 1] = excl + la;
-      rg.pref[2 * lane + 2] = excl + la + lb;
-    }
-    if (lane == 0) {
-      rg.pref[0] = 0;
-      rg.count = 2 * ncomb;
-    }
-  }
-  __syncthreads();
-  const uint32_t total = rg.pref[rg.count];
-  const int nr = rg.count;
-
-  // rounds of nthreads items: particles that reach the tile go to an LDS
-  // list (fully inside ones from the front, the others from the back); the
-  // list is deposited whenever another round might not fit
-  for (uint32_t r0 = 0; r0 < total; r0 += nthreads) {
-    const uint32_t item = r0 + threadIdx.x;
-    bool useful = false, inside = false;
-    uint32_t j = 0;
-    if (item < total) {
-      int lo = 0, hi = nr;  // pref[lo] <= item < pref[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (rg.pref[mid] <= item) lo = mid; else hi = mid;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += o;
       }
-      j = rg.start[lo] + (item - rg.pref[lo]);
-      double x, y, z;
-      load_pos(sorted, (int64_t)j, x, y, z);
-      const int cx = base_cell(grid_coord(x, g.box, g.inv), n);
-      const int cy = base_cell(grid_coord(y, g.box, g.inv), n);
-      const int cz = base_cell(grid_coord(z, g.box, g.inv), n);
-      useful = axis_reaches(cx, t0x, T, n) && axis_reaches(cy, t0y, T, n) &&
-               axis_reaches(cz, t0z, T, n);
-      inside = useful && axis_inside(cx, t0x, T, n) && axis_inside(cy, t0y, T, n) &&
-               axis_inside(cz, t0z, T, n);
-    }
-    const bool edge = useful && !inside;
-    const unsigned long long bal_in = __ballot(inside);
-    const unsigned long long bal_ed = __ballot(edge);
-    if (lane == 0) {
-      wave_cnt[wave] = __popcll(bal_in);
-      wave_cnt[MAXW + wave] = __popcll(bal_ed);
-    }
-    __syncthreads();
-    int before_in = 0, before_ed = 0, tot_in = 0, tot_ed = 0;
-    for (int w = 0; w < nwaves; ++w) {
-      const int ci = wave_cnt[w], ce = wave_cnt[MAXW + w];
-      before_in += (w < wave) ? ci : 0;
-      before_ed += (w < wave) ? ce : 0;
-      tot_in += ci;
-      tot_ed += ce;
-    }
-    const int fi0 = fill_in, fe0 = fill_edge;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    if (inside) list[fi0 + before_in + __popcll(bal_in & below)] = j;
-    if (edge) list[kListCap - 1 - (fe0 + before_ed + __popcll(bal_ed & below))] = j;
-    __syncthreads();
-    const int fi = fi0 + tot_in, fe = fe0 + tot_ed;
-    const bool last = r0 + nthreads >= total;
-    if (fi + fe > kListCap - nthreads || last) {
-      for (int e = threadIdx.x; e < fi; e += nthreads)
-        deposit_particle<P, IL, TP, AT, true, false>(sorted, list[e], g, t0x, t0y, t0z, T, acc,
-                                                     NG * T3 + lane, scale);
-      for (int e = threadIdx.x; e < fe; e += nthreads)
-        deposit_particle<P, IL, TP, AT, false, BRANCHFREE>(sorted, list[kListCap - 1 - e], g, t0x,
-                                                           t0y, t0z, T, acc, NG * T3 + lane, scale);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        fill_in = 0;
-        fill_edge = 0;
+      const uint32_t excl = incl - la - lb;
+      if (lane < ncomb) {
+        rg.start[2 * lane] = s0;
+        rg.start[2 * lane + 1] = s1;
+        rg.pref[2 * lane + 1] = excl + la;
+        rg.pref[2 * lane + 2] = excl + la + lb;
       }
-    } else if (threadIdx.x == 0) {
-      fill_in = fi;
-      fill_edge = fe;
+      if (lane == 0) {
+        rg.pref[0] = 0;
+        rg.count = 2 * ncomb;
+      }
+    }
+    // the other waves clear the tile while wave 0 waits for the offsets
+    {
+      uint4* z4 = reinterpret_cast<uint4*>(smem + kAccWord);
+      constexpr int kZero4 = (kWords - kAccWord) / 4;
+      for (int i = threadIdx.x; i < kZero4; i += nthreads) z4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
-  }
+    const uint32_t total = rg.pref[rg.count];
+    const int nr = rg.count;
 
-  for (int i = threadIdx.x; i < T3; i += nthreads) {
-    const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-    const float v1 = (float)((double)acc[i] * inv_scale);
-    if constexpr (IL) {
-      const float v2 = (float)((double)acc[T3 + i] * inv_scale);
-      reinterpret_cast<float2*>(grid)[complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] =
-          make_float2(v1, v2);
+    // rounds of blockDim candidates; the cell records of kPre rounds are
+    // loaded together so that their latencies overlap
+    constexpr int kPre = 4;
+    constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
+    for (uint32_t rb = 0; rb < total; rb += kPre * nthreads) {
+      uint32_t jj[kPre];
+      uint64_t rec[kPre];
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) {
+        const uint32_t r0 = rb + q * nthreads;
+        const uint32_t item = r0 + threadIdx.x;
+        jj[q] = 0;
+        rec[q] = 0;
+        if (r0 < total) {
+          const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item);
+          if (item < total) {
+            jj[q] = rg.start[seg] + (item - rg.pref[seg]);
+            rec[q] = cells[jj[q]];
+          }
+        }
+      }
+#pragma unroll 1
+      for (int q = 0; q < kPre; ++q) {
+        const uint32_t r0 = rb + q * nthreads;
+        if (r0 >= total) break;
+        // (1) candidates of this round -> work items
+        const uint32_t item = r0 + threadIdx.x;
+        const uint32_t j = jj[0];
+        bool ok[NG];
+        int cls[NG];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          ok[gi] = false;
+          cls[gi] = 0;
+        }
+        if (item < total) {
+          const uint64_t r = rec[0];
+          const int cx = (int)(r & 0xFFFF) - off;
+          const int cy = (int)((r >> 16) & 0xFFFF) - off;
+          const int cz = (int)((r >> 32) & 0xFFFF) - off;
+#pragma unroll
+          for (int gi = 0; gi < NG; ++gi) {
+            const int sx = gi ? (int)((r >> 48) & 1) : 0;
+            const int sy = gi ? (int)((r >> 49) & 1) : 0;
+            const int sz = gi ? (int)((r >> 50) & 1) : 0;
+            const int rx = rel_first<P, PERIODIC>(cx + sx, t0x, n);
+            const int ry = rel_first<P, PERIODIC>(cy + sy, t0y, n);
+            const int rz = rel_first<P, PERIODIC>(cz + sz, t0z, n);
+            ok[gi] = reaches_tile<P, PERIODIC>(rx, ry, rz);
+            cls[gi] = bank_class(rx, ry, rz);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t + 1 < kPre; ++t) {
+          jj[t] = jj[t + 1];
+          rec[t] = rec[t + 1];
+        }
+        unsigned long long bal[NG];
+        int mine = 0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          bal[gi] = __ballot(ok[gi]);
+          mine += __popcll(bal[gi]);
+        }
+        if (lane == 0) wave_cnt[wave] = mine;
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int w = 0; w < nwaves; ++w) {
+          const int c = wave_cnt[w];
+          before += (w < wave) ? c : 0;
+          tot += c;
+        }
+        const int f0 = fill;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int pos = f0 + before;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          if (ok[gi]) {
+            const int p = pos + __popcll(bal[gi] & below);
+            item_j[p] = j;
+            item_meta[p] = (uint8_t)(cls[gi] | (gi << 6));
+            atomicAdd(&cls_cnt[cls[gi]], 1);
+          }
+          pos += __popcll(bal[gi]);
+        }
+        __syncthreads();
+        const int m = f0 + tot;
+        const bool last = r0 + nthreads >= total;
+        if (m + NG * nthreads > kItemCap || last) {
+          // (2) sort the items by bank class, then deposit them
+          if (wave == 0) {
+            const int c = cls_cnt[lane];
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+              const int t = __shfl_up(incl, o, 64);
+              if (lane >= o) incl += t;
+            }
+            cls_cur[lane] = incl - c;
+            cls_cnt[lane] = 0;
+          }
+          __syncthreads();
+          for (int e = threadIdx.x; e < m; e += nthreads)
+            item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
+          __syncthreads();
+          // lane l of virtual wave r takes item r + l W; each item's position
+          // is loaded one iteration ahead
+          const int W = (m + 63) >> 6;
+          const int vend = 64 * W;
+          int e_cur = -1;
+          TP px = 0, py = 0, pz = 0;
+          {
+            const int v = threadIdx.x;
+            const int p = (v >> 6) + (v & 63) * W;
+            if (v < vend && p < m) {
+              e_cur = item_order[p];
+              const int64_t jq = item_j[e_cur];
+              px = sorted[3 * jq + 0];
+              py = sorted[3 * jq + 1];
+              pz = sorted[3 * jq + 2];
+            }
+          }
+          for (int v = threadIdx.x; v < vend; v += nthreads) {
+            const int vn = v + nthreads;
+            const int pn = (vn >> 6) + (vn & 63) * W;
+            int e_nxt = -1;
+            TP nx = 0, ny = 0, nz = 0;
+            if (vn < vend && pn < m) {
+              e_nxt = item_order[pn];
+              const int64_t jq = item_j[e_nxt];
+              nx = sorted[3 * jq + 0];
+              ny = sorted[3 * jq + 1];
+              nz = sorted[3 * jq + 2];
+            }
+            if (e_cur >= 0)
+              deposit_item<P, AT, PERIODIC>((double)px, (double)py, (double)pz,
+                                            item_meta[e_cur] >> 6, g, t0x, t0y, t0z, sm, scale);
+            e_cur = e_nxt;
+            px = nx;
+            py = ny;
+            pz = nz;
+          }
+          __syncthreads();
+          if (threadIdx.x == 0) fill = 0;
+        } else if (threadIdx.x == 0) {
+          fill = m;
+        }
+        __syncthreads();
+      }
+    }
+
+    // (3) write the tile (halo cells dropped, or folded back when periodic)
+    if constexpr (!PERIODIC) {
+      // four consecutive z cells per thread; the narrow scale is a power of
+      // two, so float(sum) * 2^-F rounds exactly like the double product
+      constexpr int TT = kTileMax;
+      const float inv_f = (float)inv_scale;
+      for (int i = threadIdx.x; i < TT * TT * TT / 4; i += nthreads) {
+        const int lx = i / (TT * TT / 4), ly = (i / (TT / 4)) % TT, lz = (i % (TT / 4)) * 4;
+        float v[NG][4];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + kZHalo;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const AT s = sm[a + q];
+            v[gi][q] = WIDE ? (float)((double)s * inv_scale) : (float)s * inv_f;
+          }
+        }
+        if constexpr (IL) {
+          float4* dst = reinterpret_cast<float4*>(
+              reinterpret_cast<float2*>(grid) + complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz));
+          dst[0] = make_float4(v[0][0], v[NG - 1][0], v[0][1], v[NG - 1][1]);
+          dst[1] = make_float4(v[0][2], v[NG - 1][2], v[0][3], v[NG - 1][3]);
+        } else {
+          *reinterpret_cast<float4*>(grid + real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)) =
+              make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
+        }
+      }
     } else {
-      grid[real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] = v1;
+      for (int i = threadIdx.x; i < T * T * T; i += nthreads) {
+        const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
+        float v[NG];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + kZHalo;
+          AT s = sm[a];
+          if (lz < kZHalo) s += sm[a + T];
+          v[gi] = (float)((double)s * inv_scale);
+        }
+        if constexpr (IL) {
+          reinterpret_cast<float2*>(grid)[complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] =
+              make_float2(v[0], v[NG - 1]);
+        } else {
+          grid[real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] = v[0];
+        }
+      }
+    }
+    if (dynamic) {
+      __syncthreads();  // every thread has read next_tile and finished the tile
+      if (threadIdx.x == 0) next_tile = (int)atomicAdd(&stats[1], 1u);
+      __syncthreads();
+      b = next_tile;
+    } else {
+      b += gridDim.x;
+      __syncthreads();
     }
   }
 }
 
-template <int P, bool IL, typename TP, bool BF>
-static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, hipStream_t s) {
+template <int P, bool IL, typename TP, bool PER>
+static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
+                           hipStream_t s) {
   const int tpa = g.n / g.tile;
-  const unsigned blocks = (unsigned)((int64_t)g.batch * tpa * tpa * tpa);
+  const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   if (narrow)
-    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, BF>), dim3(blocks), dim3(threads), 0, s,
-                       (const TP*)b.sorted, b.boff, (float*)b.grid, g, b.stats, 0);
-  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, BF>), dim3(blocks), dim3(threads), 0, s,
-                     (const TP*)b.sorted, b.boff, (float*)b.grid, g, b.stats, narrow ? 0 : 1);
+    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, PER>), dim3((unsigned)ntiles), dim3(threads),
+                       0, s, (const TP*)b.sorted, b.cells, b.boff, (float*)b.grid, g, b.stats, 0,
+                       0, xcd ? 1 : 0);
+  // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
+  // counter, so when the 32-bit kernel does the work it costs one short wave
+  // per workgroup
+  const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
+  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, PER>), dim3(wblocks), dim3(threads), 0, s,
+                     (const TP*)b.sorted, b.cells, b.boff, (float*)b.grid, g, b.stats,
+                     narrow ? 0 : 1, 1, 0);
 }
 
 template <int P, bool IL>
 static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
                                int threads, hipStream_t s) {
   const bool narrow = tu.dep_narrow != 0;
+  const bool xcd = tu.dep_xcd != 0;
+  const bool per = g.tile == g.n;
   if (dt == EST_F32) {
-    if (tu.dep_branchfree) deposit_launch<P, IL, float, true>(g, b, threads, narrow, s);
-    else deposit_launch<P, IL, float, false>(g, b, threads, narrow, s);
+    if (per) deposit_launch<P, IL, float, true>(g, b, threads, narrow, xcd, s);
+    else deposit_launch<P, IL, float, false>(g, b, threads, narrow, xcd, s);
   } else {
-    if (tu.dep_branchfree) deposit_launch<P, IL, double, true>(g, b, threads, narrow, s);
-    else deposit_launch<P, IL, double, false>(g, b, threads, narrow, s);
+    if (per) deposit_launch<P, IL, double, true>(g, b, threads, narrow, xcd, s);
+    else deposit_launch<P, IL, double, false>(g, b, threads, narrow, xcd, s);
   }
 }
 

@@ -44,10 +44,11 @@ __device__ __forceinline__ int64_t complex_index(const Geom& g, int mock, int x,
 struct Buffers {
   float2* grid;            // batch * N * N * nz complex (rho1 + i rho2, or packed reals)
   void* sorted;            // max_particles * 3 * 8 bytes
+  uint64_t* cells;         // max_particles cell records (sorted order)
   uint32_t* rank;          // max_particles
   uint32_t* boff;          // batch * nb^3 + 1 bucket offsets
   uint32_t* scan_tmp;      // scan block sums
-  uint32_t* stats;         // [0] = largest bucket count of the last sort
+  uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter
   float2* tw_n;            // exp(-2 pi i n / N)
   float2* tw_nz;           // exp(-2 pi i n / nz)
   float* inv_w2;           // 1 / W_1D(m(i))^2 for FFT index i (N entries)
@@ -66,9 +67,9 @@ struct Buffers {
 struct Tune {
   int cols_c = 16;        // lines per workgroup of the strided FFT passes
   int bin_blocks = 1024;  // reduction workgroups per set in the fused P(k) pass
-  int dep_threads = 1024; // threads per deposit workgroup
+  int dep_threads = 512;  // threads per deposit workgroup
   int dep_narrow = 1;     // 32-bit fixed point when provably safe (else 64-bit)
-  int dep_branchfree = 0; // masked footprint loops without lane-divergent branches
+  int dep_xcd = 1;        // consecutive deposit tiles on one XCD (shared L2)
 };
 
 // Device helper: wrap one float64 coordinate into [0, L) with the fixed
