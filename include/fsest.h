@@ -62,6 +62,17 @@ typedef enum {
 
 typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
 
+/* est_config.flags.  Particles are bucket-sorted (4^3-cell buckets) before
+ * the deposit.  By default the sort works in two levels without
+ * device-scope atomics: per-workgroup histograms over super-buckets of
+ * 16^3 buckets, then one workgroup per super-bucket.  That workgroup count
+ * bounds the second level, so for strongly clustered inputs (a large
+ * fraction of all particles inside one 64^3-cell region) this flag selects
+ * the single-level counting sort with device-scope atomics instead.  The
+ * atomic sort is also used whenever batch * (N/64)^3 exceeds 8192.  Both
+ * give identical grids. */
+#define EST_FLAG_ATOMIC_SORT 1
+
 typedef struct {
   int32_t n_grid;        /* N: power of two in [8, 1024]                       */
   int32_t order;         /* p = 1..4: NGP, CIC, TSC, PCS (Sec. 2.3)            */
@@ -69,7 +80,7 @@ typedef struct {
   int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
   double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */
   int64_t max_particles; /* upper bound of n_total per call, 1 .. 2^31-1      */
-  int32_t flags;         /* reserved, must be 0                                */
+  int32_t flags;         /* 0 or EST_FLAG_ATOMIC_SORT (below)                  */
   int32_t reserved;      /* must be 0                                          */
 } est_config;
 
@@ -164,7 +175,7 @@ est_status estimator_graph_launch(est_handle h);
 
 /* Pick this handle's launch shapes (strided-FFT lines per workgroup, P(k)
  * reduction workgroups, deposit workgroup size, 32- or 64-bit fixed-point
- * deposit, branch-free footprint loop) by timing the whole pipeline on the
+ * deposit, deposit tiles grouped per XCD) by timing the whole pipeline on the
  * given input `iters` times per candidate, one parameter at a time.  Returns
  * the chosen combination as an index in [0, 48) in *choice.  Results do not
  * depend on the choice beyond rounding.  Host-synchronising. */

@@ -30,6 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 EST_OK, EST_EINVAL, EST_ENOMEM, EST_ESTATE, EST_EDEVICE, EST_EUNSUPPORTED = range(6)
 EST_F32, EST_F64 = 0, 1
+EST_FLAG_ATOMIC_SORT = 1
 STATUS_NAMES = {0: "EST_OK", 1: "EST_EINVAL", 2: "EST_ENOMEM", 3: "EST_ESTATE",
                 4: "EST_EDEVICE", 5: "EST_EUNSUPPORTED"}
 

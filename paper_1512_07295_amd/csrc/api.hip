@@ -127,7 +127,8 @@ est_status check_config(const est_config* c) {
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return fail(EST_EINVAL, "box must be finite and > 0");
   if (c->max_particles < 1 || c->max_particles > 2147483647LL)
     return fail(EST_EINVAL, "max_particles must be 1..2^31-1");
-  if (c->flags != 0 || c->reserved != 0) return fail(EST_EINVAL, "flags and reserved must be 0");
+  if ((c->flags & ~EST_FLAG_ATOMIC_SORT) != 0 || c->reserved != 0)
+    return fail(EST_EINVAL, "flags must be 0 or EST_FLAG_ATOMIC_SORT and reserved 0");
   if (!pow2(c->n_grid) || c->n_grid < 8 || c->n_grid > 1024)
     return fail(EST_EUNSUPPORTED, "n_grid must be a power of two in [8, 1024] (got %d)", c->n_grid);
   const int64_t nb = c->n_grid / kBucket;
@@ -144,6 +145,11 @@ Geom make_geom(const est_config& c) {
   g.il = c.interlace;
   g.batch = c.batch;
   g.nb = c.n_grid / kBucket;
+  g.fb = g.nb < kFineMax ? g.nb : kFineMax;
+  g.sa = g.nb / g.fb;
+  const int64_t nsup = (int64_t)c.batch * g.sa * g.sa * g.sa;
+  // the two-level sort runs when nsup <= kMaxSuper; a larger value selects the atomic sort
+  g.nsup = ((c.flags & EST_FLAG_ATOMIC_SORT) || nsup > kMaxSuper) ? kMaxSuper + 1 : (int)nsup;
   g.tile = c.n_grid < kTileMax ? c.n_grid : kTileMax;
   g.box = c.box;
   g.inv = (double)c.n_grid / c.box;
@@ -169,7 +175,14 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   bb.cells = (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t));
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
   bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
-  bb.scan_tmp = (uint32_t*)take(((nkeys + 2047) / 2048 + 1) * sizeof(uint32_t));
+  bb.bcnt = (uint32_t*)take(nkeys * sizeof(uint32_t));
+  const bool two_level = g.nsup <= kMaxSuper;
+  bb.tpos = two_level ? take((size_t)c.max_particles * 3 * sizeof(double)) : nullptr;
+  bb.trec = two_level ? (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t)) : nullptr;
+  const size_t nh = two_level ? (size_t)g.nsup * kMaxSortBlocks + 1 : 0;
+  bb.hsup = two_level ? (uint32_t*)take(nh * sizeof(uint32_t)) : nullptr;
+  const size_t nscan = nkeys > nh ? nkeys : nh;
+  bb.scan_tmp = (uint32_t*)take(((nscan + 2047) / 2048 + 1) * sizeof(uint32_t));
   bb.stats = (uint32_t*)take(64 * sizeof(uint32_t));
   bb.tw_n = (float2*)take(n * sizeof(float2));
   bb.tw_nz = (float2*)take((size_t)g.nz * sizeof(float2));

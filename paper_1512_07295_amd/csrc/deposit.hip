@@ -66,21 +66,56 @@ __device__ __forceinline__ int base_cell(double u, int n) {
 }
 
 // ------------------------------------------------------------------ sort
+// Bucket counts and each particle's rank inside its bucket.  A workgroup
+// first counts its particles per bucket key in an LDS hash table (open
+// addressing), then adds each distinct key's count to the global counter
+// with one atomic, whose old value becomes the base of that key's ranks.
+// Particles stored near each other in memory (simulation order) share
+// buckets, so this removes most of the device-scope atomics.
+constexpr int kCountThreads = 1024;
+constexpr int kCountHash = 2048;  // slots, load factor <= 1/2
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
 template <typename TP>
-__global__ __launch_bounds__(256) void k_bucket_count(const TP* __restrict__ pos, int64_t n_total,
-                                                      const int64_t* __restrict__ offsets, Geom g,
-                                                      uint32_t* __restrict__ counts,
-                                                      uint32_t* __restrict__ rank) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_total) return;
-  double x, y, z;
-  load_pos(pos, j, x, y, z);
-  const int mock = mock_of(offsets, g.batch, j);
-  const int bx = base_cell(grid_coord(x, g.box, g.inv), g.n) / kBucket;
-  const int by = base_cell(grid_coord(y, g.box, g.inv), g.n) / kBucket;
-  const int bz = base_cell(grid_coord(z, g.box, g.inv), g.n) / kBucket;
-  const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
-  rank[j] = atomicAdd(&counts[key], 1u);
+__global__ __launch_bounds__(kCountThreads) void k_bucket_count(
+    const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ rank) {
+  __shared__ uint32_t hkey[kCountHash];
+  __shared__ uint32_t hval[kCountHash];
+  for (int i = threadIdx.x; i < kCountHash; i += kCountThreads) {
+    hkey[i] = kEmptyKey;
+    hval[i] = 0u;
+  }
+  const int64_t j = (int64_t)blockIdx.x * kCountThreads + threadIdx.x;
+  uint32_t key = kEmptyKey;
+  if (j < n_total) {
+    double x, y, z;
+    load_pos(pos, j, x, y, z);
+    const int mock = mock_of(offsets, g.batch, j);
+    const int bx = base_cell(grid_coord(x, g.box, g.inv), g.n) / kBucket;
+    const int by = base_cell(grid_coord(y, g.box, g.inv), g.n) / kBucket;
+    const int bz = base_cell(grid_coord(z, g.box, g.inv), g.n) / kBucket;
+    key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
+  }
+  __syncthreads();
+  int slot = 0;
+  uint32_t local = 0;
+  if (key != kEmptyKey) {
+    slot = (int)(key & (kCountHash - 1));
+    while (true) {
+      const uint32_t prev = atomicCAS(&hkey[slot], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) break;
+      slot = (slot + 1) & (kCountHash - 1);
+    }
+    local = atomicAdd(&hval[slot], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCountHash; i += kCountThreads) {
+    const uint32_t k = hkey[i];
+    if (k != kEmptyKey) hval[i] = atomicAdd(&counts[k], hval[i]);
+  }
+  __syncthreads();
+  if (key != kEmptyKey) rank[j] = hval[slot] + local;
 }
 
 // Cell record of one particle, used by the deposit to decide which tiles a
@@ -88,6 +123,10 @@ __global__ __launch_bounds__(256) void k_bucket_count(const TP* __restrict__ pos
 // bits 16a .. 16a+15 hold the first-grid floor cell along axis a (floor(u)
 // for even p, floor(u + 1/2) for odd p; mod N), bit 48 + a holds the step
 // from it to the same floor on the grid shifted by H/2 (0 or 1).
+// bits kRecFineShift.. carry a particle's bucket inside its super-bucket
+// between the two passes of the two-level sort
+constexpr int kRecFineShift = 52;
+
 __device__ __forceinline__ uint64_t cell_record(double ux, double uy, double uz, const Geom& g) {
   const bool even = (g.order % 2) == 0;
   const double u[3] = {ux, uy, uz};
@@ -195,27 +234,40 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t* data, size_
     if (base + i < n) data[base + i] += add;
 }
 
-hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                       int64_t n_total, const Buffers& b, hipStream_t s) {
+__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+static hipError_t scan_in_place(uint32_t* data, size_t n, uint32_t* tmp, uint32_t* maxcount,
+                                hipStream_t s) {
+  const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, data, n, tmp, maxcount);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nblk);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanThreads), 0, s, data, n, tmp);
+  return hipGetLastError();
+}
+
+// Counting sort with device-scope atomics: the general path, used when there
+// are more super-buckets than one workgroup can histogram.
+static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
+                              const int64_t* offsets, int64_t n_total, const Buffers& b,
+                              hipStream_t s) {
   const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
   hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_fill_u32(b.stats, 2, 0u, s)) != hipSuccess) return e;
   const unsigned pblocks = (unsigned)((n_total + 255) / 256);
+  const unsigned cblocks = (unsigned)((n_total + kCountThreads - 1) / kCountThreads);
   if (dt == EST_F32)
-    hipLaunchKernelGGL(k_bucket_count<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
-                       n_total, offsets, g, b.boff, b.rank);
+    hipLaunchKernelGGL(k_bucket_count<float>, dim3(cblocks), dim3(kCountThreads), 0, s,
+                       (const float*)pos, n_total, offsets, g, b.boff, b.rank);
   else
-    hipLaunchKernelGGL(k_bucket_count<double>, dim3(pblocks), dim3(256), 0, s, (const double*)pos,
-                       n_total, offsets, g, b.boff, b.rank);
+    hipLaunchKernelGGL(k_bucket_count<double>, dim3(cblocks), dim3(kCountThreads), 0, s,
+                       (const double*)pos, n_total, offsets, g, b.boff, b.rank);
+  hipLaunchKernelGGL(k_copy_u32, dim3(2048), dim3(256), 0, s, b.boff, b.bcnt, nkeys);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t n = nkeys + 1;
-  const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp,
-                     b.stats);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, b.scan_tmp, nblk);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanThreads), 0, s, b.boff, n, b.scan_tmp);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_in_place(b.boff, nkeys + 1, b.scan_tmp, b.stats, s)) != hipSuccess) return e;
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
                        n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells);
@@ -224,6 +276,181 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
                        (const double*)pos, n_total, offsets, g, b.boff, b.rank,
                        (double*)b.sorted, b.cells);
   return hipGetLastError();
+}
+
+// ---- two-level sort without device-scope atomics
+// Super-buckets are cubes of g.fb^3 buckets (g.nsup of them).  (A) each of
+// nblk workgroups histograms a contiguous chunk of particles over the
+// super-buckets in LDS; (B) the histograms, laid out super-major, are
+// scanned, giving every (super-bucket, workgroup) pair its output offset;
+// (C) each workgroup re-reads its chunk and moves every particle (position
+// and cell record) into its super-bucket segment, ranking with LDS
+// counters; (D) one workgroup per super-bucket counts its particles per
+// bucket, writes the bucket offsets and counts, and moves the particles into
+// bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
+// the deposit splits its bucket runs at super-bucket boundaries.
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
+                                                 int& bx, int& by, int& bz) {
+  bx = base_cell(ux, g.n) / kBucket;
+  by = base_cell(uy, g.n) / kBucket;
+  bz = base_cell(uz, g.n) / kBucket;
+}
+
+__device__ __forceinline__ int super_of(int mock, int bx, int by, int bz, const Geom& g) {
+  return ((mock * g.sa + bx / g.fb) * g.sa + by / g.fb) * g.sa + bz / g.fb;
+}
+
+template <typename TP>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict__ pos,
+                                                            int64_t n_total,
+                                                            const int64_t* __restrict__ offsets,
+                                                            Geom g, int64_t chunk, int nblk,
+                                                            uint32_t* __restrict__ hsup) {
+  __shared__ uint32_t hist[kMaxSuper];
+  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads) hist[i] = 0u;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk;
+  const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
+    double x, y, z;
+    load_pos(pos, j, x, y, z);
+    int bx, by, bz;
+    particle_buckets(grid_coord(x, g.box, g.inv), grid_coord(y, g.box, g.inv),
+                     grid_coord(z, g.box, g.inv), g, bx, by, bz);
+    atomicAdd(&hist[super_of(mock_of(offsets, g.batch, j), bx, by, bz, g)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
+    hsup[(int64_t)i * nblk + blockIdx.x] = hist[i];
+}
+
+template <typename TP>
+__global__ __launch_bounds__(kSortThreads) void k_sort_super(
+    const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
+    int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ tpos,
+    uint64_t* __restrict__ trec) {
+  __shared__ uint32_t cur[kMaxSuper];
+  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
+    cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * chunk;
+  const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
+    const TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+    const double ux = grid_coord((double)px, g.box, g.inv);
+    const double uy = grid_coord((double)py, g.box, g.inv);
+    const double uz = grid_coord((double)pz, g.box, g.inv);
+    int bx, by, bz;
+    particle_buckets(ux, uy, uz, g, bx, by, bz);
+    const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
+    const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
+    const uint32_t p = atomicAdd(&cur[sup], 1u);
+    tpos[3 * (int64_t)p + 0] = px;
+    tpos[3 * (int64_t)p + 1] = py;
+    tpos[3 * (int64_t)p + 2] = pz;
+    trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
+  }
+}
+
+template <typename TP>
+__global__ __launch_bounds__(kSortThreads) void k_sort_fine(
+    const TP* __restrict__ tpos, const uint64_t* __restrict__ trec, int64_t n_total, Geom g,
+    int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ sorted,
+    uint64_t* __restrict__ cells, uint32_t* __restrict__ boff, uint32_t* __restrict__ bcnt,
+    uint32_t* __restrict__ stats) {
+  constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
+  __shared__ uint32_t hist[kFineMax * kFineMax * kFineMax];
+  __shared__ uint32_t wtot[kSortThreads / 64];
+  const int sup = blockIdx.x;
+  const int nf = g.fb * g.fb * g.fb;
+  const uint32_t seg0 = hoff[(int64_t)sup * nblk];
+  const uint32_t seg1 = (sup + 1 < g.nsup) ? hoff[(int64_t)(sup + 1) * nblk] : (uint32_t)n_total;
+  for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
+  __syncthreads();
+  for (uint32_t i = seg0 + threadIdx.x; i < seg1; i += kSortThreads)
+    atomicAdd(&hist[(uint32_t)(trec[i] >> kRecFineShift)], 1u);
+  __syncthreads();
+  // exclusive scan of hist[0, nf): kPer consecutive buckets per thread
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint32_t c[kPer], run = 0, mx = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int f = t * kPer + q;
+    c[q] = (f < nf) ? hist[f] : 0u;
+    mx = max(mx, c[q]);
+    run += c[q];
+  }
+  uint32_t incl = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) wtot[wave] = incl;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, o, 64));
+  if (lane == 0) atomicMax(&stats[0], mx);
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wtot[w];
+  uint32_t start = seg0 + before + incl - run;
+  // bucket offsets and counts, in global key order
+  const int ms = sup / (g.sa * g.sa * g.sa), srem = sup % (g.sa * g.sa * g.sa);
+  const int sx = srem / (g.sa * g.sa), sy = (srem / g.sa) % g.sa, sz = srem % g.sa;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int f = t * kPer + q;
+    if (f < nf) {
+      const int fx = f / (g.fb * g.fb), fy = (f / g.fb) % g.fb, fz = f % g.fb;
+      const int64_t key = (((int64_t)ms * g.nb + sx * g.fb + fx) * g.nb + sy * g.fb + fy) * g.nb +
+                          sz * g.fb + fz;
+      boff[key] = start;
+      bcnt[key] = c[q];
+      hist[f] = start - seg0;
+    }
+    start += c[q];
+  }
+  __syncthreads();
+  for (uint32_t i = seg0 + threadIdx.x; i < seg1; i += kSortThreads) {
+    const uint64_t r = trec[i];
+    const uint32_t p = seg0 + atomicAdd(&hist[(uint32_t)(r >> kRecFineShift)], 1u);
+    sorted[3 * (int64_t)p + 0] = tpos[3 * (int64_t)i + 0];
+    sorted[3 * (int64_t)p + 1] = tpos[3 * (int64_t)i + 1];
+    sorted[3 * (int64_t)p + 2] = tpos[3 * (int64_t)i + 2];
+    cells[p] = r & ((1ull << kRecFineShift) - 1ull);
+  }
+}
+
+template <typename TP>
+static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* offsets,
+                                 int64_t n_total, const Buffers& b, hipStream_t s) {
+  int nblk = (int)((n_total + 4095) / 4096);
+  if (nblk > kMaxSortBlocks) nblk = kMaxSortBlocks;
+  const int64_t chunk = (n_total + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_sort_hist<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
+                     offsets, g, chunk, nblk, b.hsup);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the scan's largest-entry output is not a bucket count here
+  if ((e = scan_in_place(b.hsup, (size_t)g.nsup * nblk, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
+                     offsets, g, chunk, nblk, b.hsup, (TP*)b.tpos, b.trec);
+  hipLaunchKernelGGL(k_sort_fine<TP>, dim3(g.nsup), dim3(kSortThreads), 0, s, (const TP*)b.tpos,
+                     b.trec, n_total, g, nblk, b.hsup, (TP*)b.sorted, b.cells, b.boff, b.bcnt,
+                     b.stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
+                       int64_t n_total, const Buffers& b, hipStream_t s) {
+  hipError_t e = launch_fill_u32(b.stats, 4, 0u, s);
+  if (e != hipSuccess) return e;
+  if (g.nsup > kMaxSuper) return sort_atomic(g, pos, dt, offsets, n_total, b, s);
+  if (dt == EST_F32) return sort_two_level(g, (const float*)pos, offsets, n_total, b, s);
+  return sort_two_level(g, (const double*)pos, offsets, n_total, b, s);
 }
 
 // ------------------------------------------------------------------ stencils
@@ -482,7 +709,8 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 template <int P, bool IL, typename TP, bool WIDE, bool PERIODIC>
 __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
                                                   const uint64_t* __restrict__ cells,
-                                                  const uint32_t* __restrict__ boff, float* grid,
+                                                  const uint32_t* __restrict__ boff,
+                                                  const uint32_t* __restrict__ bcnt, float* grid,
                                                   Geom g, uint32_t* __restrict__ stats,
                                                   int exclusive, int dynamic, int xcd) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
@@ -542,20 +770,23 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     const int ncomb = cnt * cnt;  // <= 36
     const int64_t mbase = (int64_t)mock * nb * nb * nb;
     if (wave == 0) {
+      // a column's run of cnt buckets in z is contiguous in memory except
+      // where it crosses a super-bucket edge (every g.fb buckets, which
+      // includes the periodic wrap): at most two pieces
       uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
       if (lane < ncomb) {
         const int ix = lane / cnt, iy = lane % cnt;
         const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
         const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
-        const int z1 = b0z + cnt;  // exclusive end, may exceed nb (wrap)
-        if (z1 <= nb) {
-          s0 = boff[row + b0z];
-          e0 = boff[row + z1];
-        } else {
-          s0 = boff[row + b0z];
-          e0 = boff[row + nb];
-          s1 = boff[row];
-          e1 = boff[row + (z1 - nb)];
+        const int z1 = b0z + cnt;                       // exclusive end, may pass nb
+        const int zs = (b0z / g.fb + 1) * g.fb;         // next super-bucket edge
+        const int za = z1 < zs ? z1 : zs;               // end of the first piece
+        s0 = boff[row + b0z];
+        e0 = boff[row + za - 1] + bcnt[row + za - 1];
+        if (z1 > zs) {
+          const int zb = zs % nb, ze = zb + (z1 - zs);
+          s1 = boff[row + zb];
+          e1 = boff[row + ze - 1] + bcnt[row + ze - 1];
         }
       }
       // exclusive prefix of the per-lane lengths across the wave
@@ -805,14 +1036,14 @@ static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool na
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   if (narrow)
     hipLaunchKernelGGL((k_deposit<P, IL, TP, false, PER>), dim3((unsigned)ntiles), dim3(threads),
-                       0, s, (const TP*)b.sorted, b.cells, b.boff, (float*)b.grid, g, b.stats, 0,
+                       0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0,
                        0, xcd ? 1 : 0);
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
   const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
   hipLaunchKernelGGL((k_deposit<P, IL, TP, true, PER>), dim3(wblocks), dim3(threads), 0, s,
-                     (const TP*)b.sorted, b.cells, b.boff, (float*)b.grid, g, b.stats,
+                     (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats,
                      narrow ? 0 : 1, 1, 0);
 }
 

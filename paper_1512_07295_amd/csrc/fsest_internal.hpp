@@ -13,6 +13,9 @@ constexpr int kBucket = 4;      // bucket edge in cells (particles sorted by buc
 constexpr int kTileMax = 16;    // deposit tile edge in cells (LDS-resident)
 constexpr int kMaxBins = 512;   // largest n_bins (N / 2 at N = 1024)
 constexpr int kMaxBinBlocks = 2048;  // upper bound of P(k) reduction blocks per set
+constexpr int kFineMax = 16;    // buckets per super-bucket edge (two-level sort)
+constexpr int kMaxSuper = 8192; // super-buckets one workgroup histograms in LDS
+constexpr int kMaxSortBlocks = 1024;  // workgroups of the super-bucket passes
 
 // Geometry and per-call constants that device code needs.
 struct Geom {
@@ -23,6 +26,9 @@ struct Geom {
   int batch;
   int nb;         // buckets per axis = N / kBucket
   int tile;       // deposit tile edge
+  int fb;         // buckets per super-bucket edge: min(kFineMax, nb)
+  int sa;         // super-buckets per axis: nb / fb
+  int nsup;       // batch * sa^3 (two-level sort when <= kMaxSuper)
   double box;     // L
   double inv;     // fl64(N / L)
   int64_t ps;     // complex elements between consecutive x planes: N*nz plus
@@ -46,7 +52,11 @@ struct Buffers {
   void* sorted;            // max_particles * 3 * 8 bytes
   uint64_t* cells;         // max_particles cell records (sorted order)
   uint32_t* rank;          // max_particles
-  uint32_t* boff;          // batch * nb^3 + 1 bucket offsets
+  uint32_t* boff;          // batch * nb^3 + 1 bucket start offsets (key order)
+  uint32_t* bcnt;          // batch * nb^3 bucket counts
+  void* tpos;              // max_particles * 3 * 8 bytes: positions in super-bucket order
+  uint64_t* trec;          // max_particles cell records in super-bucket order
+  uint32_t* hsup;          // kMaxSuper * kMaxSortBlocks + 1 histogram / offsets
   uint32_t* scan_tmp;      // scan block sums
   uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter
   float2* tw_n;            // exp(-2 pi i n / N)

@@ -8,7 +8,7 @@ estimator runs in the HIP kernels of ``libfsest.so``.
 import numpy as np
 import torch
 
-from . import (EST_F32, EST_F64, estimator_autotune, estimator_backward, estimator_bispectrum,
+from . import (EST_F32, EST_F64, EST_FLAG_ATOMIC_SORT, estimator_autotune, estimator_backward, estimator_bispectrum,
                estimator_bispectrum_workspace_bytes, estimator_copy_grid, estimator_create,
                estimator_deposit, estimator_destroy, estimator_graph_capture,
                estimator_graph_launch, estimator_power, estimator_sample_delta, estimator_set_launch,
@@ -40,14 +40,15 @@ class Estimator:
     """One handle: grid size N, box L, order p, interlacing, batch of sets."""
 
     def __init__(self, n_grid, box, order=4, interlace=True, batch=1, max_particles=1 << 20,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, atomic_sort=False):
         self.n_grid = int(n_grid)
         self.box = float(box)
         self.order = int(order)
         self.interlace = bool(interlace)
         self.batch = int(batch)
         self.device = torch.device(device)
-        self.cfg = make_config(n_grid, box, order, int(interlace), batch, max_particles)
+        self.cfg = make_config(n_grid, box, order, int(interlace), batch, max_particles,
+                               EST_FLAG_ATOMIC_SORT if atomic_sort else 0)
         self.ws_bytes = estimator_workspace_bytes(self.cfg)
         self._ws, self._ws_ptr = _aligned_workspace(self.ws_bytes, self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)

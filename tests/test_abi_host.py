@@ -64,7 +64,8 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(box=float("nan")), fsest.EST_EINVAL),
     (dict(max_particles=0), fsest.EST_EINVAL),
     (dict(max_particles=1 << 31), fsest.EST_EINVAL),
-    (dict(flags=1), fsest.EST_EINVAL),
+    (dict(flags=2), fsest.EST_EINVAL),
+    (dict(flags=-1), fsest.EST_EINVAL),
     (dict(n_grid=100), fsest.EST_EUNSUPPORTED),
     (dict(n_grid=4), fsest.EST_EUNSUPPORTED),
     (dict(n_grid=2048), fsest.EST_EUNSUPPORTED),
@@ -126,3 +127,12 @@ def test_package_binds_to_one_hip_runtime():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_atomic_sort_flag_accepted_and_drops_two_level_buffers():
+    """EST_FLAG_ATOMIC_SORT is a valid flag; the atomic sort needs no
+    super-bucket staging buffers, so its workspace is smaller."""
+    two = fsest.estimator_workspace_bytes(_cfg(n_grid=64, max_particles=1 << 16))
+    one = fsest.estimator_workspace_bytes(_cfg(n_grid=64, max_particles=1 << 16,
+                                               flags=fsest.EST_FLAG_ATOMIC_SORT))
+    assert one < two

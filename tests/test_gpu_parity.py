@@ -243,7 +243,7 @@ def test_call_order_errors(torch):
 @pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 7, 13, 24, 47])
 def test_every_launch_variant_matches_oracle(torch, choice):
     """Each autotuner candidate (FFT lines per workgroup, reduction blocks,
-    deposit workgroup size, 32/64-bit fixed point, branch-free loop)."""
+    deposit workgroup size, 32/64-bit fixed point, tiles grouped per XCD)."""
     box, n = 300.0, 32
     pos = synth.zeldovich(16, box, 11, dtype=np.float32)
     est = _est(torch, n, box, 4, True, maxp=len(pos))
@@ -288,3 +288,32 @@ def test_deposit_is_bitwise_reproducible(torch):
         assert np.array_equal(est.copy_grid(1).cpu().numpy(), a)
         assert np.array_equal(est.copy_grid(2).cpu().numpy(), b)
     est.close()
+
+
+@pytest.mark.parametrize("n,batch", [(16, 1), (64, 1), (128, 1), (128, 3)])
+def test_two_level_and_atomic_sorts_give_identical_grids(torch, n, batch):
+    """The default two-level bucket sort (super-buckets of 16^3 buckets) and
+    the counting sort with device-scope atomics order particles differently
+    inside buckets, but integer fixed-point sums make the grids bitwise
+    equal; both match the oracle."""
+    from paper_1512_07295_amd.estimator import Estimator
+    box = 500.0
+    if batch == 1:
+        pos = synth.zeldovich(32, box, 13, dtype=np.float32)
+        offs = None
+    else:
+        pos, offs = synth.mocks(batch, box, 31, n_min=2000, n_max=40000)
+    grids = []
+    for atomic in (False, True):
+        est = Estimator(n, box, 4, True, batch, len(pos), atomic_sort=atomic)
+        est.deposit(to_dev(torch, pos), offsets=None if offs is None else to_dev(torch, offs))
+        grids.append([est.copy_grid(w, m).cpu().numpy().copy()
+                      for m in range(batch) for w in (1, 2)])
+        est.close()
+    for a, b in zip(*grids):
+        assert np.array_equal(a, b)
+    s0 = 0 if offs is None else int(offs[0])
+    s1 = len(pos) if offs is None else int(offs[1])
+    r1, r2 = assign.deposit(pos[s0:s1], box, n, 4, True)
+    assert np.max(np.abs(grids[0][0] - r1)) <= 2e-6 * r1.max()
+    assert np.max(np.abs(grids[0][1] - r2)) <= 2e-6 * r2.max()
