@@ -290,6 +290,7 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
 // bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
 // the deposit splits its bucket runs at super-bucket boundaries.
 constexpr int kSortThreads = 1024;
+constexpr int kSortBatch = 1;  // particles per thread handled together (loads in flight together)
 
 __device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
                                                  int& bx, int& by, int& bz) {
@@ -313,13 +314,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
-    double x, y, z;
-    load_pos(pos, j, x, y, z);
-    int bx, by, bz;
-    particle_buckets(grid_coord(x, g.box, g.inv), grid_coord(y, g.box, g.inv),
-                     grid_coord(z, g.box, g.inv), g, bx, by, bz);
-    atomicAdd(&hist[super_of(mock_of(offsets, g.batch, j), bx, by, bz, g)], 1u);
+  // kSortBatch particles per thread at a time, their loads issued together
+  for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
+    double x[kSortBatch], y[kSortBatch], z[kSortBatch];
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const int64_t j = jb + (int64_t)q * kSortThreads;
+      if (j < j1) load_pos(pos, j, x[q], y[q], z[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const int64_t j = jb + (int64_t)q * kSortThreads;
+      if (j < j1) {
+        int bx, by, bz;
+        particle_buckets(grid_coord(x[q], g.box, g.inv), grid_coord(y[q], g.box, g.inv),
+                         grid_coord(z[q], g.box, g.inv), g, bx, by, bz);
+        atomicAdd(&hist[super_of(mock_of(offsets, g.batch, j), bx, by, bz, g)], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
@@ -337,20 +349,35 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
-    const TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-    const double ux = grid_coord((double)px, g.box, g.inv);
-    const double uy = grid_coord((double)py, g.box, g.inv);
-    const double uz = grid_coord((double)pz, g.box, g.inv);
-    int bx, by, bz;
-    particle_buckets(ux, uy, uz, g, bx, by, bz);
-    const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
-    const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
-    const uint32_t p = atomicAdd(&cur[sup], 1u);
-    tpos[3 * (int64_t)p + 0] = px;
-    tpos[3 * (int64_t)p + 1] = py;
-    tpos[3 * (int64_t)p + 2] = pz;
-    trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
+  for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
+    TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const int64_t j = jb + (int64_t)q * kSortThreads;
+      if (j < j1) {
+        px[q] = pos[3 * j + 0];
+        py[q] = pos[3 * j + 1];
+        pz[q] = pos[3 * j + 2];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const int64_t j = jb + (int64_t)q * kSortThreads;
+      if (j < j1) {
+        const double ux = grid_coord((double)px[q], g.box, g.inv);
+        const double uy = grid_coord((double)py[q], g.box, g.inv);
+        const double uz = grid_coord((double)pz[q], g.box, g.inv);
+        int bx, by, bz;
+        particle_buckets(ux, uy, uz, g, bx, by, bz);
+        const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
+        const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
+        const uint32_t p = atomicAdd(&cur[sup], 1u);
+        tpos[3 * (int64_t)p + 0] = px[q];
+        tpos[3 * (int64_t)p + 1] = py[q];
+        tpos[3 * (int64_t)p + 2] = pz[q];
+        trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
+      }
+    }
   }
 }
 
@@ -369,8 +396,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   const uint32_t seg1 = (sup + 1 < g.nsup) ? hoff[(int64_t)(sup + 1) * nblk] : (uint32_t)n_total;
   for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
   __syncthreads();
-  for (uint32_t i = seg0 + threadIdx.x; i < seg1; i += kSortThreads)
-    atomicAdd(&hist[(uint32_t)(trec[i] >> kRecFineShift)], 1u);
+  for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
+    uint64_t r[kSortBatch];
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const uint32_t i = ib + q * kSortThreads;
+      r[q] = (i < seg1) ? trec[i] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q)
+      if (ib + q * kSortThreads < seg1) atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
+  }
   __syncthreads();
   // exclusive scan of hist[0, nf): kPer consecutive buckets per thread
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -413,13 +449,29 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
     start += c[q];
   }
   __syncthreads();
-  for (uint32_t i = seg0 + threadIdx.x; i < seg1; i += kSortThreads) {
-    const uint64_t r = trec[i];
-    const uint32_t p = seg0 + atomicAdd(&hist[(uint32_t)(r >> kRecFineShift)], 1u);
-    sorted[3 * (int64_t)p + 0] = tpos[3 * (int64_t)i + 0];
-    sorted[3 * (int64_t)p + 1] = tpos[3 * (int64_t)i + 1];
-    sorted[3 * (int64_t)p + 2] = tpos[3 * (int64_t)i + 2];
-    cells[p] = r & ((1ull << kRecFineShift) - 1ull);
+  for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
+    uint64_t r[kSortBatch];
+    TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      const uint32_t i = ib + q * kSortThreads;
+      if (i < seg1) {
+        r[q] = trec[i];
+        px[q] = tpos[3 * (int64_t)i + 0];
+        py[q] = tpos[3 * (int64_t)i + 1];
+        pz[q] = tpos[3 * (int64_t)i + 2];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSortBatch; ++q) {
+      if (ib + q * kSortThreads < seg1) {
+        const uint32_t p = seg0 + atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
+        sorted[3 * (int64_t)p + 0] = px[q];
+        sorted[3 * (int64_t)p + 1] = py[q];
+        sorted[3 * (int64_t)p + 2] = pz[q];
+        cells[p] = r[q] & ((1ull << kRecFineShift) - 1ull);
+      }
+    }
   }
 }
 
