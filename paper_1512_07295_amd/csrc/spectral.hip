@@ -95,6 +95,18 @@ __device__ __forceinline__ float2 combined_mode(float2 za, float2 zb, int mx, in
   }
 }
 
+// |K C(m)|^2 from the pair (Za, Zb) = (Z(k), Z(-k)) and the phase ph of
+// combined_mode: with a = Za, b = conj(Zb), 2 F1 = a + b and 2 F2 = (a - b)/i,
+// so (cx, cy) = 2 (F1 + ph F2).  The interlaced combination is
+// C = (F1 + ph F2)/2 (K = 4); the packed real grid's is C = F1 + ph F2 (K = 2).
+__device__ __forceinline__ float pair_power(float2 za, float2 zb, float2 ph) {
+  const float sx = za.x + zb.x, sy = za.y - zb.y;
+  const float dx = za.x - zb.x, dy = za.y + zb.y;
+  const float cx = sx + (ph.x * dy + ph.y * dx);
+  const float cy = sy + (ph.y * dy - ph.x * dx);
+  return cx * cx + cy * cy;
+}
+
 template <int L>
 struct PairShape {
   static constexpr int TPL = LinePlan<L>::TPL;
@@ -116,6 +128,8 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   constexpr int EPT = LinePlan<L>::EPT;
   __shared__ float2 rows[2 * PPB * ROWP];
   __shared__ double hist[kMaxBins];
+  // per half-space z index: the z part of the phase and 1/W^2
+  __shared__ float4 ztab[MODE != 2 ? kMaxBins + 1 : 1];
 
   const int n = g.n;
   const int mock = blockIdx.y;
@@ -127,8 +141,14 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   float2* own_lds = rows + (2 * ps + r) * ROWP;
   const float2* par_lds = rows + (2 * ps + (r ^ 1)) * ROWP;
 
-  if constexpr (MODE != 2)
+  if constexpr (MODE != 2) {
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
+    for (int i = threadIdx.x; i <= n / 2; i += blockDim.x) {
+      // interlaced: exp(+i pi mz/N); packed: exp(-2 pi i mz/N)
+      const float2 ph = IL ? phase[i] : cconj(phase[(2 * i) & (2 * n - 1)]);
+      ztab[i] = make_float4(ph.x, ph.y, inv_w2[i], 0.0f);
+    }
+  }
 
   for (int64_t pg = blockIdx.x; pg < ngroups; pg += gridDim.x) {
     const int64_t q = pg * PPB + ps;
@@ -148,40 +168,55 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     const int mxr = signed_freq(xr, n), myr = signed_freq(yr, n);
     if constexpr (MODE != 2) {
       if (valid && !(r == 1 && self)) {
+        // this thread's run of half-space z indices; the shell index only
+        // grows along it, so it advances by comparing 4|m|^2 with the next
+        // shell's lower edge ((2b+1) n_dk)^2 (same rule as shell_of)
         const int nm = n / 2 + 1;
         const int per = (nm + TPL - 1) / TPL;
         const int z0 = t * per;
         const int z1 = min(z0 + per, nm);
-        const float wxy = inv_w2[xr] * inv_w2[yr];
-        const int r2 = mxr * mxr + myr * myr;
-        int cur_b = -1;
-        float cur = 0.0f;
-        for (int mz = z0; mz < z1; ++mz) {
-          const int m2 = r2 + mz * mz;
-          if (m2 == 0) continue;
-          const int b = shell_of(m2, n_dk);
-          if (b < 1 || b > n_bins) continue;
-          float2 za, zb;
-          if constexpr (IL) {
-            za = own_lds[lds_index<1>(mz)];
-            zb = par_lds[lds_index<1>((n - mz) & (n - 1))];
-          } else {
-            const int h = n / 2;
-            const int kz = mz & (h - 1);
-            za = own_lds[lds_index<1>(kz)];
-            zb = par_lds[lds_index<1>((h - kz) & (h - 1))];
+        if (z0 < z1) {
+          const float wxy = inv_w2[xr] * inv_w2[yr] * (IL ? 0.0625f : 0.25f);
+          const float2 ph_xy = IL ? phase[(mxr + myr) & (2 * n - 1)] : make_float2(1.0f, 0.0f);
+          const int r2 = mxr * mxr + myr * myr;
+          const int m2_0 = r2 + z0 * z0;
+          int b = m2_0 ? shell_of(m2_0, n_dk) : 0;
+          int edge = (2 * b + 1) * n_dk;
+          edge *= edge;
+          int cur_b = -1;
+          float cur = 0.0f;
+          for (int mz = z0; mz < z1; ++mz) {
+            const int m4 = 4 * (r2 + mz * mz);
+            while (edge <= m4) {
+              ++b;
+              edge = (2 * b + 1) * n_dk;
+              edge *= edge;
+            }
+            if (b > n_bins) break;
+            if (b < 1) continue;  // below the first shell (and the k = 0 mode)
+            float2 za, zb;
+            if constexpr (IL) {
+              za = own_lds[lds_index<1>(mz)];
+              zb = par_lds[lds_index<1>((n - mz) & (n - 1))];
+            } else {
+              const int h = n / 2;
+              const int kz = mz & (h - 1);
+              za = own_lds[lds_index<1>(kz)];
+              zb = par_lds[lds_index<1>((h - kz) & (h - 1))];
+            }
+            const float4 zt = ztab[mz];
+            const float2 ph = IL ? cmul(ph_xy, make_float2(zt.x, zt.y)) : make_float2(zt.x, zt.y);
+            const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
+            const float val = wgt * pair_power(za, zb, ph) * zt.z;
+            if (b != cur_b) {
+              if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)(cur * wxy));
+              cur_b = b;
+              cur = 0.0f;
+            }
+            cur += val;
           }
-          const float2 c = combined_mode<IL>(za, zb, mxr, myr, mz, phase, n);
-          const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
-          const float val = wgt * (c.x * c.x + c.y * c.y) * wxy * inv_w2[mz];
-          if (b != cur_b) {
-            if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)cur);
-            cur_b = b;
-            cur = 0.0f;
-          }
-          cur += val;
+          if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)(cur * wxy));
         }
-        if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)cur);
       }
       __syncthreads();
     } else {
