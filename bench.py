@@ -219,6 +219,69 @@ def fwd_bwd(args, torch, F, est_mod, synth):
                        "n_particles": npart}}
 
 
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+def direct_leg(args, torch, est_mod, synth):
+    """Direct summation delta_DS (eq. deltaDS) of 64^3 Zel'dovich particles
+    over every half-spectrum mode of a 64^3 grid; ALU-bound.  Algorithmic
+    work per (particle, mode) term: one complex multiply and one complex add,
+    8 flops, against the FP32 vector peak."""
+    box, n, n_side = 500.0, 64, 64
+    pos = torch.as_tensor(synth.zeldovich(n_side, box, 12, dtype=np.float32), device="cuda")
+    npart = pos.shape[0]
+    est = est_mod.Estimator(n, box, 4, True, 1, npart)
+    terms = npart * n * n * (n // 2 + 1)
+    for _ in range(max(1, args.warmup // 2)):
+        est.direct_delta(pos)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        est.direct_delta(pos)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    est.close()
+    tflops = 8.0 * terms / dt / 1e12
+    log("direct sum: %.2f ms per call, %.3g terms/s" % (1e3 * dt, terms / dt))
+    return {"value": round(terms / dt / 1e9, 2), "unit": "Gterms/s", "ms_per_call": round(1e3 * dt, 3),
+            "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+                         "traffic": None, "flops_per_term": 8},
+            "config": {"workload": "delta_DS of 64^3 Zel'dovich particles (L=500) at every "
+                                   "half-spectrum mode of a 64^3 grid",
+                       "n_particles": npart, "terms": terms}}
+
+
+def bias_experiment(torch, est_mod, synth, n_side=192, n=128, box=1000.0):
+    """Sec. 3.2 on synthetic Zel'dovich particles: |P_G/P_DS - 1| and
+    |P_{G-DS}/P_DS - 1| per shell for p = 1..4 with and without interlacing,
+    P_DS from the GPU direct sum (one JSON line per configuration)."""
+    pos = torch.as_tensor(synth.zeldovich(n_side, box, 50, dtype=np.float32), device="cuda")
+    est = est_mod.Estimator(n, box, 4, True, 1, pos.shape[0])
+    t0 = time.perf_counter()
+    dds = est.direct_delta(pos)
+    log("bias: direct sum of %d particles on %d^3 modes in %.1f s" % (pos.shape[0], n, time.perf_counter() - t0))
+    k, p_ds, nm = est.spectrum_power(dds)
+    p_ds = p_ds.cpu().numpy()
+    k_n = np.pi * n / box
+    for order in (1, 2, 3, 4):
+        for il in (False, True):
+            e = est_mod.Estimator(n, box, order, il, 1, pos.shape[0])
+            e.deposit(pos)
+            e.transform()
+            dg = e.export_delta()
+            _, p_g, _ = e.spectrum_power(dg)
+            _, p_x, _ = e.spectrum_power(dg, dds)
+            e.close()
+            print(json.dumps({"order": order, "interlace": il,
+                              "k_over_kN": [round(float(v) / k_n, 4) for v in k.cpu().numpy()],
+                              "abs_PG_over_PDS_m1": [float("%.3g" % v) for v in np.abs(p_g.cpu().numpy() / p_ds - 1)],
+                              "abs_PGDS_over_PDS_m1": [float("%.3g" % v) for v in np.abs(p_x.cpu().numpy() / p_ds - 1)]}),
+                  flush=True)
+    est.close()
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample: the same kind of workload at 1/64 size."""
     import oracle
@@ -248,6 +311,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-choice", type=int, default=None,
                     help="headline launch shapes (0..47) instead of autotuning them")
+    ap.add_argument("--bias", action="store_true",
+                    help="only run the aliasing comparison against direct summation (Sec. 3.2)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -272,11 +337,16 @@ def main():
     from paper_1512_07295_amd import estimator as est_mod
     import synth
 
+    if args.bias:
+        bias_experiment(torch, est_mod, synth)
+        return
+
     head = headline(args, torch, F, est_mod, synth)
     extra = {}
     if not args.no_extra:
         extra["batched"] = batched(args, torch, F, est_mod, synth)
         extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth)
+        extra["direct_sum"] = direct_leg(args, torch, est_mod, synth)
     out = {
         "metric": "Mparticles/s end-to-end P(k), PCS+interlace 1024^3 grid; fwd+bwd & batched vs plain",
         "value": round(head["value"], 2),

@@ -202,6 +202,50 @@ est_status estimator_sample_delta(est_handle h, int32_t mock,
                                   const int32_t* modes, int64_t n,
                                   double* out);
 
+/* ---- Direct summation and half-spectrum statistics (Sec. 2.2; Sec. 3.2,
+ * comparison to direct summation).  A half spectrum is a device float64
+ * array [N][N][N/2+1][2] (re, im): entry (ix, iy, m_z) holds the mode
+ * (m_x, m_y, m_z) with m = ix for ix <= N/2 and ix - N otherwise (index N/2
+ * is +N/2), the same for y, and m_z = 0 .. N/2. */
+
+/* Bytes of device workspace estimator_direct_delta needs for n particles
+ * (the handle's N).  Host only. */
+est_status estimator_direct_workspace_bytes(est_handle h, int64_t n,
+                                            size_t* bytes);
+
+/* Alias-free Fourier density by direct summation (eq. deltaDS):
+ * delta_DS(m) = n^-1 sum_j exp(-2 pi i m . x_j / L) at every mode of the
+ * handle's half spectrum, for the n positions pos (device, [n][3] float32 or
+ * float64, wrapped into [0, L) like the deposit), written to out (device
+ * half spectrum).  dws: caller-owned device workspace of
+ * estimator_direct_workspace_bytes(h, n) bytes, 256-byte aligned.  Each
+ * position is reduced to 32-bit fixed-point phases (error < 2^-32 turns per
+ * unit of m); terms are summed in FP32 per chunk of 256 particles and in
+ * FP64 across chunks.  Cost N_P N^3 / 2 terms (ALU-bound).  Independent of
+ * the handle's deposit state. */
+est_status estimator_direct_delta(est_handle h, const void* pos,
+                                  est_dtype dtype, int64_t n, void* dws,
+                                  size_t dws_bytes, double* out);
+
+/* The estimator's delta(m) = C(m) / (N_P W(m)) (eqs. intdelta,
+ * windowcorrection; normalised like the direct sum) of set `mock` at every
+ * half-spectrum mode, into out (device half spectrum).  Needs
+ * estimator_transform first; brings the handle to the full-spectrum state. */
+est_status estimator_export_delta(est_handle h, int32_t mock, double* out);
+
+/* Shell statistics of two half spectra a, b (device; b may be NULL for
+ * b = a): P_b = V sum_{m in shell b} w Re(a(m) b*(m)) / N_b - shot, with the
+ * shells, half-spectrum weights w and mode counts of estimator_power (eq. ps).
+ * With a = b = delta_DS this is the direct-summation estimator of Sec. 2.2
+ * (shot noise V / N_P when shot is set to it); with a = delta_G and
+ * b = delta_DS the cross spectrum P_{G-DS} used to measure aliasing in
+ * Sec. 3.2.  Outputs
+ * k (mean |k| per shell), p, nmodes: device [n_bins]. */
+est_status estimator_spectrum_power(est_handle h, const double* a,
+                                    const double* b, int32_t n_dk,
+                                    int32_t n_bins, double shot, double* k,
+                                    double* p, int64_t* nmodes);
+
 /* Per-kernel-group timing (tracing).  enable = 1 clears the accumulators
  * and from then on brackets every kernel group a call launches (bucket sort,
  * deposit, each FFT pass, the fused P(k) pass, ...) with HIP events on the

@@ -7,11 +7,14 @@ Test infrastructure only (see ``oracle/__init__.py``).
 * ``footprint_dft``: the DFT of a deposited grid evaluated particle by
   particle, F(m) = sum_j prod_i sum_t w_{j,i,t} exp(-2 pi i m_i c_{j,i,t}/N),
   with no grid and no FFT (separability of the kernel, Sec. 2.3).
+* ``delta_half_direct``: delta_DS at every mode of the half spectrum (the
+  layout of ``spectrum.half_axes``), the alias-free reference of Sec. 3.2.
 """
 
 import numpy as np
 
-from .assign import grid_coords, stencil
+from .assign import grid_coords, stencil, wrap
+from .spectrum import signed_index
 
 
 def delta_direct(pos, box, modes, chunk=1 << 16):
@@ -49,3 +52,25 @@ def footprint_dft(pos, box, n_grid, p, modes, shift=0.0, chunk=1 << 21):
                 f *= (w * tables[i][ax][cells]).sum(axis=1)
             out[i] += f.sum()
     return out
+
+
+def delta_half_direct(pos, box, n, chunk=4096):
+    """N_P^-1 sum_j exp(-2 pi i m.x_j / L) on the half spectrum [n][n][n/2+1].
+
+    Entry (ix, iy, mz) is the mode (signed_index(n)[ix], signed_index(n)[iy],
+    mz).  The exponential factorises over the axes, so for a chunk of
+    particles the sum is the contraction of three per-axis phase matrices
+    exp(-2 pi i m_a x_a / L) over the particle index.
+    """
+    pos = wrap(np.asarray(pos, dtype=np.float64), box)
+    m_full = signed_index(n).astype(np.float64)
+    m_half = np.arange(n // 2 + 1, dtype=np.float64)
+    out = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    for s in range(0, len(pos), chunk):
+        t = pos[s:s + chunk] / box
+        ex = np.exp(-2j * np.pi * np.outer(m_full, t[:, 0]))
+        ey = np.exp(-2j * np.pi * np.outer(m_full, t[:, 1]))
+        ez = np.exp(-2j * np.pi * np.outer(m_half, t[:, 2]))
+        exy = ex[:, None, :] * ey[None, :, :]
+        out += np.matmul(exy.reshape(n * n, -1), ez.T).reshape(n, n, n // 2 + 1)
+    return out / len(pos)

@@ -156,6 +156,31 @@ def bin_power(delta, box, n, n_dk, n_bins):
     return k, pk, counts
 
 
+def bin_cross(a, b, box, n, n_dk, n_bins, shot=0.0):
+    """(k_b, P_b, N_b) with P_b = V sum_shell w Re(a b*) / N_b - shot.
+
+    a and b are half spectra (``half_axes`` layout); b = a gives the auto
+    spectrum of the direct-summation estimator (Sec. 2.2) or of the grid
+    estimator, a = delta_G and b = delta_DS the cross spectrum P_{G-DS} used
+    to measure aliasing in Sec. 3.2.  Shells, weights and mode counts as in
+    ``bin_power``.
+    """
+    mx, my, mz = half_axes(n)
+    m2 = mx * mx + my * my + mz * mz
+    bi = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
+    w = np.broadcast_to(half_weights(n), m2.shape).astype(np.float64)
+    sel = (m2 > 0) & (bi >= 1) & (bi <= n_bins)
+    re = (np.asarray(a) * np.conj(np.asarray(b))).real
+    s = np.bincount(bi[sel], weights=(w * re)[sel], minlength=n_bins + 1)[1:]
+    counts, ksum = mode_table(n, n_dk, n_bins)
+    kf = 2.0 * np.pi / box
+    vol = float(box) ** 3
+    with np.errstate(invalid="ignore", divide="ignore"):
+        k = kf * ksum / counts
+        pk = vol * s / counts - shot
+    return k, pk, counts
+
+
 def power(pos, box, n_grid, order, interlace_on, n_dk=1, n_bins=None,
           subtract_shot=False, workers=None):
     """Binned power spectrum of a particle set.

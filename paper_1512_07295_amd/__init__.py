@@ -41,6 +41,8 @@ EXPORTS = [
     "estimator_bispectrum_workspace_bytes", "estimator_bispectrum",
     "estimator_backward", "estimator_graph_capture", "estimator_graph_launch",
     "estimator_autotune", "estimator_set_launch", "estimator_copy_grid", "estimator_sample_delta",
+    "estimator_direct_workspace_bytes", "estimator_direct_delta", "estimator_export_delta",
+    "estimator_spectrum_power",
     "estimator_profile", "estimator_profile_read", "estimator_last_error",
 ]
 
@@ -85,6 +87,10 @@ _SIGS = {
     "estimator_set_launch": [_P, _I32],
     "estimator_copy_grid": [_P, _I32, _I32, _P],
     "estimator_sample_delta": [_P, _I32, _P, _I64, _P],
+    "estimator_direct_workspace_bytes": [_P, _I64, ctypes.POINTER(_SZ)],
+    "estimator_direct_delta": [_P, _P, _I32, _I64, _P, _SZ, _P],
+    "estimator_export_delta": [_P, _I32, _P],
+    "estimator_spectrum_power": [_P, _P, _P, _I32, _I32, ctypes.c_double, _P, _P, _P],
     "estimator_profile": [_P, _I32],
     "estimator_profile_read": [_P, _I32, ctypes.c_char_p, _SZ, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
@@ -196,6 +202,27 @@ def estimator_copy_grid(h, which, mock, dst):
 
 def estimator_sample_delta(h, mock, modes, n, out):
     _check(_lib.estimator_sample_delta(h, int(mock), _ptr(modes), int(n), _ptr(out)))
+
+
+def estimator_direct_workspace_bytes(h, n):
+    out = _SZ(0)
+    _check(_lib.estimator_direct_workspace_bytes(h, int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+def estimator_direct_delta(h, pos, dtype, n, dws, dws_bytes, out):
+    _check(_lib.estimator_direct_delta(h, _ptr(pos), int(dtype), int(n), _ptr(dws),
+                                       _SZ(int(dws_bytes)), _ptr(out)))
+
+
+def estimator_export_delta(h, mock, out):
+    _check(_lib.estimator_export_delta(h, int(mock), _ptr(out)))
+
+
+def estimator_spectrum_power(h, a, b, n_dk, n_bins, shot, k, p, nmodes):
+    _check(_lib.estimator_spectrum_power(h, _ptr(a), _ptr(b), int(n_dk), int(n_bins),
+                                         ctypes.c_double(float(shot)), _ptr(k), _ptr(p),
+                                         _ptr(nmodes)))
 
 
 def estimator_profile(h, enable):

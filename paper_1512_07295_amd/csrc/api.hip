@@ -40,11 +40,11 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 enum ProfLabel {
   kPSort = 0, kPDeposit, kPFftX, kPFftY, kPFftZ, kPPower, kPAdjoint, kPIfftY, kPIfftX, kPGather,
-  kPModes, kPBispec, kPNumLabels
+  kPModes, kPBispec, kPDirect, kPNumLabels
 };
 static const char* kProfNames[kPNumLabels] = {
     "bucket_sort", "deposit", "fft_x", "fft_y", "fft_z", "power_fused_z", "adjoint_fused_z",
-    "ifft_y", "ifft_x", "gather_grad", "mode_table", "bispectrum"};
+    "ifft_y", "ifft_x", "gather_grad", "mode_table", "bispectrum", "direct_sum"};
 
 struct ProfRec {
   double total_ms = 0.0;
@@ -671,6 +671,51 @@ est_status estimator_sample_delta(est_handle h, int32_t mock, const int32_t* mod
   if (!modes || !out || n < 1) return fail(EST_EINVAL, "modes/out missing");
   if ((st = to_spectrum(h))) return st;
   return dev_err(launch_sample_delta(h->g, h->b, mock, modes, n, out, h->stream), "sample delta");
+}
+
+est_status estimator_direct_workspace_bytes(est_handle h, int64_t n, size_t* bytes) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!bytes) return fail(EST_EINVAL, "bytes is NULL");
+  if (n < 1 || n > 2147483647LL) return fail(EST_EINVAL, "n must be 1..2^31-1");
+  *bytes = direct_workspace(h->g.n, n);
+  return ok();
+}
+
+est_status estimator_direct_delta(est_handle h, const void* pos, est_dtype dtype, int64_t n,
+                                  void* dws, size_t dws_bytes, double* out) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!pos || !out || !dws) return fail(EST_EINVAL, "pos, dws and out are required");
+  if (dtype != EST_F32 && dtype != EST_F64) return fail(EST_EINVAL, "dtype must be EST_F32 or EST_F64");
+  if (n < 1 || n > 2147483647LL) return fail(EST_EINVAL, "n must be 1..2^31-1");
+  if (((uintptr_t)dws & 255) != 0) return fail(EST_EINVAL, "dws must be 256-byte aligned");
+  const size_t need = direct_workspace(h->g.n, n);
+  if (dws_bytes < need) return fail(EST_ENOMEM, "direct workspace too small: %zu < %zu", dws_bytes, need);
+  ProfScope ps(h, kPDirect);
+  return dev_err(launch_direct(h->g, pos, dtype, n, dws, out, h->stream), "direct sum");
+}
+
+est_status estimator_export_delta(est_handle h, int32_t mock, double* out) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (mock < 0 || mock >= h->g.batch) return fail(EST_EINVAL, "mock out of range");
+  if (!out) return fail(EST_EINVAL, "out is NULL");
+  if ((st = to_spectrum(h))) return st;
+  return dev_err(launch_export_delta(h->g, h->b, mock, out, h->stream), "export delta");
+}
+
+est_status estimator_spectrum_power(est_handle h, const double* a, const double* b, int32_t n_dk,
+                                    int32_t n_bins, double shot, double* k, double* p,
+                                    int64_t* nmodes) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!a || !k || !p || !nmodes) return fail(EST_EINVAL, "a, k, p and nmodes are required");
+  if (!std::isfinite(shot)) return fail(EST_EINVAL, "shot must be finite");
+  if ((st = check_bins(h, n_dk, n_bins))) return st;
+  if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  return dev_err(launch_spectrum_power(h->g, h->b, a, b, n_dk, n_bins, shot, k, p, nmodes, h->stream),
+                 "spectrum power");
 }
 
 est_status estimator_profile(est_handle h, int32_t enable) {

@@ -128,6 +128,16 @@ hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& 
                                    const double* dldp, int n_dk, int n_bins, hipStream_t s);
 hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,
                                int64_t n, double* out, hipStream_t s);
+hipError_t launch_export_delta(const Geom& g, const Buffers& b, int mock, double* out,
+                               hipStream_t s);
+// P = V sum_shell w Re(a conj(b)) / N_b - shot over half spectra a, b (b null: |a|^2)
+hipError_t launch_spectrum_power(const Geom& g, const Buffers& b, const double* a, const double* bb,
+                                 int n_dk, int n_bins, double shot, double* k, double* p,
+                                 int64_t* nmodes, hipStream_t s);
+// direct summation (eq. deltaDS) over every half-space mode
+size_t direct_workspace(int ngrid, int64_t n);
+hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, void* ws,
+                         double* out, hipStream_t s);
 // bispectrum
 hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
                              bool counts_only, float2* out, hipStream_t s);

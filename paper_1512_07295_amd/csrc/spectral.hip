@@ -504,13 +504,12 @@ hipError_t launch_mode_table(const Geom& g, const Buffers& b, int n_dk, int n_bi
 
 // ------------------------------------------------------------------ sampled delta
 // delta(m) = C(m) / (N_P W(m)) at signed modes, from the stored full spectrum.
-__global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock,
-                               const int32_t* __restrict__ modes, int64_t nm,
-                               const int64_t* __restrict__ np, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nm) return;
+// delta(m) = C(m) / (N_P W(m)) at half-space mode m from the stored
+// spectrum Z (after the z pass), in FP64: the estimator's Fourier density
+// (eqs. intdelta, windowcorrection), normalised like the direct sum.
+__device__ void delta_at(const float2* __restrict__ data, const Geom& g, int mock, int mx, int my,
+                         int mz, double npart, double& re, double& im) {
   const int n = g.n;
-  const int mx = modes[3 * i], my = modes[3 * i + 1], mz = modes[3 * i + 2];
   const int x = mx & (n - 1), y = my & (n - 1);
   const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
   const int L = g.nz;
@@ -540,9 +539,116 @@ __global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock
       for (int k = 0; k < g.order; ++k) w *= sc;
     }
   }
-  const double d = (double)np[mock] * w;
-  out[2 * i] = cr / d;
-  out[2 * i + 1] = ci / d;
+  const double d = npart * w;
+  re = cr / d;
+  im = ci / d;
+}
+
+__global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock,
+                               const int32_t* __restrict__ modes, int64_t nm,
+                               const int64_t* __restrict__ np, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nm) return;
+  delta_at(data, g, mock, modes[3 * i], modes[3 * i + 1], modes[3 * i + 2], (double)np[mock],
+           out[2 * i], out[2 * i + 1]);
+}
+
+// every half-space mode, index (ix * N + iy) * (N/2 + 1) + m_z (FFT indices
+// ix, iy; index N/2 is +N/2)
+__global__ void k_export_delta(const float2* __restrict__ data, Geom g, int mock,
+                               const int64_t* __restrict__ np, double* __restrict__ out) {
+  const int n = g.n, nh = n / 2 + 1;
+  const int64_t nm = (int64_t)n * n * nh;
+  const double npart = (double)np[mock];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nm;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int mz = (int)(i % nh);
+    const int iy = (int)((i / nh) % n), ix = (int)(i / ((int64_t)n * nh));
+    delta_at(data, g, mock, signed_freq(ix, n), signed_freq(iy, n), mz, npart, out[2 * i],
+             out[2 * i + 1]);
+  }
+}
+
+hipError_t launch_export_delta(const Geom& g, const Buffers& b, int mock, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_export_delta, dim3(4096), dim3(256), 0, s, b.grid, g, mock, b.np, out);
+  return hipGetLastError();
+}
+
+// Shell sums of w Re(a conj(b)) over the half spectrum (a, b complex128 in
+// k_export_delta's order; b == a when b is null), w = 1 on m_z in {0, N/2}
+// and 2 elsewhere, shells as shell_of.  Per-workgroup partial histograms,
+// then the same fixed-order reduction as the P(k) pass.
+constexpr int kSpecBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_spec_bins(const double* __restrict__ a,
+                                                   const double* __restrict__ bb, Geom g, int n_dk,
+                                                   int n_bins, double* __restrict__ partials) {
+  __shared__ double hist[kMaxBins];
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
+  __syncthreads();
+  const int n = g.n, nh = n / 2 + 1;
+  constexpr int CH = 16;
+  const int chunks = (nh + CH - 1) / CH;
+  const int64_t items = (int64_t)n * n * chunks;
+  const double* b2 = bb ? bb : a;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = it / chunks;
+    const int ch = (int)(it % chunks);
+    const int mx = signed_freq((int)(row / n), n), my = signed_freq((int)(row % n), n);
+    const int r2 = mx * mx + my * my;
+    int cur_b = -1;
+    double cur = 0.0;
+    for (int mz = ch * CH; mz < (ch + 1) * CH && mz < nh; ++mz) {
+      const int m2 = r2 + mz * mz;
+      if (m2 == 0) continue;
+      const int b = shell_of(m2, n_dk);
+      if (b < 1 || b > n_bins) continue;
+      const int64_t i = row * nh + mz;
+      const double v = a[2 * i] * b2[2 * i] + a[2 * i + 1] * b2[2 * i + 1];
+      const double w = (mz == 0 || mz == n / 2) ? 1.0 : 2.0;
+      if (b != cur_b) {
+        if (cur_b > 0) atomicAdd(&hist[cur_b - 1], cur);
+        cur_b = b;
+        cur = 0.0;
+      }
+      cur += w * v;
+    }
+    if (cur_b > 0) atomicAdd(&hist[cur_b - 1], cur);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x)
+    partials[(int64_t)blockIdx.x * n_bins + i] = hist[i];
+}
+
+__global__ __launch_bounds__(64) void k_spec_finalize(const double* __restrict__ partials, int nblk,
+                                                      int n_bins,
+                                                      const int64_t* __restrict__ mode_n,
+                                                      const double* __restrict__ mode_k, double box,
+                                                      double shot, double* k, double* p,
+                                                      int64_t* nmodes) {
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 64) s += partials[(int64_t)i * n_bins + b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (threadIdx.x != 0) return;
+  const double vol = box * box * box;
+  const double nb = (double)mode_n[b];
+  p[b] = vol * s / nb - shot;
+  k[b] = (2.0 * M_PI / box) * mode_k[b] / nb;
+  nmodes[b] = mode_n[b];
+}
+
+hipError_t launch_spectrum_power(const Geom& g, const Buffers& b, const double* a, const double* bb,
+                                 int n_dk, int n_bins, double shot, double* k, double* p,
+                                 int64_t* nmodes, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_bins, dim3(kSpecBlocks), dim3(256), 0, s, a, bb, g, n_dk, n_bins,
+                     b.partials);
+  hipLaunchKernelGGL(k_spec_finalize, dim3(n_bins), dim3(64), 0, s, b.partials, kSpecBlocks,
+                     n_bins, b.mode_n, b.mode_k, g.box, shot, k, p, nmodes);
+  return hipGetLastError();
 }
 
 hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,

@@ -10,9 +10,11 @@ import torch
 
 from . import (EST_F32, EST_F64, EST_FLAG_ATOMIC_SORT, estimator_autotune, estimator_backward, estimator_bispectrum,
                estimator_bispectrum_workspace_bytes, estimator_copy_grid, estimator_create,
-               estimator_deposit, estimator_destroy, estimator_graph_capture,
+               estimator_deposit, estimator_destroy, estimator_direct_delta,
+               estimator_direct_workspace_bytes, estimator_export_delta, estimator_graph_capture,
                estimator_graph_launch, estimator_power, estimator_sample_delta, estimator_set_launch,
-               estimator_transform, estimator_workspace_bytes, make_config)
+               estimator_spectrum_power, estimator_transform, estimator_workspace_bytes,
+               make_config)
 
 
 def _dtype_code(t):
@@ -158,6 +160,39 @@ class Estimator:
         out = torch.empty((m.shape[0], 2), dtype=torch.float64, device=self.device)
         estimator_sample_delta(self.h, mock, m, m.shape[0], out)
         return torch.complex(out[:, 0], out[:, 1])
+
+    # ---- direct summation and half-spectrum statistics
+    def _half(self):
+        n = self.n_grid
+        return torch.empty((n, n, n // 2 + 1, 2), dtype=torch.float64, device=self.device)
+
+    def direct_delta(self, pos):
+        """delta_DS on the half spectrum ([N, N, N/2+1, 2] float64) by direct summation."""
+        _check_pos(pos)
+        n = pos.shape[0]
+        nbytes = estimator_direct_workspace_bytes(self.h, n)
+        ws, ws_ptr = _aligned_workspace(nbytes, self.device)
+        out = self._half()
+        estimator_direct_delta(self.h, pos, _dtype_code(pos), n, ws_ptr, nbytes, out)
+        self.stream.synchronize()  # the workspace is released on return
+        del ws
+        return out
+
+    def export_delta(self, mock=0):
+        """The estimator's delta(m) on the half spectrum ([N, N, N/2+1, 2] float64)."""
+        out = self._half()
+        estimator_export_delta(self.h, mock, out)
+        return out
+
+    def spectrum_power(self, a, b=None, n_dk=1, n_bins=None, shot=0.0):
+        """(k, P, N) with P = V <Re(a b*)> per shell - shot (b = a if None)."""
+        if n_bins is None:
+            n_bins = self.n_grid // (2 * n_dk)
+        k = torch.empty(n_bins, dtype=torch.float64, device=self.device)
+        p = torch.empty_like(k)
+        nm = torch.empty(n_bins, dtype=torch.int64, device=self.device)
+        estimator_spectrum_power(self.h, a, b, n_dk, n_bins, shot, k, p, nm)
+        return k, p, nm
 
 
 class PowerSpectrumFn(torch.autograd.Function):
