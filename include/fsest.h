@@ -75,7 +75,8 @@ typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
 
 typedef struct {
   int32_t n_grid;        /* N: power of two in [8, 1024]                       */
-  int32_t order;         /* p = 1..4: NGP, CIC, TSC, PCS (Sec. 2.3)            */
+  int32_t order;         /* p = 1..6: NGP, CIC, TSC, PCS (Sec. 2.3), then the  */
+                         /* order-5/6 B-splines (p-fold box convolutions)      */
   int32_t interlace;     /* 0 or 1: second grid shifted by H/2 (Sec. 3.1)     */
   int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
   double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */

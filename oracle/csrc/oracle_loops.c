@@ -5,7 +5,8 @@
  *
  *   stencil: even p -> first cell floor(u) - (p/2 - 1); odd p -> first cell
  *            floor(u + 1/2) - (p - 1)/2; p consecutive cells (mod N); weight
- *            W^(p)(cell - u) of Sec. 2.3 (CIC support |s| < 1; NGP weight 1).
+ *            W^(p)(cell - u) of Sec. 2.3 (CIC support |s| < 1; NGP weight 1;
+ *            p = 5, 6: the centred B-spline's truncated-power sum).
  *   deposit: rho[g] += prod_axes W (eq. delgrid), grid index (x*N + y)*N + z.
  *   footprint DFT: F(m) = sum_j prod_axes sum_t w exp(-2 pi i m c / N).
  *
@@ -20,8 +21,23 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#define MAXP 6
+
+/* 1/(p-1)! sum_k (-1)^k C(p,k) (s + p/2 - k)_+^(p-1) */
+static double bspline(int p, double s) {
+  double out = 0.0, c = 1.0, fact = 1.0;
+  for (int i = 2; i < p; ++i) fact *= i;
+  for (int k = 0; k <= p; ++k) {
+    const double x = s + 0.5 * p - k;
+    if (x > 0.0) out += ((k & 1) ? -c : c) * pow(x, p - 1);
+    c = c * (p - k) / (k + 1);
+  }
+  return out / fact;
+}
+
 static double weight(int p, double s) {
   const double a = fabs(s);
+  if (p > 4) return a < 0.5 * p ? bspline(p, s) : 0.0;
   switch (p) {
     case 1:
       return (s > -0.5 && s <= 0.5) ? 1.0 : 0.0;
@@ -39,6 +55,7 @@ static double weight(int p, double s) {
 }
 
 static void stencil(double u, int p, int64_t n, int64_t* cell, double* w) {
+  /* cell and w hold MAXP entries */
   const double first = (p % 2 == 0) ? floor(u) - (p / 2 - 1) : floor(u + 0.5) - (p - 1) / 2;
   for (int t = 0; t < p; ++t) {
     const double c = first + t;
@@ -51,8 +68,8 @@ static void stencil(double u, int p, int64_t n, int64_t* cell, double* w) {
 
 /* rho (n^3, zeroed by the caller) += deposit of n_p particles at u (n_p x 3) */
 void oracle_deposit(const double* u, int64_t n_p, int64_t n, int p, double* rho) {
-  int64_t cx[4], cy[4], cz[4];
-  double wx[4], wy[4], wz[4];
+  int64_t cx[MAXP], cy[MAXP], cz[MAXP];
+  double wx[MAXP], wy[MAXP], wz[MAXP];
   for (int64_t j = 0; j < n_p; ++j) {
     stencil(u[3 * j + 0], p, n, cx, wx);
     stencil(u[3 * j + 1], p, n, cy, wy);
@@ -88,8 +105,8 @@ void oracle_footprint_dft(const double* u, int64_t n_p, int64_t n, int p,
     /* thread-local sums (no shared cache lines while accumulating) */
     double* my_re = (double*)calloc((size_t)n_modes, sizeof(double));
     double* my_im = (double*)calloc((size_t)n_modes, sizeof(double));
-    int64_t cell[3][4];
-    double w[3][4];
+    int64_t cell[3][MAXP];
+    double w[3][MAXP];
 #pragma omp for schedule(static)
     for (int64_t j = 0; j < n_p; ++j) {
       for (int ax = 0; ax < 3; ++ax) stencil(u[3 * j + ax], p, n, cell[ax], w[ax]);
@@ -142,8 +159,8 @@ void oracle_cell_values(const double* u, int64_t n_p, int64_t n, int p,
   {
     const int tid = omp_get_thread_num();
     double* mine = (double*)calloc((size_t)k, sizeof(double));
-    int64_t cell[3][4];
-    double w[3][4];
+    int64_t cell[3][MAXP];
+    double w[3][MAXP];
 #pragma omp for schedule(static)
     for (int64_t j = 0; j < n_p; ++j) {
       for (int ax = 0; ax < 3; ++ax) stencil(u[3 * j + ax], p, n, cell[ax], w[ax]);

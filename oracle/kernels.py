@@ -4,7 +4,13 @@ Test infrastructure only (see ``oracle/__init__.py``).
 
 The one-dimensional weights W^(p)(s), s = (x_grid - x)/H, are the
 piecewise polynomials printed for NGP (p=1), CIC (p=2), TSC (p=3) and PCS
-(p=4) in Sec. 2.3.  Two readings:
+(p=4) in Sec. 2.3.  Orders p = 5, 6 (the higher-order B-splines Sec. 2.3
+mentions) use the centred cardinal B-spline of order p, the p-fold
+convolution of the unit box, written as its truncated-power sum
+
+    W^(p)(s) = 1/(p-1)! sum_{k=0}^{p} (-1)^k C(p, k) (s + p/2 - k)_+^{p-1},
+
+whose Fourier transform is sinc^p (eq. intkerFT).  Two readings:
 
 * CIC: the printed support "|s| < 1/2" is a typo; the support is |s| < 1
   (partition of unity and the sinc^2 window of eq. intkerFT both require it).
@@ -14,7 +20,22 @@ piecewise polynomials printed for NGP (p=1), CIC (p=2), TSC (p=3) and PCS
   cell so that no mass is dropped.
 """
 
+from math import comb, factorial
+
 import numpy as np
+
+MAX_ORDER = 6
+
+
+def _bspline(p, s, deriv=False):
+    """Truncated-power sum of the centred order-p B-spline (or its derivative)."""
+    s = np.asarray(s, dtype=np.float64)
+    e = p - 2 if deriv else p - 1
+    out = np.zeros_like(s)
+    for k in range(p + 1):
+        x = s + 0.5 * p - k
+        out += (-1) ** k * comb(p, k) * np.where(x > 0, x, 0.0) ** e
+    return out / factorial(e)
 
 
 def weight(p, s):
@@ -34,7 +55,9 @@ def weight(p, s):
         inner = (4.0 - 6.0 * s * s + 3.0 * a ** 3) / 6.0
         outer = (2.0 - a) ** 3 / 6.0
         return np.where(a < 1.0, inner, np.where(a < 2.0, outer, 0.0))
-    raise ValueError("order p must be 1..4")
+    if p <= MAX_ORDER:
+        return np.where(a < 0.5 * p, _bspline(p, s), 0.0)
+    raise ValueError("order p must be 1..%d" % MAX_ORDER)
 
 
 def dweight(p, s):
@@ -55,7 +78,9 @@ def dweight(p, s):
         inner = -2.0 * s + 1.5 * s * a
         outer = -0.5 * (2.0 - a) ** 2 * sg
         return np.where(a < 1.0, inner, np.where(a < 2.0, outer, 0.0))
-    raise ValueError("order p must be 1..4")
+    if p <= MAX_ORDER:
+        return np.where(a < 0.5 * p, _bspline(p, s, deriv=True), 0.0)
+    raise ValueError("order p must be 1..%d" % MAX_ORDER)
 
 
 def window_1d(p, m, n_grid):

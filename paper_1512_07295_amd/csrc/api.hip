@@ -120,7 +120,7 @@ void prof_fold(est_ctx* h) {
 
 est_status check_config(const est_config* c) {
   if (!c) return fail(EST_EINVAL, "config is NULL");
-  if (c->order < 1 || c->order > 4) return fail(EST_EINVAL, "order must be 1..4 (got %d)", c->order);
+  if (c->order < 1 || c->order > 6) return fail(EST_EINVAL, "order must be 1..6 (got %d)", c->order);
   if (c->interlace != 0 && c->interlace != 1)
     return fail(EST_EINVAL, "interlace must be 0 or 1 (got %d)", c->interlace);
   if (c->batch < 1 || c->batch > 65535) return fail(EST_EINVAL, "batch must be 1..65535 (got %d)", c->batch);

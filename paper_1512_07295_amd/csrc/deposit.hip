@@ -506,6 +506,40 @@ hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64
 }
 
 // ------------------------------------------------------------------ stencils
+// Orders above 4 (the higher-order B-splines of Sec. 2.3): the weights of
+// the p stencil cells are N_p(t + i), i = 0..p-1, of the cardinal B-spline
+// N_p (the p-fold convolution of the unit box on [0, 1], support [0, p]),
+// with t = 1 - f for even p and t = 1/2 - f for odd p (f = u - floor(...)
+// as below), from the recursion
+//   N_{k+1}(t + j) = ((t + j) N_k(t + j) + (k + 1 - t - j) N_k(t + j - 1)) / k,
+// N_1(t) = 1 (convex combinations: no cancellation).  d/ds of the order-p
+// weight is N_{p-1}(t + i) - N_{p-1}(t + i - 1), from the previous level.
+template <int P>
+__device__ __forceinline__ void bspline_weights(float t, float (&w)[P], float (&wd)[P]) {
+  float v[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) v[j] = (j == 0) ? 1.0f : 0.0f;
+#pragma unroll
+  for (int k = 1; k < P; ++k) {
+    if (k == P - 1) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) wd[j] = (j < k ? v[j] : 0.0f) - (j >= 1 ? v[j - 1] : 0.0f);
+    }
+    float nv[P];
+    const float rk = 1.0f / (float)k;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const float a = (j < k) ? v[j] : 0.0f;
+      const float b = (j >= 1 && j <= k) ? v[j - 1] : 0.0f;
+      nv[j] = (j <= k) ? ((t + (float)j) * a + ((float)(k + 1 - j) - t) * b) * rk : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = nv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) w[j] = v[j];
+}
+
 // Cells (mod N) and weights of the p-point stencil of one axis, for grid
 // coordinate u (float64).  Even p: first cell floor(u) - (p/2 - 1); odd p:
 // first cell floor(u + 1/2) - (p-1)/2.  Weights are W^(p)(cell - u) of
@@ -525,13 +559,16 @@ __device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], floa
     w[0] = 0.5f * a * a;
     w[1] = 0.75f - f * f;
     w[2] = 0.5f * c * c;
-  } else {
+  } else if constexpr (P == 4) {
     const float t = 1.0f - f;
     const float f2 = f * f, t2 = t * t;
     w[0] = t2 * t * (1.0f / 6.0f);
     w[1] = (4.0f - 6.0f * f2 + 3.0f * f2 * f) * (1.0f / 6.0f);
     w[2] = (4.0f - 6.0f * t2 + 3.0f * t2 * t) * (1.0f / 6.0f);
     w[3] = f2 * f * (1.0f / 6.0f);
+  } else {
+    float wd[P];
+    bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, wd);
   }
 #pragma unroll
   for (int i = 0; i < P; ++i) cell[i] = (first + i) & (n - 1);
@@ -554,6 +591,9 @@ __device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
     dw[0] = (0.5f - f);           // W' = -(3/2-|s|) sgn(s), s<0 -> +(1/2 - f)
     dw[1] = 2.0f * f;             // -2 s
     dw[2] = -(0.5f + f);          // s>0 -> -(3/2 - (1-f))
+  } else if constexpr (P > 4) {
+    float w[P];
+    bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, dw);
   } else {
     const float t = 1.0f - f;
     // s0 = -1-f (|s| in [1,2)): W' = +(1/2)(2-|s|)^2 = t^2/2
@@ -584,8 +624,12 @@ __device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
 constexpr float kFixWide = 4294967040.0f;  // 2^32 - 2^8
 constexpr int kNarrowMinBits = 24;
 
+// The base cells of the particles that reach one cell span p + 1 cells per
+// axis (both grids), so they meet at most 2 buckets per axis for p <= 4 and
+// 3 for p = 5, 6.
+template <int P>
 __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
-  const double bound = 8.0 * (double)(maxcount > 0 ? maxcount : 1);
+  const double bound = (P <= 4 ? 8.0 : 27.0) * (double)(maxcount > 0 ? maxcount : 1);
   int f = 0;
   while (f < 31 && bound * (ldexp(1.0, f + 1) + 1.0) < 4294967295.0) ++f;
   return f;
@@ -597,18 +641,22 @@ __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
 //   [.., + kItemCap/2)       item order after sorting by bank class (u16)
 //   [kAccWord, ...)          tile accumulators, one region of kGridWords
 //                            elements per grid
-// Each tile row holds kZHalo extra cells on both z sides, so every cell of a
-// stencil row that reaches the tile has an address: a stencil is added at
-// base + i*kPlane + k*kRow + l with compile-time offsets, rows outside the
-// tile in x or y are skipped, and halo cells are dropped (or, when the tile
-// is the whole periodic grid, folded back) at write-out.  kRow and kPlane
-// make the 64 offsets i*kPlane + k*kRow + l (i, k, l < 4) distinct mod 64,
-// so two stencils whose bases differ mod 64 never share an LDS bank in one
+// Each tile row holds h = zhalo<p>() extra cells on both z sides (3 up to
+// p = 4, p - 1 above), so every cell of a stencil row that reaches the tile
+// has an address: a stencil is added at base + i*kPlane + k*kRow + l with
+// compile-time offsets, rows outside the tile in x or y are skipped, and
+// halo cells are dropped (or, when the tile is the whole periodic grid,
+// folded back) at write-out.  kRow and kPlane make the 64 offsets
+// i*kPlane + k*kRow + l (i, k, l < 4) distinct mod 64, so for p <= 4 two
+// stencils whose bases differ mod 64 never share an LDS bank in one
 // instruction; work items are ordered by that residue ("bank class") and
 // each wave takes items spread evenly over the order, which keeps the
 // classes of its 64 lanes distinct except where a class holds more items
 // than there are waves in the flush.
-constexpr int kZHalo = 3;
+constexpr int kZHalo = 3;  // orders up to 4; zhalo<P>() in general
+constexpr int kMaxOrder = 6;
+template <int P>
+__device__ __host__ constexpr int zhalo() { return P <= 4 ? kZHalo : P - 1; }
 constexpr int kRow = 28;
 constexpr int kPlane = 464;
 constexpr int kGridWords = kTileMax * kPlane;
@@ -627,11 +675,16 @@ constexpr bool offsets_cover_banks() {
   return true;
 }
 static_assert(offsets_cover_banks(), "stencil offsets must cover the 64 banks");
-static_assert(kRow >= kTileMax + 2 * kZHalo && kPlane >= kTileMax * kRow, "tile pitches");
+static_assert(kRow >= kTileMax + 2 * (kMaxOrder - 1) && kPlane >= kTileMax * kRow, "tile pitches");
 static_assert(kAccWord % 64 == 0 && kGridWords % 64 == 0, "regions start on bank 0");
 // the lowest element a stencil base can address lies kAccMargin below a region
-constexpr int kAccMargin = 3 * kPlane + 3 * kRow;
-static_assert(kAccWord / 2 >= kAccMargin, "base addresses stay non-negative (64-bit elements)");
+constexpr int kAccMargin = (kMaxOrder - 1) * (kPlane + kRow);
+// 64-bit accumulators start further in, so that their margin also fits
+constexpr int kAccWordWide = 5120;
+static_assert(kAccWord >= kAccMargin && kAccWordWide / 2 >= kAccMargin && kAccWordWide % 64 == 0,
+              "base addresses stay non-negative");
+template <typename AT>
+__device__ __host__ constexpr int acc_first_word() { return sizeof(AT) == 4 ? kAccWord : kAccWordWide; }
 
 struct DepRanges {
   uint32_t start[72];
@@ -675,8 +728,9 @@ __device__ __forceinline__ bool reaches_tile(int rx, int ry, int rz) {
   else return rx < kTileMax && ry < kTileMax && rz < kTileMax;
 }
 
+template <int P>
 __device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
-  return (rx * kPlane + ry * kRow + rz + kZHalo) & 63;
+  return (rx * kPlane + ry * kRow + rz + zhalo<P>()) & 63;
 }
 
 // Adds one grid's footprint of one particle to the tile.
@@ -692,11 +746,11 @@ __device__ __forceinline__ void deposit_item(double x, double y, double z, int g
   const int rx = rel_first<P, PERIODIC>(fx, t0x, n);
   const int ry = rel_first<P, PERIODIC>(fy, t0y, n);
   const int rz = rel_first<P, PERIODIC>(fz, t0z, n);
-  const int region = (kAccWord * 4 / (int)sizeof(AT)) + gi * kGridWords;
+  const int region = (acc_first_word<AT>() * 4 / (int)sizeof(AT)) + gi * kGridWords;
   if constexpr (PERIODIC) {
     // the tile is the whole grid (n <= kTileMax): x and y wrap, z runs into
     // the upper halo and is folded back at write-out
-    AT* zrow = sm + region + rz + kZHalo;
+    AT* zrow = sm + region + rz + zhalo<P>();
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int xo = ((rx + i) & (n - 1)) * kPlane;
@@ -710,7 +764,7 @@ __device__ __forceinline__ void deposit_item(double x, double y, double z, int g
       }
     }
   } else {
-    AT* base = sm + region + rx * kPlane + ry * kRow + rz + kZHalo;
+    AT* base = sm + region + rx * kPlane + ry * kRow + rz + zhalo<P>();
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       if ((unsigned)(rx + i) >= (unsigned)kTileMax) continue;
@@ -768,7 +822,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int NG = IL ? 2 : 1;
   constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
-  constexpr int kWords = kAccWord + NG * kGridWords * (int)(sizeof(AT) / 4);
+  constexpr int kWords = acc_first_word<AT>() + NG * kGridWords * (int)(sizeof(AT) / 4);
   __shared__ __align__(16) uint32_t smem[kWords];
   __shared__ DepRanges rg;
   __shared__ int wave_cnt[MAXW];
@@ -779,10 +833,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   uint8_t* item_meta = reinterpret_cast<uint8_t*>(smem + kItemCap);
   uint16_t* item_order = reinterpret_cast<uint16_t*>(smem + kItemCap + kItemCap / 4);
   AT* sm = reinterpret_cast<AT*>(smem);
-  const int acc0 = kAccWord * 4 / (int)sizeof(AT);
+  const int acc0 = acc_first_word<AT>() * 4 / (int)sizeof(AT);
 
   // fixed-point format for this deposit (uniform over the grid)
-  const int nbits = narrow_bits(stats[0]);
+  const int nbits = narrow_bits<P>(stats[0]);
   if (!WIDE && nbits < kNarrowMinBits) return;                // the wide kernel does it
   if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
   const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
@@ -863,8 +917,8 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     }
     // the other waves clear the tile while wave 0 waits for the offsets
     {
-      uint4* z4 = reinterpret_cast<uint4*>(smem + kAccWord);
-      constexpr int kZero4 = (kWords - kAccWord) / 4;
+      uint4* z4 = reinterpret_cast<uint4*>(smem + acc_first_word<AT>());
+      constexpr int kZero4 = (kWords - acc_first_word<AT>()) / 4;
       for (int i = threadIdx.x; i < kZero4; i += nthreads) z4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
@@ -920,7 +974,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
             const int ry = rel_first<P, PERIODIC>(cy + sy, t0y, n);
             const int rz = rel_first<P, PERIODIC>(cz + sz, t0z, n);
             ok[gi] = reaches_tile<P, PERIODIC>(rx, ry, rz);
-            cls[gi] = bank_class(rx, ry, rz);
+            cls[gi] = bank_class<P>(rx, ry, rz);
           }
         }
 #pragma unroll
@@ -1033,7 +1087,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
         float v[NG][4];
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
-          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + kZHalo;
+          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const AT s = sm[a + q];
@@ -1056,9 +1110,9 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
         float v[NG];
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
-          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + kZHalo;
+          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
           AT s = sm[a];
-          if (lz < kZHalo) s += sm[a + T];
+          if (lz < zhalo<P>()) s += sm[a + T];
           v[gi] = (float)((double)s * inv_scale);
         }
         if constexpr (IL) {
@@ -1129,7 +1183,9 @@ hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const T
     case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, s); break;
     case 2: dispatch_deposit_p<2>(g, dt, b, tu, threads, s); break;
     case 3: dispatch_deposit_p<3>(g, dt, b, tu, threads, s); break;
-    default: dispatch_deposit_p<4>(g, dt, b, tu, threads, s); break;
+    case 4: dispatch_deposit_p<4>(g, dt, b, tu, threads, s); break;
+    case 5: dispatch_deposit_p<5>(g, dt, b, tu, threads, s); break;
+    default: dispatch_deposit_p<6>(g, dt, b, tu, threads, s); break;
   }
   return hipGetLastError();
 }
@@ -1234,7 +1290,9 @@ hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, cons
     case 1: dispatch_gather<1>(g, pos, dt, offsets, n_total, b, grad, s); break;
     case 2: dispatch_gather<2>(g, pos, dt, offsets, n_total, b, grad, s); break;
     case 3: dispatch_gather<3>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    default: dispatch_gather<4>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    case 4: dispatch_gather<4>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    case 5: dispatch_gather<5>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    default: dispatch_gather<6>(g, pos, dt, offsets, n_total, b, grad, s); break;
   }
   return hipGetLastError();
 }

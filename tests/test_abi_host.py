@@ -55,7 +55,7 @@ def test_workspace_bytes_valid_and_monotone():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(order=0), fsest.EST_EINVAL),
-    (dict(order=5), fsest.EST_EINVAL),
+    (dict(order=7), fsest.EST_EINVAL),
     (dict(interlace=2), fsest.EST_EINVAL),
     (dict(batch=0), fsest.EST_EINVAL),
     (dict(box=0.0), fsest.EST_EINVAL),

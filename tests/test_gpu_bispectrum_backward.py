@@ -70,7 +70,8 @@ def _setup_loss(n, box, p, il, n_bins):
     return pos, target, counts, dldp
 
 
-@pytest.mark.parametrize("p,il", [(4, True), (4, False), (2, False), (3, True), (2, True)])
+@pytest.mark.parametrize("p,il", [(4, True), (4, False), (2, False), (3, True), (2, True),
+                                  (5, True), (6, True), (6, False)])
 def test_backward_matches_oracle_gradient(torch, p, il):
     from paper_1512_07295_amd.estimator import Estimator
     n, box, n_bins = 32, 1000.0, 16

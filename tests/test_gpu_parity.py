@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import assign, spectrum
+from oracle import kernels, assign, spectrum
 import synth
 from gpu_common import rel_err, require_gpu, to_dev
 
@@ -31,7 +31,7 @@ def _est(torch, n, box, p, il, batch=1, maxp=1 << 16):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32])
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("il", [False, True])
 def test_grid_parity(torch, n, p, il):
     box = 500.0
@@ -49,7 +49,7 @@ def test_grid_parity(torch, n, p, il):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32, 64])
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("il", [False, True])
 def test_power_parity_uniform(torch, n, p, il):
     box = 1000.0
@@ -63,7 +63,8 @@ def test_power_parity_uniform(torch, n, p, il):
     est.close()
 
 
-@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, True), (1, False)])
+@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, True), (1, False), (5, True),
+                                  (6, True), (6, False)])
 def test_power_parity_zeldovich_f32(torch, p, il):
     box = 1000.0
     pos = synth.zeldovich(32, box, 2, dtype=np.float32)
@@ -111,7 +112,8 @@ def test_power_bins_options(torch, n_dk, n_bins):
     est.close()
 
 
-@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, False), (1, True)])
+@pytest.mark.parametrize("p,il", [(4, True), (2, False), (3, False), (1, True), (5, True),
+                                  (6, False)])
 def test_sampled_delta(torch, p, il):
     box, n = 200.0, 32
     pos = synth.zeldovich(16, box, 8, dtype=np.float32)
@@ -125,7 +127,11 @@ def test_sampled_delta(torch, p, il):
     d = est.sample_delta(modes).cpu().numpy()
     delta, _ = spectrum.delta_half(pos, box, n, p, il)
     ref = delta[modes[:, 0] % n, modes[:, 1] % n, modes[:, 2]]
-    assert np.max(np.abs(d - ref)) <= 1e-5 * np.max(np.abs(ref))
+    # FP32 grid and FFT rounding is relative to the field's norm; dividing by
+    # the window W(m) (down to (2/pi)^(3p) at the Nyquist corner) scales it
+    # by 1/W(m), so the bound is on |delta error| W(m)
+    w = np.prod([kernels.window_1d(p, modes[:, a], n) for a in range(3)], axis=0)
+    assert np.max(np.abs(d - ref) * w) <= 1e-5 * np.max(np.abs(ref) * w)
     est.close()
 
 
@@ -257,22 +263,24 @@ def test_every_launch_variant_matches_oracle(torch, choice):
     est.close()
 
 
-def test_clustered_input_uses_wide_fixed_point(torch):
+@pytest.mark.parametrize("p", [4, 6])
+def test_clustered_input_uses_wide_fixed_point(torch, p):
     """A dense clump (thousands of particles in one bucket) exceeds the 32-bit
-    fixed-point bound and must go through the 64-bit path."""
+    fixed-point bound and must go through the 64-bit path (p = 6 also checks
+    the 64-bit layout's margin for the widest stencil)."""
     box, n = 100.0, 32
     rng = np.random.default_rng(4)
     clump = (37.1 + 0.3 * rng.random((6000, 3))).astype(np.float32)
     pos = np.concatenate([clump, synth.uniform(4000, box, 5, np.float32)])
     for choice in (0, 2):
-        est = _est(torch, n, box, 4, True, maxp=len(pos))
+        est = _est(torch, n, box, p, True, maxp=len(pos))
         est.set_launch(choice)
         est.deposit(to_dev(torch, pos))
-        r1, r2 = assign.deposit(pos, box, n, 4, True)
+        r1, r2 = assign.deposit(pos, box, n, p, True)
         assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
         assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
         _, pk, _ = est.power(to_dev(torch, pos))
-        assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
+        assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, p, True)[1]) < P_TOL
         est.close()
 
 

@@ -13,7 +13,7 @@ from scipy import integrate
 from oracle import assign, direct, kernels, spectrum
 import synth
 
-ORDERS = [1, 2, 3, 4]
+ORDERS = [1, 2, 3, 4, 5, 6]
 
 
 @pytest.mark.parametrize("p,u,expected", [
@@ -26,6 +26,11 @@ ORDERS = [1, 2, 3, 4]
     (3, 3.5, [0.5, 0.5, 0.0]),
     (4, 3.5, [1 / 48, 23 / 48, 23 / 48, 1 / 48]),
     (1, 3.49, [1.0]),
+    # orders 5 and 6: centred quartic / quintic B-spline values at integers
+    # and half-integers (p-fold convolution of the unit box)
+    (5, 3.0, [1 / 384, 19 / 96, 115 / 192, 19 / 96, 1 / 384]),
+    (6, 3.0, [1 / 120, 13 / 60, 11 / 20, 13 / 60, 1 / 120, 0.0]),
+    (6, 3.5, [1 / 3840, 237 / 3840, 841 / 1920, 841 / 1920, 237 / 3840, 1 / 3840]),
 ])
 def test_rational_weights(p, u, expected):
     cells, w = assign.stencil(np.array([u]), p, 16)
@@ -54,15 +59,16 @@ def test_kernel_fourier_transform_is_sinc_power(p):
     for q in (0.3, 1.1, 2.5, np.pi, 5.0):
         def f(s):
             return kernels.weight(p, np.array([s]))[0] * np.cos(q * s)
-        pts = [-2, -1.5, -1, -0.5, 0, 0.5, 1, 1.5, 2]
-        val = integrate.quad(f, -2.5, 2.5, points=pts, limit=200, epsabs=1e-13)[0]
+        pts = [-3, -2.5, -2, -1.5, -1, -0.5, 0, 0.5, 1, 1.5, 2, 2.5, 3]
+        val = integrate.quad(f, -3.5, 3.5, points=pts, limit=400, epsabs=1e-13)[0]
         assert val == pytest.approx(np.sinc(q / (2 * np.pi)) ** p, abs=1e-10)
 
 
-@pytest.mark.parametrize("p", [2, 3, 4])
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
 def test_kernel_derivative_matches_finite_difference(p):
-    s = np.linspace(-2.3, 2.3, 1001)
-    s = s[np.all(np.abs(np.abs(s)[:, None] - np.array([0.5, 1.0, 1.5, 2.0])) > 1e-3, axis=1)]
+    s = np.linspace(-3.3, 3.3, 1501)
+    knots = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0])
+    s = s[np.all(np.abs(np.abs(s)[:, None] - knots) > 1e-3, axis=1)]
     h = 1e-6
     fd = (kernels.weight(p, s + h) - kernels.weight(p, s - h)) / (2 * h)
     assert np.allclose(kernels.dweight(p, s), fd, atol=1e-6)
@@ -105,8 +111,11 @@ def test_deposit_equals_bruteforce_gather(p):
 
 
 def _lattice_factor(p, theta):
+    # sum_n W(n) exp(-i n theta) over the integer points of the kernel
     return {1: np.ones_like(theta), 2: np.ones_like(theta),
-            3: 0.75 + 0.25 * np.cos(theta), 4: 2 / 3 + np.cos(theta) / 3}[p]
+            3: 0.75 + 0.25 * np.cos(theta), 4: 2 / 3 + np.cos(theta) / 3,
+            5: 115 / 192 + 19 / 48 * np.cos(theta) + 1 / 192 * np.cos(2 * theta),
+            6: 11 / 20 + 13 / 30 * np.cos(theta) + 1 / 60 * np.cos(2 * theta)}[p]
 
 
 @pytest.mark.parametrize("p", ORDERS)
