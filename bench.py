@@ -6,8 +6,9 @@ float32) -> PCS deposit on a 1024^3 grid and on the grid shifted by H/2 ->
 3D FFT -> interlace + deconvolve -> P(k) in dk = k_f shells to Nyquist
 (512 bins).  A step is one deposit -> transform -> power over the resident
 particles.  Beside it (same JSON line): a batch of 64 uneven mocks on 128^3
-grids replayed as one HIP graph, and forward + backward of a P(k) loss for
-128^3 particles on a 256^3 grid.
+grids replayed as one HIP graph, forward + backward of a P(k) loss for
+128^3 particles on a 256^3 grid, the direct-summation engine, and the
+paper's own Zel'dovich shape (360^3 particles on a 480^3 mixed-radix grid).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -219,6 +220,53 @@ def fwd_bwd(args, torch, F, est_mod, synth):
                        "n_particles": npart}}
 
 
+def paper_za_leg(args, torch, F, est_mod, synth):
+    """The paper's Zel'dovich measurement shape (Sec. 3.3): 360^3 particles,
+    L = 2400 Mpc/h, N_G = 480 (2^5 3 5: mixed-radix FFT), PCS + interlacing,
+    P(k) in k_f shells to Nyquist.  Same step as the headline."""
+    n_side, box, n = 360, 2400.0, 480
+    pos = torch.as_tensor(synth.zeldovich(n_side, box, 7, dtype=np.float32), device="cuda")
+    npart = pos.shape[0]
+    est = est_mod.Estimator(n, box, 4, True, 1, npart)
+    n_bins = n // 2
+    k = torch.empty((1, n_bins), dtype=torch.float64, device="cuda")
+    pk = torch.empty_like(k)
+    nm = torch.empty((1, n_bins), dtype=torch.int64, device="cuda")
+
+    def step():
+        F.estimator_deposit(est.h, pos, F.EST_F32, None, npart)
+        F.estimator_transform(est.h)
+        F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
+
+    choice = est.autotune(pos, n_bins=n_bins, iters=2)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.estimator_profile(est.h, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F.estimator_profile(est.h, 0)
+    prof = F.profile_table(est.h)
+    est.close()
+    log("paper ZA 480^3: %.3f ms per step" % (1e3 * dt / args.steps))
+    nkeys = (n // 4) ** 3 + 1
+    frac = {}
+    for kname, (kms, kcnt) in prof.items():
+        b = algorithmic_bytes(kname, npart, n, n, 2, nkeys)
+        if b:
+            frac[kname] = round(b / (kms / kcnt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    return {"value": round(npart * args.steps / dt / 1e6, 2), "unit": "Mparticles/s",
+            "ms_per_step": round(1e3 * dt / args.steps, 4), "launch_choice": choice,
+            "stage_ms": {kname: round(v[0] / v[1], 4) for kname, v in prof.items()},
+            "stage_hbm_frac": frac,
+            "config": {"workload": "360^3 Zel'dovich particles, L=2400, 480^3 grid (mixed radix), "
+                                   "PCS + interlacing, P(k) in k_f shells to Nyquist (240 bins)",
+                       "n_particles": npart}}
+
+
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
@@ -347,6 +395,7 @@ def main():
         extra["batched"] = batched(args, torch, F, est_mod, synth)
         extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth)
         extra["direct_sum"] = direct_leg(args, torch, est_mod, synth)
+        extra["paper_za_480"] = paper_za_leg(args, torch, F, est_mod, synth)
     out = {
         "metric": "Mparticles/s end-to-end P(k), PCS+interlace 1024^3 grid; fwd+bwd & batched vs plain",
         "value": round(head["value"], 2),

@@ -57,7 +57,7 @@ typedef enum {
   EST_ENOMEM = 2,       /* workspace too small / size overflow               */
   EST_ESTATE = 3,       /* call out of order (e.g. power before transform)   */
   EST_EDEVICE = 4,      /* HIP runtime or kernel launch failure              */
-  EST_EUNSUPPORTED = 5  /* valid but not implemented (e.g. N not 2^k)        */
+  EST_EUNSUPPORTED = 5  /* valid but not implemented (e.g. N = 28)            */
 } est_status;
 
 typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
@@ -65,16 +65,20 @@ typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
 /* est_config.flags.  Particles are bucket-sorted (4^3-cell buckets) before
  * the deposit.  By default the sort works in two levels without
  * device-scope atomics: per-workgroup histograms over super-buckets of
- * 16^3 buckets, then one workgroup per super-bucket.  That workgroup count
+ * up to 16^3 buckets (the edge is the largest divisor of N/4 up to 16),
+ * then one workgroup per super-bucket.  That workgroup count
  * bounds the second level, so for strongly clustered inputs (a large
- * fraction of all particles inside one 64^3-cell region) this flag selects
+ * fraction of all particles inside one super-bucket) this flag selects
  * the single-level counting sort with device-scope atomics instead.  The
- * atomic sort is also used whenever batch * (N/64)^3 exceeds 8192.  Both
+ * atomic sort is also used whenever batch times the number of super-buckets
+ * exceeds 8192.  Both
  * give identical grids. */
 #define EST_FLAG_ATOMIC_SORT 1
 
 typedef struct {
-  int32_t n_grid;        /* N: power of two in [8, 1024]                       */
+  int32_t n_grid;        /* N in [8, 1024], a multiple of 4 of the form        */
+                         /* 2^a 3^b 5^c (e.g. 100, 480, 800: mixed-radix FFT); */
+                         /* above 16 also N >= 15 + order                      */
   int32_t order;         /* p = 1..6: NGP, CIC, TSC, PCS (Sec. 2.3), then the  */
                          /* order-5/6 B-splines (p-fold box convolutions)      */
   int32_t interlace;     /* 0 or 1: second grid shifted by H/2 (Sec. 3.1)     */
@@ -86,8 +90,8 @@ typedef struct {
 } est_config;
 
 /* Bytes of device workspace a handle with this configuration needs.
- * Host only.  EINVAL for an invalid config, EUNSUPPORTED for N not a power of
- * two in [8, 1024], ENOMEM if the size overflows. */
+ * Host only.  EINVAL for an invalid config, EUNSUPPORTED for an N outside
+ * the set above, ENOMEM if the size overflows. */
 est_status estimator_workspace_bytes(const est_config* cfg, size_t* bytes);
 
 /* Create a handle.  `workspace` is a device pointer to at least

@@ -32,7 +32,13 @@ est_status ok() { return EST_OK; }
 
 enum State { kCreated = 0, kDeposited = 1, kXY = 2, kSpectrum = 3 };
 
-bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+// no prime factor above 5
+bool smooth235(int v) {
+  if (v < 1) return false;
+  for (int p : {2, 3, 5})
+    while (v % p == 0) v /= p;
+  return v == 1;
+}
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -129,8 +135,13 @@ est_status check_config(const est_config* c) {
     return fail(EST_EINVAL, "max_particles must be 1..2^31-1");
   if ((c->flags & ~EST_FLAG_ATOMIC_SORT) != 0 || c->reserved != 0)
     return fail(EST_EINVAL, "flags must be 0 or EST_FLAG_ATOMIC_SORT and reserved 0");
-  if (!pow2(c->n_grid) || c->n_grid < 8 || c->n_grid > 1024)
-    return fail(EST_EUNSUPPORTED, "n_grid must be a power of two in [8, 1024] (got %d)", c->n_grid);
+  if (c->n_grid < 8 || c->n_grid > 1024 || c->n_grid % kBucket != 0 || !smooth235(c->n_grid))
+    return fail(EST_EUNSUPPORTED,
+                "n_grid must be a multiple of 4 in [8, 1024] with prime factors 2, 3, 5 only (got %d)",
+                c->n_grid);
+  if (c->n_grid > kTileMax && c->n_grid < kTileMax + c->order - 1)
+    return fail(EST_EUNSUPPORTED, "n_grid = %d is too small for a tiled deposit of order %d",
+                c->n_grid, c->order);
   const int64_t nb = c->n_grid / kBucket;
   if ((int64_t)c->batch * nb * nb * nb + 1 >= 4294967295LL)
     return fail(EST_EINVAL, "batch * (N/4)^3 exceeds the 32-bit bucket index");
@@ -145,7 +156,11 @@ Geom make_geom(const est_config& c) {
   g.il = c.interlace;
   g.batch = c.batch;
   g.nb = c.n_grid / kBucket;
-  g.fb = g.nb < kFineMax ? g.nb : kFineMax;
+  // largest divisor of nb up to kFineMax (at least 5 whenever nb > kFineMax,
+  // since nb has no prime factor above 5), so super-buckets tile the axis
+  g.fb = 1;
+  for (int d = 1; d <= kFineMax && d <= g.nb; ++d)
+    if (g.nb % d == 0) g.fb = d;
   g.sa = g.nb / g.fb;
   const int64_t nsup = (int64_t)c.batch * g.sa * g.sa * g.sa;
   // the two-level sort runs when nsup <= kMaxSuper; a larger value selects the atomic sort

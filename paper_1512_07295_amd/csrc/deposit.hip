@@ -61,8 +61,10 @@ __device__ __forceinline__ void load_pos(const TP* pos, int64_t j, double& x, do
   z = (double)pos[3 * j + 2];
 }
 
+// floor(u) mod N for u in [0, N] (u = N can come out of the rounding of x N / L)
 __device__ __forceinline__ int base_cell(double u, int n) {
-  return ((int)floor(u)) & (n - 1);
+  const int c = (int)floor(u);
+  return c >= n ? c - n : c;
 }
 
 // ------------------------------------------------------------------ sort
@@ -136,7 +138,8 @@ __device__ __forceinline__ uint64_t cell_record(double ux, double uy, double uz,
     const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
     const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
     const double f2 = even ? floor(u2) : floor(u2 + 0.5);
-    rec |= (uint64_t)((int)f1 & (g.n - 1)) << (16 * a);
+    const int c1 = (int)f1;  // in [0, N]
+    rec |= (uint64_t)(c1 >= g.n ? c1 - g.n : c1) << (16 * a);
     rec |= (uint64_t)((int)(f2 - f1) & 1) << (48 + a);
   }
   return rec;
@@ -570,8 +573,12 @@ __device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], floa
     float wd[P];
     bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, wd);
   }
+  // first + i lies in [-(p-1), N + p - 1]
 #pragma unroll
-  for (int i = 0; i < P; ++i) cell[i] = (first + i) & (n - 1);
+  for (int i = 0; i < P; ++i) {
+    const int c = first + i;
+    cell[i] = c < 0 ? c + n : (c >= n ? c - n : c);
+  }
 }
 
 // derivative dW/ds of the same weights (s = cell - u)
@@ -711,15 +718,22 @@ __device__ __forceinline__ int first_cell(double u) {
   return (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
 }
 
-// Position of a stencil's first cell relative to the tile origin t0.  For a
-// tile smaller than the grid the result lies in [-(P-1), n - P + 1) and the
-// stencil reaches the tile iff it is < T; for a tile that is the whole grid
-// it lies in [0, n).
+// Position of a stencil's first cell relative to the tile origin t0, mod N.
+// For a tile smaller than the grid the result lies in [-(P-1), n - P + 1)
+// and the stencil reaches the tile's LDS block iff it is < kTileMax (which
+// needs N >= kTileMax + P - 1); for a tile that is the whole grid (t0 = 0)
+// it lies in [0, n).  `first` is a record cell (in [0, N)) minus the stencil
+// offset plus the interlacing step, so first - t0 lies in [-(P-1) - N + 1, N].
 template <int P, bool PERIODIC>
 __device__ __forceinline__ int rel_first(int first, int t0, int n) {
-  const int r = (first - t0) & (n - 1);
-  if constexpr (PERIODIC) return r;
-  else return (r >= n - (P - 1)) ? r - n : r;
+  int r = first - t0;
+  if constexpr (PERIODIC) {
+    r = r < 0 ? r + n : r;
+    return r >= n ? r - n : r;
+  } else {
+    r = r < -(P - 1) ? r + n : r;
+    return (r >= n - (P - 1)) ? r - n : r;
+  }
 }
 
 template <int P, bool PERIODIC>
@@ -753,10 +767,10 @@ __device__ __forceinline__ void deposit_item(double x, double y, double z, int g
     AT* zrow = sm + region + rz + zhalo<P>();
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const int xo = ((rx + i) & (n - 1)) * kPlane;
+      const int xo = (rx + i >= n ? rx + i - n : rx + i) * kPlane;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        AT* row = zrow + xo + ((ry + k) & (n - 1)) * kRow;
+        AT* row = zrow + xo + (ry + k >= n ? ry + k - n : ry + k) * kRow;
         const float wxy = wx[i] * wy[k];
 #pragma unroll
         for (int l = 0; l < P; ++l)
@@ -843,7 +857,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   const double inv_scale = 1.0 / (double)scale;
 
   const int n = g.n, T = g.tile, nb = g.nb;
-  const int tpa = n / T;  // tiles per axis
+  const int tpa = (n + T - 1) / T;  // tiles per axis; the last one is ragged when T does not divide N
   const int64_t tiles_per_set = (int64_t)tpa * tpa * tpa;
   const int64_t ntiles = (int64_t)g.batch * tiles_per_set;
   const int nthreads = blockDim.x;
@@ -863,6 +877,8 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     const int trem = (int)(tid_all % tiles_per_set);
     const int tx = trem / (tpa * tpa), ty = (trem / tpa) % tpa, tz = trem % tpa;
     const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
+    // cells of this tile per axis (a multiple of kBucket)
+    const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
 
     if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) fill = 0;
@@ -1084,6 +1100,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
       const float inv_f = (float)inv_scale;
       for (int i = threadIdx.x; i < TT * TT * TT / 4; i += nthreads) {
         const int lx = i / (TT * TT / 4), ly = (i / (TT / 4)) % TT, lz = (i % (TT / 4)) * 4;
+        if (lx >= ex || ly >= ey || lz >= ez) continue;  // outside a ragged tile
         float v[NG][4];
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
@@ -1138,7 +1155,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
 template <int P, bool IL, typename TP, bool PER>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
                            hipStream_t s) {
-  const int tpa = g.n / g.tile;
+  const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   if (narrow)
     hipLaunchKernelGGL((k_deposit<P, IL, TP, false, PER>), dim3((unsigned)ntiles), dim3(threads),

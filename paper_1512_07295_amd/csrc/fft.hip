@@ -7,7 +7,8 @@
 //   x, y (strided): k_fft_cols, C adjacent lines per workgroup so that every
 //                   global access is a run of C complex values (C*8 bytes),
 //                   lines interleaved in LDS.
-// Every workgroup owns its lines, so the passes run in place.
+// Every workgroup owns its lines, so the passes run in place.  Lengths with
+// factors 3 and 5 take the run-time-planned kernels (k_*_rt).
 #include "fft_line.hpp"
 #include "fsest_internal.hpp"
 
@@ -88,6 +89,101 @@ static hipError_t cols_t(float2* data, int64_t elem_stride, int64_t inner, int64
   return cols_tc<L, DIR, 4>(data, elem_stride, inner, outer, outer_stride, tw, s);
 }
 
+// ---- lengths 2^a 3^b 5^c (run-time plan) ----
+// rows: lpb = 256 / tpl lines per workgroup, padded rows in LDS (at most
+// (256 / tpl) (L + L/16 + 1) <= 4608 elements since L <= 16 tpl)
+constexpr int kRtRowsLds = 4608;
+
+template <int DIR>
+__global__ __launch_bounds__(256) void k_fft_rows_rt(float2* __restrict__ data, int64_t nrows,
+                                                     int rows_per_plane, int64_t plane_stride,
+                                                     const float2* __restrict__ tw, RtLine pl) {
+  __shared__ float2 lds[kRtRowsLds];
+  const int L = pl.L, tpl = pl.tpl;
+  const int lpb = 256 / tpl;
+  const int rowp = L + L / 16 + 1;
+  const int line = threadIdx.x / tpl, t = threadIdx.x % tpl;
+  const int64_t row = (int64_t)blockIdx.x * lpb + line;
+  const bool valid = row < nrows;
+  float2* p = data + (row / rows_per_plane) * plane_stride + (row % rows_per_plane) * L;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = t + e * tpl;
+    v[e] = (valid && j < L) ? p[j] : make_float2(0.f, 0.f);
+  }
+  line_fft_rt<DIR, 1>(v, t, lds + line * rowp, pl, tw);
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int j = t + e * tpl;
+      if (j < L) p[j] = v[e];
+    }
+  }
+}
+
+// strided lines: C adjacent lines per workgroup, interleaved in LDS; the
+// last chunk of a row may be partial (lines past `inner` load zeros and are
+// not stored)
+template <int DIR, int C>
+__global__ __launch_bounds__(1024) void k_fft_cols_rt(float2* __restrict__ data, int64_t elem_stride,
+                                                      int64_t inner, int64_t chunks_per_outer,
+                                                      int64_t outer_stride,
+                                                      const float2* __restrict__ tw, RtLine pl) {
+  extern __shared__ float2 lds_dyn[];
+  const int L = pl.L, tpl = pl.tpl;
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t outer = blockIdx.x / chunks_per_outer;
+  const int64_t ic = blockIdx.x % chunks_per_outer;
+  const bool valid = ic * C + c < inner;
+  float2* p = data + outer * outer_stride + ic * C + c;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = t + e * tpl;
+    v[e] = (valid && j < L) ? p[(int64_t)j * elem_stride] : make_float2(0.f, 0.f);
+  }
+  line_fft_rt<DIR, C>(v, t, lds_dyn + c, pl, tw);
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int j = t + e * tpl;
+      if (j < L) p[(int64_t)j * elem_stride] = v[e];
+    }
+  }
+}
+
+template <int DIR>
+static hipError_t rows_rt(int L, float2* data, int64_t nrows, int rpp, int64_t ps, const float2* tw,
+                          hipStream_t s) {
+  RtLine pl;
+  if (!make_rt_line(L, &pl)) return hipErrorInvalidValue;
+  const int lpb = 256 / pl.tpl;
+  const unsigned blocks = (unsigned)((nrows + lpb - 1) / lpb);
+  hipLaunchKernelGGL((k_fft_rows_rt<DIR>), dim3(blocks), dim3(lpb * pl.tpl), 0, s, data, nrows, rpp,
+                     ps, tw, pl);
+  return hipGetLastError();
+}
+
+template <int DIR>
+static hipError_t cols_rt(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                          int64_t outer_stride, const float2* tw, hipStream_t s) {
+  constexpr int C = 16;  // 16 * tpl <= 1024 threads and 16 L <= 16384 elements of LDS
+  RtLine pl;
+  if (!make_rt_line(L, &pl) || C * pl.tpl > 1024) return hipErrorInvalidValue;
+  const int64_t chunks = (inner + C - 1) / C;
+  const size_t lds = sizeof(float2) * (size_t)L * C;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_fft_cols_rt<DIR, C>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * 1024 * C));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_fft_cols_rt<DIR, C>), dim3((unsigned)(chunks * outer)), dim3(C * pl.tpl),
+                     lds, s, data, elem_stride, inner, chunks, outer_stride, tw, pl);
+  return hipGetLastError();
+}
+
 template <int DIR>
 static hipError_t rows_dir(int L, float2* data, int64_t nrows, int rpp, int64_t ps,
                            const float2* tw, hipStream_t s) {
@@ -101,7 +197,7 @@ static hipError_t rows_dir(int L, float2* data, int64_t nrows, int rpp, int64_t 
     case 256: return rows_t<256, DIR>(data, nrows, rpp, ps, tw, s);
     case 512: return rows_t<512, DIR>(data, nrows, rpp, ps, tw, s);
     case 1024: return rows_t<1024, DIR>(data, nrows, rpp, ps, tw, s);
-    default: return hipErrorInvalidValue;
+    default: return rows_rt<DIR>(L, data, nrows, rpp, ps, tw, s);
   }
 }
 
@@ -117,7 +213,7 @@ static hipError_t cols_dir(int L, float2* data, int64_t elem_stride, int64_t inn
     case 256: return cols_t<256, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
     case 512: return cols_t<512, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
     case 1024: return cols_t<1024, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    default: return hipErrorInvalidValue;
+    default: return cols_rt<DIR>(L, data, elem_stride, inner, outer, outer_stride, tw, s);
   }
 }
 

@@ -160,4 +160,154 @@ __device__ __forceinline__ void line_fft(float2 (&v)[LinePlan<L>::EPT], int t, f
   fft_stage<L, DIR, LS, 1>(v, t, lb, tw);
 }
 
+// ---------------------------------------------------------------- mixed radix
+// Lengths L = 2^a 3^b 5^c that are not powers of two use a plan chosen at
+// run time: Stockham stages of radix 16, 8, 4, 2 (the power-of-two part,
+// largest first) then 3 and 5, the line held by tpl = ceil(L / 16) threads.
+// Thread t holds elements t + e * tpl (e < 16, element < L) in registers on
+// entry and exit, as for the power-of-two lines; between stages the line
+// lives in LDS in natural order, each thread reading the inputs of its
+// butterflies (at most ceil(16 / R) of radix R), then, after a barrier,
+// writing their outputs.
+constexpr int kRtMaxStages = 12;
+struct RtLine {
+  int L;
+  int tpl;
+  int nst;
+  int radix[kRtMaxStages];
+};
+
+// radix-3 and radix-5 DFTs, natural order, sign DIR in the exponent
+template <int DIR>
+__device__ __forceinline__ void dft3(float2* a) {
+  constexpr float s3 = DIR * 0.86602540378443865f;  // sin(2 pi / 3)
+  const float2 t1 = cadd(a[1], a[2]);
+  const float2 d = csub(a[1], a[2]);
+  const float2 m = make_float2(a[0].x - 0.5f * t1.x, a[0].y - 0.5f * t1.y);
+  const float2 r = make_float2(-s3 * d.y, s3 * d.x);  // i s3 (a1 - a2)
+  a[0] = cadd(a[0], t1);
+  a[1] = cadd(m, r);
+  a[2] = csub(m, r);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft5(float2* a) {
+  constexpr float c1 = 0.30901699437494742f;   // cos(2 pi / 5)
+  constexpr float c2 = -0.80901699437494742f;  // cos(4 pi / 5)
+  constexpr float s1 = DIR * 0.95105651629515357f;  // sin(2 pi / 5)
+  constexpr float s2 = DIR * 0.58778525229247313f;  // sin(4 pi / 5)
+  const float2 b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+  const float2 d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+  const float2 m1 = make_float2(a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y);
+  const float2 m2 = make_float2(a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y);
+  // i (s1 d1 + s2 d2) and i (s2 d1 - s1 d2)
+  const float2 r1 = make_float2(-(s1 * d1.y + s2 * d2.y), s1 * d1.x + s2 * d2.x);
+  const float2 r2 = make_float2(-(s2 * d1.y - s1 * d2.y), s2 * d1.x - s1 * d2.x);
+  a[0] = cadd(a[0], cadd(b1, b2));
+  a[1] = cadd(m1, r1);
+  a[4] = csub(m1, r1);
+  a[2] = cadd(m2, r2);
+  a[3] = csub(m2, r2);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_any(float2* a) {
+  if constexpr (R == 3) dft3<DIR>(a);
+  else if constexpr (R == 5) dft5<DIR>(a);
+  else Dft<R, DIR>::run(a);
+}
+
+// One Stockham stage of radix R over a line of length L in LDS, after
+// sub-transforms of length ns: butterfly j reads elements j + q L/R, applies
+// the twiddles w^(q k), k = j mod ns, w = exp(DIR 2 pi i / (ns R)), and writes
+// its outputs to (j - k) R + k + q ns.
+template <int R, int DIR, int LS>
+__device__ __forceinline__ void rt_stage(float2* lb, int t, int tpl, int L, int ns,
+                                         const float2* __restrict__ tw) {
+  constexpr int NB = (16 + R - 1) / R;
+  const int nbf = L / R;
+  const int step = L / (ns * R);
+  float2 a[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * tpl;
+    if (j < nbf) {
+      const int k = j % ns;
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[i][q] = lb[lds_index<LS>(j + q * nbf)];
+      if (ns > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 w = tw[q * k * step];
+          if constexpr (DIR > 0) w.y = -w.y;
+          a[i][q] = cmul(a[i][q], w);
+        }
+      }
+      dft_any<R, DIR>(a[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int j = t + i * tpl;
+    if (j < nbf) {
+      const int k = j % ns;
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) lb[lds_index<LS>(base + q * ns)] = a[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Whole-line FFT of a run-time plan; every thread of the workgroup calls it.
+template <int DIR, int LS>
+__device__ __forceinline__ void line_fft_rt(float2 (&v)[16], int t, float2* lb, const RtLine& pl,
+                                            const float2* __restrict__ tw) {
+  const int L = pl.L, tpl = pl.tpl;
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    if (t + e * tpl < L) lb[lds_index<LS>(t + e * tpl)] = v[e];
+  __syncthreads();
+  int ns = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int r = pl.radix[s];
+    switch (r) {
+      case 16: rt_stage<16, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      case 8: rt_stage<8, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      case 4: rt_stage<4, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      case 2: rt_stage<2, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      case 3: rt_stage<3, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      default: rt_stage<5, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+    }
+    ns *= r;
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    if (t + e * tpl < L) v[e] = lb[lds_index<LS>(t + e * tpl)];
+  __syncthreads();
+}
+
+// Plan for length L (host and device); false if L has a prime factor above 5.
+__host__ __device__ inline bool make_rt_line(int L, RtLine* pl) {
+  if (L < 2) return false;
+  int rem = L, p2 = 1;
+  while (rem % 2 == 0) { rem /= 2; p2 *= 2; }
+  int nst = 0;
+  int r[kRtMaxStages];
+  while (p2 > 1) {
+    const int q = p2 >= 16 ? 16 : p2;
+    r[nst++] = q;
+    p2 /= q;
+  }
+  while (rem % 3 == 0) { rem /= 3; r[nst++] = 3; }
+  while (rem % 5 == 0) { rem /= 5; r[nst++] = 5; }
+  if (rem != 1 || nst > kRtMaxStages) return false;
+  pl->L = L;
+  pl->tpl = (L + 15) / 16;
+  pl->nst = nst;
+  for (int i = 0; i < kRtMaxStages; ++i) pl->radix[i] = i < nst ? r[i] : 1;
+  return true;
+}
+
 }  // namespace fsest

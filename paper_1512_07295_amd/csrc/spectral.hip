@@ -56,6 +56,21 @@ hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s) {
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int signed_freq(int i, int n) { return (i <= n / 2) ? i : i - n; }
 
+// -i mod n for 0 <= i < n (a mask when n is a compile-time power of two)
+template <bool P2>
+__device__ __forceinline__ int neg_mod(int i, int n) {
+  if constexpr (P2) return (n - i) & (n - 1);
+  else return i ? n - i : 0;
+}
+// s mod 2n for -2n <= s < 4n: index into the table exp(+i pi s / N)
+template <bool P2>
+__device__ __forceinline__ int mod_2n(int s, int n) {
+  if constexpr (P2) return s & (2 * n - 1);
+  else return s < 0 ? s + 2 * n : (s >= 2 * n ? s - 2 * n : s);
+}
+// FFT index of signed frequency m, |m| < n
+__device__ __forceinline__ int fft_index(int m, int n) { return m < 0 ? m + n : m; }
+
 // shell b with (2b-1)^2 n^2 <= 4 m2 < (2b+1)^2 n^2 (b = 0 below the first shell)
 __device__ __forceinline__ int shell_of(int m2, int n_dk) {
   const int x = 4 * m2;
@@ -79,18 +94,18 @@ __device__ __forceinline__ void pair_rows(int64_t q, int n, int& x, int& y) {
 
 // Transforms of the real grids at half-space mode (row, mz) from the pair
 // (Za, Zb) = (Z(k), Z(-k)), combined per eq. intdelta: returns C(m).
-template <bool IL>
+template <bool IL, bool P2 = true>
 __device__ __forceinline__ float2 combined_mode(float2 za, float2 zb, int mx, int my, int mz,
                                                 const float2* __restrict__ phase, int n) {
   // first and second real transforms: (za + conj zb)/2 and (za - conj zb)/(2i)
   const float2 f1 = make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y));
   const float2 f2 = make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x));
   if constexpr (IL) {
-    const float2 ph = phase[(mx + my + mz) & (2 * n - 1)];  // exp(+i pi (mx+my+mz)/N)
+    const float2 ph = phase[mod_2n<P2>(mx + my + mz, n)];  // exp(+i pi (mx+my+mz)/N)
     return cscale(cadd(f1, cmul(ph, f2)), 0.5f);
   } else {
     // even/odd z samples: F = E + exp(-2 pi i mz/N) O
-    const float2 ph = cconj(phase[(2 * mz) & (2 * n - 1)]);
+    const float2 ph = cconj(phase[mod_2n<P2>(2 * mz, n)]);
     return cadd(f1, cmul(ph, f2));
   }
 }
@@ -113,7 +128,19 @@ struct PairShape {
   static constexpr int PPB = (256 / (2 * TPL)) > 0 ? (256 / (2 * TPL)) : 1;
   static constexpr int THREADS = PPB * 2 * TPL;
   static constexpr int ROWP = LdsLine<L>::padded;
+  static constexpr int EPT = LinePlan<L>::EPT;
+  static constexpr int ROWS_LDS = 2 * PPB * ROWP;
 };
+// L = 0: row length 2^a 3^b 5^c with a run-time plan (tpl = ceil(L/16)
+// threads per row, 16 elements per thread); PPB = max(1, 128 / tpl) pairs,
+// so 2 PPB (L + L/16 + 1) <= 4608 elements as for the FFT rows
+template <>
+struct PairShape<0> {
+  static constexpr int THREADS = 256;
+  static constexpr int EPT = 16;
+  static constexpr int ROWS_LDS = 4608;
+};
+__host__ __device__ inline int rt_pairs_per_block(int tpl) { return 128 / tpl > 0 ? 128 / tpl : 1; }
 
 // MODE 0: forward z FFT + P(k) shell sums; MODE 1: shell sums of a stored
 // spectrum; MODE 2: forward z FFT, adjoint spectrum, inverse z FFT, write.
@@ -121,12 +148,22 @@ template <int L, bool IL, int MODE>
 __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     float2* __restrict__ data, Geom g, const float2* __restrict__ tw,
     const float2* __restrict__ phase, const float* __restrict__ inv_w2, int n_dk, int n_bins,
-    double* __restrict__ partials, const double* __restrict__ coef) {
-  constexpr int TPL = PairShape<L>::TPL;
-  constexpr int PPB = PairShape<L>::PPB;
-  constexpr int ROWP = PairShape<L>::ROWP;
-  constexpr int EPT = LinePlan<L>::EPT;
-  __shared__ float2 rows[2 * PPB * ROWP];
+    double* __restrict__ partials, const double* __restrict__ coef, RtLine rt) {
+  constexpr bool P2 = L != 0;  // compile-time power-of-two row length
+  constexpr int EPT = PairShape<L>::EPT;
+  int TPL, PPB, ROWP, LL;
+  if constexpr (P2) {
+    TPL = PairShape<L>::TPL;
+    PPB = PairShape<L>::PPB;
+    ROWP = PairShape<L>::ROWP;
+    LL = L;
+  } else {
+    TPL = rt.tpl;
+    PPB = rt_pairs_per_block(rt.tpl);
+    ROWP = rt.L + rt.L / 16 + 1;
+    LL = rt.L;
+  }
+  __shared__ float2 rows[PairShape<L>::ROWS_LDS];
   __shared__ double hist[kMaxBins];
   // per half-space z index: the z part of the phase and 1/W^2
   __shared__ float4 ztab[MODE != 2 ? kMaxBins + 1 : 1];
@@ -145,7 +182,7 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
     for (int i = threadIdx.x; i <= n / 2; i += blockDim.x) {
       // interlaced: exp(+i pi mz/N); packed: exp(-2 pi i mz/N)
-      const float2 ph = IL ? phase[i] : cconj(phase[(2 * i) & (2 * n - 1)]);
+      const float2 ph = IL ? phase[i] : cconj(phase[mod_2n<P2>(2 * i, n)]);
       ztab[i] = make_float4(ph.x, ph.y, inv_w2[i], 0.0f);
     }
   }
@@ -155,14 +192,23 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     const bool valid = q < npairs;
     int xa = 0, ya = 0;
     if (valid) pair_rows(q, n, xa, ya);
-    const int xb = (n - xa) & (n - 1), yb = (n - ya) & (n - 1);
+    const int xb = neg_mod<P2>(xa, n), yb = neg_mod<P2>(ya, n);
     const bool self = (xa == xb) && (ya == yb);
     const int xr = r ? xb : xa, yr = r ? yb : ya;
-    float2* gp = data + ((int64_t)mock * n + xr) * g.ps + (int64_t)yr * L;
+    float2* gp = data + ((int64_t)mock * n + xr) * g.ps + (int64_t)yr * LL;
     float2 v[EPT];
-    static_for<0, EPT>([&](auto e) { v[e] = valid ? gp[t + e * TPL] : make_float2(0.f, 0.f); });
-    if constexpr (MODE != 1) line_fft<L, -1, 1>(v, t, own_lds, tw);
-    static_for<0, EPT>([&](auto e) { own_lds[lds_index<1>(t + e * TPL)] = v[e]; });
+    static_for<0, EPT>([&](auto e) {
+      const int j = t + e * TPL;
+      v[e] = (valid && (P2 || j < LL)) ? gp[j] : make_float2(0.f, 0.f);
+    });
+    if constexpr (MODE != 1) {
+      if constexpr (P2) line_fft<L, -1, 1>(v, t, own_lds, tw);
+      else line_fft_rt<-1, 1>(v, t, own_lds, rt, tw);
+    }
+    static_for<0, EPT>([&](auto e) {
+      const int j = t + e * TPL;
+      if (P2 || j < LL) own_lds[lds_index<1>(j)] = v[e];
+    });
     __syncthreads();
 
     const int mxr = signed_freq(xr, n), myr = signed_freq(yr, n);
@@ -177,7 +223,7 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
         const int z1 = min(z0 + per, nm);
         if (z0 < z1) {
           const float wxy = inv_w2[xr] * inv_w2[yr] * (IL ? 0.0625f : 0.25f);
-          const float2 ph_xy = IL ? phase[(mxr + myr) & (2 * n - 1)] : make_float2(1.0f, 0.0f);
+          const float2 ph_xy = IL ? phase[mod_2n<P2>(mxr + myr, n)] : make_float2(1.0f, 0.0f);
           const int r2 = mxr * mxr + myr * myr;
           const int m2_0 = r2 + z0 * z0;
           int b = m2_0 ? shell_of(m2_0, n_dk) : 0;
@@ -197,12 +243,12 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
             float2 za, zb;
             if constexpr (IL) {
               za = own_lds[lds_index<1>(mz)];
-              zb = par_lds[lds_index<1>((n - mz) & (n - 1))];
+              zb = par_lds[lds_index<1>(neg_mod<P2>(mz, n))];
             } else {
               const int h = n / 2;
-              const int kz = mz & (h - 1);
+              const int kz = (mz == h) ? 0 : mz;
               za = own_lds[lds_index<1>(kz)];
-              zb = par_lds[lds_index<1>((h - kz) & (h - 1))];
+              zb = par_lds[lds_index<1>(neg_mod<P2>(kz, h))];
             }
             const float4 zt = ztab[mz];
             const float2 ph = IL ? cmul(ph_xy, make_float2(zt.x, zt.y)) : make_float2(zt.x, zt.y);
@@ -230,18 +276,18 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
         float2 acc = make_float2(0.f, 0.f);
         if (valid) {
           if constexpr (IL) {
-            const float2 z1 = own_lds[lds_index<1>(j)];
-            const float2 z2 = par_lds[lds_index<1>((n - j) & (n - 1))];
+            const float2 z1 = (P2 || j < LL) ? own_lds[lds_index<1>(j)] : make_float2(0.f, 0.f);
+            const float2 z2 = (P2 || j < LL) ? par_lds[lds_index<1>(neg_mod<P2>(j, n))] : make_float2(0.f, 0.f);
             // (a) mode (own row, j) holds Z(m) = z1
             if (j <= n / 2) {
               const int m2 = mxr * mxr + myr * myr + j * j;
               const int b = m2 ? shell_of(m2, n_dk) : 0;
               if (b >= 1 && b <= n_bins) {
-                const float2 c = combined_mode<true>(z1, z2, mxr, myr, j, phase, n);
+                const float2 c = combined_mode<true, P2>(z1, z2, mxr, myr, j, phase, n);
                 const float wgt = (j == 0 || j == n / 2) ? 1.0f : 2.0f;
                 const float s = wgt * (float)cf[b - 1] * inv_w2[xr] * inv_w2[yr] * inv_w2[j];
                 const float2 gc = cscale(c, s);
-                const float2 ph = cconj(phase[(mxr + myr + j) & (2 * n - 1)]);
+                const float2 ph = cconj(phase[mod_2n<P2>(mxr + myr + j, n)]);
                 const float2 gf1 = cscale(gc, 0.5f);
                 const float2 gf2 = cscale(cmul(ph, gc), 0.5f);
                 // dZ(m): 1/2 gF1 + (i/2) gF2
@@ -249,16 +295,16 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
               }
             }
             // (b) mode (partner row, -j) holds Z(-m') = z1
-            const int jp = (n - j) & (n - 1);
-            if (jp <= n / 2) {
+            const int jp = neg_mod<P2>(j, n);
+            if ((P2 || j < LL) && jp <= n / 2) {
               const int m2 = mxp * mxp + myp * myp + jp * jp;
               const int b = m2 ? shell_of(m2, n_dk) : 0;
               if (b >= 1 && b <= n_bins) {
-                const float2 c = combined_mode<true>(z2, z1, mxp, myp, jp, phase, n);
+                const float2 c = combined_mode<true, P2>(z2, z1, mxp, myp, jp, phase, n);
                 const float wgt = (jp == 0 || jp == n / 2) ? 1.0f : 2.0f;
                 const float s = wgt * (float)cf[b - 1] * inv_w2[xp] * inv_w2[yp] * inv_w2[jp];
                 const float2 gc = cscale(c, s);
-                const float2 ph = cconj(phase[(mxp + myp + jp) & (2 * n - 1)]);
+                const float2 ph = cconj(phase[mod_2n<P2>(mxp + myp + jp, n)]);
                 const float2 gf1 = cscale(gc, 0.5f);
                 const float2 gf2 = cscale(cmul(ph, gc), 0.5f);
                 // dZ(-m'): 1/2 conj(gF1) + (i/2) conj(gF2)
@@ -267,35 +313,36 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
             }
           } else {
             const int h = n / 2;
-            const float2 z1 = own_lds[lds_index<1>(j)];
-            const float2 z2 = par_lds[lds_index<1>((h - j) & (h - 1))];
+            const bool inl = P2 || j < LL;
+            const float2 z1 = inl ? own_lds[lds_index<1>(j)] : make_float2(0.f, 0.f);
+            const float2 z2 = inl ? par_lds[lds_index<1>(neg_mod<P2>(j, h))] : make_float2(0.f, 0.f);
             // direct sources: modes (own row, mz) with mz = j (and mz = h when j = 0)
-            for (int k = 0; k < ((j == 0) ? 2 : 1); ++k) {
+            for (int k = 0; k < (!inl ? 0 : (j == 0) ? 2 : 1); ++k) {
               const int mz = k ? h : j;
               const int m2 = mxr * mxr + myr * myr + mz * mz;
               const int b = m2 ? shell_of(m2, n_dk) : 0;
               if (b >= 1 && b <= n_bins) {
-                const float2 c = combined_mode<false>(z1, z2, mxr, myr, mz, phase, n);
+                const float2 c = combined_mode<false, P2>(z1, z2, mxr, myr, mz, phase, n);
                 const float wgt = (mz == 0 || mz == h) ? 1.0f : 2.0f;
                 const float s = wgt * (float)cf[b - 1] * inv_w2[xr] * inv_w2[yr] * inv_w2[mz];
                 const float2 gf = cscale(c, s);
-                const float2 ph = phase[(2 * mz) & (2 * n - 1)];  // (cos, sin) of 2 pi mz/N
+                const float2 ph = phase[mod_2n<P2>(2 * mz, n)];  // (cos, sin) of 2 pi mz/N
                 // conj(a) = ((1 - sin), cos) / 2
                 const float2 ca = make_float2(0.5f * (1.0f - ph.y), 0.5f * ph.x);
                 acc = cadd(acc, cmul(ca, gf));
               }
             }
             // conjugate sources: modes (partner row, mz') with -mz' = j mod h (and h when j = 0)
-            for (int k = 0; k < ((j == 0) ? 2 : 1); ++k) {
-              const int mz = k ? h : ((h - j) & (h - 1));
+            for (int k = 0; k < (!inl ? 0 : (j == 0) ? 2 : 1); ++k) {
+              const int mz = k ? h : neg_mod<P2>(j, h);
               const int m2 = mxp * mxp + myp * myp + mz * mz;
               const int b = m2 ? shell_of(m2, n_dk) : 0;
               if (b >= 1 && b <= n_bins) {
-                const float2 c = combined_mode<false>(z2, z1, mxp, myp, mz, phase, n);
+                const float2 c = combined_mode<false, P2>(z2, z1, mxp, myp, mz, phase, n);
                 const float wgt = (mz == 0 || mz == h) ? 1.0f : 2.0f;
                 const float s = wgt * (float)cf[b - 1] * inv_w2[xp] * inv_w2[yp] * inv_w2[mz];
                 const float2 gf = cscale(c, s);
-                const float2 ph = phase[(2 * mz) & (2 * n - 1)];
+                const float2 ph = phase[mod_2n<P2>(2 * mz, n)];
                 // b = ((1 + sin), cos) / 2
                 const float2 bb = make_float2(0.5f * (1.0f + ph.y), 0.5f * ph.x);
                 acc = cadd(acc, cmul(bb, cconj(gf)));
@@ -306,9 +353,13 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
         out[e] = acc;
       });
       __syncthreads();
-      line_fft<L, +1, 1>(out, t, own_lds, tw);
+      if constexpr (P2) line_fft<L, +1, 1>(out, t, own_lds, tw);
+      else line_fft_rt<+1, 1>(out, t, own_lds, rt, tw);
       if (valid && !(r == 1 && self))
-        static_for<0, EPT>([&](auto e) { gp[t + e * TPL] = out[e]; });
+        static_for<0, EPT>([&](auto e) {
+          const int j = t + e * TPL;
+          if (P2 || j < LL) gp[j] = out[e];
+        });
       __syncthreads();
     }
   }
@@ -363,8 +414,16 @@ __global__ void k_adjoint_coef(const double* __restrict__ dldp, int n_bins, cons
 template <int L, bool IL, int MODE>
 static hipError_t pairs_t(const Geom& g, const Buffers& b, int nblk, int n_dk, int n_bins,
                           const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL((k_pairs<L, IL, MODE>), dim3(nblk, g.batch), dim3(PairShape<L>::THREADS), 0, s,
-                     b.grid, g, tw, b.phase, b.inv_w2, n_dk, n_bins, b.partials, b.coef);
+  RtLine rt{};
+  int threads = 0;
+  if constexpr (L == 0) {
+    if (!make_rt_line(g.nz, &rt)) return hipErrorInvalidValue;
+    threads = 2 * rt_pairs_per_block(rt.tpl) * rt.tpl;
+  } else {
+    threads = PairShape<L>::THREADS;
+  }
+  hipLaunchKernelGGL((k_pairs<L, IL, MODE>), dim3(nblk, g.batch), dim3(threads), 0, s,
+                     b.grid, g, tw, b.phase, b.inv_w2, n_dk, n_bins, b.partials, b.coef, rt);
   return hipGetLastError();
 }
 
@@ -376,7 +435,7 @@ static hipError_t pairs_dispatch(const Geom& g, const Buffers& b, int nblk, int 
   case LL:                                                                       \
     return g.il ? pairs_t<LL, true, MODE>(g, b, nblk, n_dk, n_bins, tw, s)       \
                 : pairs_t<LL, false, MODE>(g, b, nblk, n_dk, n_bins, tw, s);
-  switch (g.nz) {
+  switch ((g.nz & (g.nz - 1)) == 0 ? g.nz : 0) {
     FSEST_PAIRS_CASE(4)
     FSEST_PAIRS_CASE(8)
     FSEST_PAIRS_CASE(16)
@@ -386,7 +445,7 @@ static hipError_t pairs_dispatch(const Geom& g, const Buffers& b, int nblk, int 
     FSEST_PAIRS_CASE(256)
     FSEST_PAIRS_CASE(512)
     FSEST_PAIRS_CASE(1024)
-    default: return hipErrorInvalidValue;
+    FSEST_PAIRS_CASE(0)
   }
 #undef FSEST_PAIRS_CASE
 }
@@ -404,7 +463,8 @@ static int pair_blocks(const Geom& g, const Tune& tu) {
     case 128: ppb = PairShape<128>::PPB; break;
     case 256: ppb = PairShape<256>::PPB; break;
     case 512: ppb = PairShape<512>::PPB; break;
-    default: ppb = PairShape<1024>::PPB; break;
+    case 1024: ppb = PairShape<1024>::PPB; break;
+    default: ppb = rt_pairs_per_block((g.nz + 15) / 16); break;
   }
   int64_t groups = (npairs + ppb - 1) / ppb;
   int64_t nblk = tu.bin_blocks;
@@ -510,10 +570,10 @@ hipError_t launch_mode_table(const Geom& g, const Buffers& b, int n_dk, int n_bi
 __device__ void delta_at(const float2* __restrict__ data, const Geom& g, int mock, int mx, int my,
                          int mz, double npart, double& re, double& im) {
   const int n = g.n;
-  const int x = mx & (n - 1), y = my & (n - 1);
-  const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
+  const int x = ((mx % n) + n) % n, y = ((my % n) + n) % n;
+  const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n);
   const int L = g.nz;
-  const int z = mz & (L - 1), zm = (L - z) & (L - 1);
+  const int z = ((mz % L) + L) % L, zm = neg_mod<false>(z, L);
   const float2 za = data[complex_index(g, mock, x, y, z)];
   const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
   const double f1r = 0.5 * ((double)za.x + zb.x), f1i = 0.5 * ((double)za.y - zb.y);
@@ -683,13 +743,13 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
       if (counts_only) {
         d = make_float2(1.f, 0.f);
       } else {
-        const int xm = (n - x) & (n - 1), ym = (n - y) & (n - 1);
-        const int zz = mz & (L - 1), zm = (L - zz) & (L - 1);
+        const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n);
+        const int zz = ((mz % L) + L) % L, zm = neg_mod<false>(zz, L);
         const float2 za = data[complex_index(g, mock, x, y, zz)];
         const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
         float2 c;
-        if (g.il) c = combined_mode<true>(za, zb, mx, my, mz, phase, n);
-        else c = combined_mode<false>(za, zb, mx, my, mz, phase, n);
+        if (g.il) c = combined_mode<true, false>(za, zb, mx, my, mz, phase, n);
+        else c = combined_mode<false, false>(za, zb, mx, my, mz, phase, n);
         const float w = win1[x] * win1[y] * win1[z];
         d = cscale(c, inv_np / w);
       }

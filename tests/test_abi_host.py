@@ -66,7 +66,10 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(max_particles=1 << 31), fsest.EST_EINVAL),
     (dict(flags=2), fsest.EST_EINVAL),
     (dict(flags=-1), fsest.EST_EINVAL),
-    (dict(n_grid=100), fsest.EST_EUNSUPPORTED),
+    (dict(n_grid=28), fsest.EST_EUNSUPPORTED),   # prime factor 7
+    (dict(n_grid=90), fsest.EST_EUNSUPPORTED),   # not a multiple of the 4-cell bucket
+    (dict(n_grid=1020), fsest.EST_EUNSUPPORTED),  # prime factor 17
+    (dict(n_grid=20, order=6), fsest.EST_EUNSUPPORTED),  # N < 16 + p - 1 with 16-cell tiles
     (dict(n_grid=4), fsest.EST_EUNSUPPORTED),
     (dict(n_grid=2048), fsest.EST_EUNSUPPORTED),
     (dict(n_grid=1024, batch=300), fsest.EST_EINVAL),
@@ -127,6 +130,12 @@ def test_package_binds_to_one_hip_runtime():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("n", [12, 20, 24, 100, 480, 800, 960, 1000])
+def test_mixed_radix_grid_sizes_accepted(n):
+    """N = 2^a 3^b 5^c, a multiple of 4 (the paper's N_G = 100 and 480)."""
+    assert fsest.estimator_workspace_bytes(_cfg(n_grid=n)) > 2 * 4 * n ** 3
 
 
 def test_atomic_sort_flag_accepted_and_drops_two_level_buffers():

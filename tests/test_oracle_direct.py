@@ -17,7 +17,8 @@ import synth
 
 
 @pytest.mark.parametrize("n,n_p,offset", [(8, 4, (0.0, 0.0, 0.0)), (16, 4, (0.25, 0.5, 0.125)),
-                                          (16, 8, (0.5, 0.5, 0.5))])
+                                          (16, 8, (0.5, 0.5, 0.5)), (12, 4, (0.25, 0.5, 0.125)),
+                                          (20, 5, (0.5, 0.2, 0.0))])
 def test_lattice_closed_form(n, n_p, offset):
     """n_p^3 particles at (i + o) L / n_p: delta(m) = exp(-2 pi i m.o / n_p) if
     every component of m is a multiple of n_p, else 0."""

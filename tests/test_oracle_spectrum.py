@@ -32,7 +32,8 @@ def _full_grid_counts(n, n_dk, n_bins):
     return counts
 
 
-@pytest.mark.parametrize("n,n_dk", [(16, 1), (32, 1), (32, 2), (24, 3), (8, 1)])
+@pytest.mark.parametrize("n,n_dk", [(16, 1), (32, 1), (32, 2), (24, 3), (8, 1), (12, 1), (20, 2),
+                                   (30, 1)])
 def test_mode_counts_bruteforce(n, n_dk):
     nb = spectrum.max_bins(n, n_dk)
     counts, ksum = spectrum.mode_table(n, n_dk, nb)
@@ -58,10 +59,13 @@ def test_bin_index_edges():
     assert b2.tolist() == [0, 1, 1, 2, 2, 2, 3]
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
-@pytest.mark.parametrize("il", [False, True])
-def test_white_noise_expectation_monte_carlo(p, il):
-    n, box, n_p, reps = 16, 100.0, 2000, 120
+@pytest.mark.parametrize("p,il,n", [(1, False, 16), (1, True, 16), (2, False, 16), (2, True, 16),
+                                    (3, False, 16), (3, True, 16), (4, False, 16), (4, True, 16),
+                                    (4, True, 12), (2, False, 20), (3, True, 20)])
+def test_white_noise_expectation_monte_carlo(p, il, n):
+    """Also at N = 12 and 20 (factors 3 and 5): the oracle's FFT path has no
+    power-of-two assumption."""
+    box, n_p, reps = 100.0, 2000, 120
     mx, my, mz = spectrum.half_axes(n)
     m = np.stack(np.broadcast_arrays(mx, my, mz), axis=-1)
     m2 = (m ** 2).sum(-1)
