@@ -42,14 +42,15 @@ def chi2_loss(pk, target, counts):
     return float(np.sum(r * r / sigma2)), 2.0 * r / sigma2
 
 
-def grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp):
-    """dL/drho_a on the grids, for a given dL/dP_b.  Returns (u, [g1, g2])."""
-    n_p = pos.shape[0]
+def grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights=None):
+    """dL/drho_a on the grids, for a given dL/dP_b.  Returns (u, [g1, g2]).
+    With masses, N_P above is the total mass W (the masses are constants)."""
+    n_p = pos.shape[0] if weights is None else float(np.sum(np.asarray(weights, dtype=np.float64)))
     u = grid_coords(pos, box, n)
-    rho1 = deposit_u(u, p, n)
+    rho1 = deposit_u(u, p, n, weights)
     f1 = fft_grid(rho1)
     if interlace_on:
-        f2 = fft_grid(deposit_u(u + 0.5, p, n))
+        f2 = fft_grid(deposit_u(u + 0.5, p, n, weights))
         c = interlace(f1, f2, n)
     else:
         c = f1
@@ -78,10 +79,11 @@ def grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp):
     return u, grads
 
 
-def position_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp):
-    """dL/dx_j (N_P, 3) for a given dL/dP_b (n_bins,)."""
+def position_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights=None):
+    """dL/dx_j (N_P, 3) for a given dL/dP_b (n_bins,); a particle of mass
+    w_j deposits w_j times the kernel, so its gradient carries the factor w_j."""
     pos = np.asarray(pos)
-    u, grads = grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp)
+    u, grads = grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights)
     out = np.zeros((pos.shape[0], 3), dtype=np.float64)
     shifts = [0.0, 0.5][: len(grads)]
     for shift, gam in zip(shifts, grads):
@@ -104,4 +106,6 @@ def position_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp):
                     out[:, 0] += gv * dx[:, a] * wy[:, bq] * wz[:, cq]
                     out[:, 1] += gv * wx[:, a] * dy[:, bq] * wz[:, cq]
                     out[:, 2] += gv * wx[:, a] * wy[:, bq] * dz[:, cq]
+    if weights is not None:
+        out *= np.asarray(weights, dtype=np.float64)[:, None]
     return out * (-float(n) / float(box))

@@ -21,6 +21,10 @@ Sec. 3.1 (a second grid shifted by H/2 along every axis).  Readings:
 The density grid is rho[g] = sum_j prod_axes W^(p)(g_i - u_{j,i}); it sums to
 N_P.  The overdensity of eq. delgrid is rho / (N_P / N^3) - 1; the constant
 only affects the k = 0 mode, which no estimator uses.
+
+Weighted particles (the paper takes equal masses for simplicity, Sec. 2.1):
+particle j carries a mass w_j >= 0, rho[g] = sum_j w_j prod_axes W^(p)(...),
+which sums to W = sum_j w_j; unit weights give the equal-mass grid.
 """
 
 import numpy as np
@@ -75,13 +79,16 @@ def stencil(u, p, n_grid):
     return cells_i, w
 
 
-def deposit_u(u, p, n_grid):
-    """Deposit particles given their float64 grid coordinates u (n, 3)."""
+def deposit_u(u, p, n_grid, weights=None):
+    """Deposit particles given their float64 grid coordinates u (n, 3) and
+    optional masses (n,)."""
     n = n_grid
     cx, wx = stencil(u[:, 0], p, n)
     cy, wy = stencil(u[:, 1], p, n)
     cz, wz = stencil(u[:, 2], p, n)
     rho = np.zeros(n * n * n, dtype=np.float64)
+    if weights is not None:
+        wx = wx * np.asarray(weights, dtype=np.float64)[:, None]
     for a in range(p):
         for b in range(p):
             wab = wx[:, a] * wy[:, b]
@@ -92,16 +99,16 @@ def deposit_u(u, p, n_grid):
     return rho.reshape(n, n, n)
 
 
-def deposit(pos, box, n_grid, p, interlace):
+def deposit(pos, box, n_grid, p, interlace, weights=None):
     """Primary grid rho1 and (if ``interlace``) the H/2-shifted grid rho2.
 
-    ``pos`` is (N_P, 3) in any float dtype; it is promoted to float64.
-    Returns (rho1, rho2 or None), float64 arrays of shape (N, N, N) indexed
-    [x, y, z] with z fastest.
+    ``pos`` is (N_P, 3) in any float dtype; it is promoted to float64, as
+    are the optional masses ``weights`` (N_P,).  Returns (rho1, rho2 or
+    None), float64 arrays of shape (N, N, N) indexed [x, y, z] with z fastest.
     """
     u = grid_coords(pos, box, n_grid)
-    rho1 = deposit_u(u, p, n_grid)
-    rho2 = deposit_u(u + 0.5, p, n_grid) if interlace else None
+    rho1 = deposit_u(u, p, n_grid, weights)
+    rho2 = deposit_u(u + 0.5, p, n_grid, weights) if interlace else None
     return rho1, rho2
 
 

@@ -54,8 +54,9 @@ def footprint_dft(pos, box, n_grid, p, modes, shift=0.0, chunk=1 << 21):
     return out
 
 
-def delta_half_direct(pos, box, n, chunk=4096):
-    """N_P^-1 sum_j exp(-2 pi i m.x_j / L) on the half spectrum [n][n][n/2+1].
+def delta_half_direct(pos, box, n, chunk=4096, weights=None):
+    """N_P^-1 sum_j exp(-2 pi i m.x_j / L) on the half spectrum [n][n][n/2+1]
+    (with masses: W^-1 sum_j w_j exp(...), W = sum_j w_j).
 
     Entry (ix, iy, mz) is the mode (signed_index(n)[ix], signed_index(n)[iy],
     mz).  The exponential factorises over the axes, so for a chunk of
@@ -66,11 +67,14 @@ def delta_half_direct(pos, box, n, chunk=4096):
     m_full = signed_index(n).astype(np.float64)
     m_half = np.arange(n // 2 + 1, dtype=np.float64)
     out = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    w = None if weights is None else np.asarray(weights, dtype=np.float64)
     for s in range(0, len(pos), chunk):
         t = pos[s:s + chunk] / box
         ex = np.exp(-2j * np.pi * np.outer(m_full, t[:, 0]))
+        if w is not None:
+            ex = ex * w[s:s + chunk][None, :]
         ey = np.exp(-2j * np.pi * np.outer(m_full, t[:, 1]))
         ez = np.exp(-2j * np.pi * np.outer(m_half, t[:, 2]))
         exy = ex[:, None, :] * ey[None, :, :]
         out += np.matmul(exy.reshape(n * n, -1), ez.T).reshape(n, n, n // 2 + 1)
-    return out / len(pos)
+    return out / (len(pos) if w is None else w.sum())

@@ -125,10 +125,28 @@ def mode_table(n, n_dk, n_bins, planes=None):
     return counts[1:], ksum[1:]
 
 
-def delta_half(pos, box, n, p, interlace_on, workers=None):
-    """delta(m) on the half spectrum (steps 1-3 above) and N_P."""
-    n_p = pos.shape[0]
-    rho1, rho2 = deposit(pos, box, n, p, interlace_on)
+def total_weight(pos, weights):
+    """(W, sum w^2): N_P and N_P for equal masses."""
+    if weights is None:
+        return float(pos.shape[0]), float(pos.shape[0])
+    w = np.asarray(weights, dtype=np.float64)
+    return float(w.sum()), float((w * w).sum())
+
+
+def shot_noise(pos, box, weights=None):
+    """V sum w^2 / W^2 (V / N_P for equal masses): the self-pair term of
+    V |delta(k)|^2 for the weighted density."""
+    if weights is None:
+        return float(box) ** 3 / pos.shape[0]
+    wsum, w2sum = total_weight(pos, weights)
+    return float(box) ** 3 * w2sum / (wsum * wsum)
+
+
+def delta_half(pos, box, n, p, interlace_on, workers=None, weights=None):
+    """delta(m) on the half spectrum (steps 1-3 above) and the total mass W
+    (N_P for equal masses), which normalises it."""
+    n_p, _ = total_weight(pos, weights)
+    rho1, rho2 = deposit(pos, box, n, p, interlace_on, weights)
     f1 = fft_grid(rho1, workers)
     if interlace_on:
         f2 = fft_grid(rho2, workers)
@@ -182,16 +200,18 @@ def bin_cross(a, b, box, n, n_dk, n_bins, shot=0.0):
 
 
 def power(pos, box, n_grid, order, interlace_on, n_dk=1, n_bins=None,
-          subtract_shot=False, workers=None):
-    """Binned power spectrum of a particle set.
+          subtract_shot=False, workers=None, weights=None):
+    """Binned power spectrum of a particle set (optionally with masses).
 
     Returns (k_b [h/Mpc units of 1/box], P_b, N_b); P is raw unless
-    ``subtract_shot`` (then P_b - V/N_P).
+    ``subtract_shot`` (then P_b - V sum w^2 / W^2, i.e. V/N_P for equal
+    masses).
     """
     if n_bins is None:
         n_bins = max_bins(n_grid, n_dk)
-    delta, n_p = delta_half(np.asarray(pos), box, n_grid, order, interlace_on, workers)
+    pos = np.asarray(pos)
+    delta, _ = delta_half(pos, box, n_grid, order, interlace_on, workers, weights)
     k, pk, counts = bin_power(delta, box, n_grid, n_dk, n_bins)
     if subtract_shot:
-        pk = pk - float(box) ** 3 / n_p
+        pk = pk - shot_noise(pos, box, weights)
     return k, pk, counts
