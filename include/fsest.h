@@ -74,6 +74,9 @@ typedef enum { EST_F32 = 0, EST_F64 = 1 } est_dtype;
  * exceeds 8192.  Both
  * give identical grids. */
 #define EST_FLAG_ATOMIC_SORT 1
+/* The handle reserves room for per-particle masses (8 bytes per particle):
+ * see estimator_set_weights. */
+#define EST_FLAG_WEIGHTS 2
 
 typedef struct {
   int32_t n_grid;        /* N in [8, 1024], a multiple of 4 of the form        */
@@ -85,7 +88,7 @@ typedef struct {
   int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
   double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */
   int64_t max_particles; /* upper bound of n_total per call, 1 .. 2^31-1      */
-  int32_t flags;         /* 0 or EST_FLAG_ATOMIC_SORT (below)                  */
+  int32_t flags;         /* EST_FLAG_ATOMIC_SORT | EST_FLAG_WEIGHTS (below)    */
   int32_t reserved;      /* must be 0                                          */
 } est_config;
 
@@ -193,6 +196,23 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype,
  * estimator_autotune (e.g. one cached from an earlier run).  EINVAL outside
  * [0, 48). */
 est_status estimator_set_launch(est_handle h, int32_t choice);
+
+/* Per-particle masses (the paper takes equal masses for simplicity,
+ * Sec. 2.1; a mass w_j weights particle j's kernel in eq. delgrid).
+ * `weights` is a device array of float32 masses, w[j] for particle j in the
+ * order of the positions passed to the following estimator_deposit,
+ * estimator_backward, estimator_graph_capture, estimator_autotune and
+ * estimator_direct_delta calls on this handle (n_total, or n, entries); NULL
+ * restores equal masses.  The library keeps the pointer, not the data: the
+ * array must stay valid while those calls run, and a captured graph reads
+ * the array set at capture time on every launch.  With masses, delta is
+ * normalised by the total mass W = sum w_j of its set, the subtracted shot
+ * noise is V sum w^2 / W^2, and dL/dx_j carries the factor w_j.  Masses must
+ * be finite and >= 0: a negative, NaN or infinite mass makes every grid
+ * value of the call NaN (and so P(k)); all-zero masses give W = 0 and NaN
+ * P(k).  Host only; EINVAL for a NULL handle or one created without
+ * EST_FLAG_WEIGHTS. */
+est_status estimator_set_weights(est_handle h, const float* weights);
 
 /* Test hook: copy grid `which` (1 = primary, 2 = interlaced) of set `mock`
  * as float32 [N][N][N] (z fastest) to dst (device).  ESTATE unless the last

@@ -31,6 +31,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 EST_OK, EST_EINVAL, EST_ENOMEM, EST_ESTATE, EST_EDEVICE, EST_EUNSUPPORTED = range(6)
 EST_F32, EST_F64 = 0, 1
 EST_FLAG_ATOMIC_SORT = 1
+EST_FLAG_WEIGHTS = 2
 STATUS_NAMES = {0: "EST_OK", 1: "EST_EINVAL", 2: "EST_ENOMEM", 3: "EST_ESTATE",
                 4: "EST_EDEVICE", 5: "EST_EUNSUPPORTED"}
 
@@ -40,7 +41,8 @@ EXPORTS = [
     "estimator_deposit", "estimator_transform", "estimator_power",
     "estimator_bispectrum_workspace_bytes", "estimator_bispectrum",
     "estimator_backward", "estimator_graph_capture", "estimator_graph_launch",
-    "estimator_autotune", "estimator_set_launch", "estimator_copy_grid", "estimator_sample_delta",
+    "estimator_autotune", "estimator_set_launch", "estimator_set_weights", "estimator_copy_grid",
+    "estimator_sample_delta",
     "estimator_direct_workspace_bytes", "estimator_direct_delta", "estimator_export_delta",
     "estimator_spectrum_power",
     "estimator_profile", "estimator_profile_read", "estimator_last_error",
@@ -85,6 +87,7 @@ _SIGS = {
     "estimator_graph_launch": [_P],
     "estimator_autotune": [_P, _P, _I32, _P, _I64, _I32, _I32, _I32, ctypes.POINTER(_I32)],
     "estimator_set_launch": [_P, _I32],
+    "estimator_set_weights": [_P, _P],
     "estimator_copy_grid": [_P, _I32, _I32, _P],
     "estimator_sample_delta": [_P, _I32, _P, _I64, _P],
     "estimator_direct_workspace_bytes": [_P, _I64, ctypes.POINTER(_SZ)],
@@ -194,6 +197,10 @@ def estimator_autotune(h, pos, dtype, offsets, n_total, n_dk, n_bins, iters):
 
 def estimator_set_launch(h, choice):
     _check(_lib.estimator_set_launch(h, int(choice)))
+
+
+def estimator_set_weights(h, weights):
+    _check(_lib.estimator_set_weights(h, _ptr(weights)))
 
 
 def estimator_copy_grid(h, which, mock, dst):

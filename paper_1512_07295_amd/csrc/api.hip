@@ -72,6 +72,7 @@ struct est_ctx {
   void* tune_out = nullptr;
   bool prof = false;
   bool capturing = false;
+  const float* weights = nullptr;  // masses for the particle calls (EST_FLAG_WEIGHTS)
   ProfRec rec[kPNumLabels];
   std::vector<hipEvent_t> pool;
 };
@@ -133,8 +134,9 @@ est_status check_config(const est_config* c) {
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return fail(EST_EINVAL, "box must be finite and > 0");
   if (c->max_particles < 1 || c->max_particles > 2147483647LL)
     return fail(EST_EINVAL, "max_particles must be 1..2^31-1");
-  if ((c->flags & ~EST_FLAG_ATOMIC_SORT) != 0 || c->reserved != 0)
-    return fail(EST_EINVAL, "flags must be 0 or EST_FLAG_ATOMIC_SORT and reserved 0");
+  if ((c->flags & ~(EST_FLAG_ATOMIC_SORT | EST_FLAG_WEIGHTS)) != 0 || c->reserved != 0)
+    return fail(EST_EINVAL,
+                "flags must combine EST_FLAG_ATOMIC_SORT and EST_FLAG_WEIGHTS only, reserved 0");
   if (c->n_grid < 8 || c->n_grid > 1024 || c->n_grid % kBucket != 0 || !smooth235(c->n_grid))
     return fail(EST_EUNSUPPORTED,
                 "n_grid must be a multiple of 4 in [8, 1024] with prime factors 2, 3, 5 only (got %d)",
@@ -208,6 +210,11 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   bb.mode_n = (int64_t*)take(half * sizeof(int64_t));
   bb.mode_k = (double*)take(half * sizeof(double));
   bb.np = (int64_t*)take(batch * sizeof(int64_t));
+  bb.norm = (double*)take(batch * 2 * sizeof(double));
+  const bool weighted = (c.flags & EST_FLAG_WEIGHTS) != 0;
+  bb.sw = weighted ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
+  bb.tw = weighted && two_level ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
+  bb.wpart = weighted ? (double*)take(batch * kWSlices * 2 * sizeof(double)) : nullptr;
   bb.coef = (double*)take(batch * half * sizeof(double));
   bb.mode_partials_n = (uint64_t*)take(512 * half * sizeof(uint64_t));
   bb.mode_partials_k = (double*)take(512 * half * sizeof(double));
@@ -268,13 +275,21 @@ est_status run_deposit(est_handle h, const void* pos, est_dtype dt, const int64_
   est_status st;
   {
     ProfScope ps(h, kPSort);
-    st = dev_err(launch_set_counts(offsets, n_total, h->g.batch, h->b.np, h->stream), "counts");
+    st = dev_err(launch_set_counts(offsets, n_total, h->g.batch, h->b.np, h->b.norm, h->stream),
+                 "counts");
     if (st) return st;
-    st = dev_err(launch_sort(h->g, pos, dt, offsets, n_total, h->b, h->stream), "bucket sort");
+    if (h->weights) {
+      st = dev_err(launch_weight_stats(h->weights, offsets, n_total, h->g.batch, h->b.wpart,
+                                       h->b.norm, h->b.stats, h->stream),
+                   "mass sums");
+      if (st) return st;
+    }
+    st = dev_err(launch_sort(h->g, pos, dt, offsets, n_total, h->weights, h->b, h->stream),
+                 "bucket sort");
     if (st) return st;
   }
   ProfScope ps(h, kPDeposit);
-  return dev_err(launch_deposit(h->g, dt, h->b, h->tu, h->stream), "deposit");
+  return dev_err(launch_deposit(h->g, dt, h->b, h->tu, h->weights != nullptr, h->stream), "deposit");
 }
 
 est_status run_xy(est_handle h, int dir) {
@@ -524,7 +539,8 @@ est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype, co
   if ((st = run_xy(h, +1))) return st;
   {
     ProfScope ps(h, kPGather);
-    if ((st = dev_err(launch_gather_grad(h->g, pos, dtype, offsets, n_total, h->b, grad, h->stream), "gather")))
+    if ((st = dev_err(launch_gather_grad(h->g, pos, dtype, offsets, n_total, h->weights, h->b, grad,
+                                                    h->stream), "gather")))
       return st;
   }
   h->state = kCreated;  // the grid now holds dL/drho, not a density
@@ -607,6 +623,15 @@ est_status estimator_set_launch(est_handle h, int32_t choice) {
   id[1] = (choice / 8) % 3;
   id[0] = choice / 24;
   h->tu = tune_from_index(id);
+  return ok();
+}
+
+est_status estimator_set_weights(est_handle h, const float* weights) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!(h->cfg.flags & EST_FLAG_WEIGHTS))
+    return fail(EST_EINVAL, "the handle was created without EST_FLAG_WEIGHTS");
+  h->weights = weights;
   return ok();
 }
 
@@ -708,7 +733,7 @@ est_status estimator_direct_delta(est_handle h, const void* pos, est_dtype dtype
   const size_t need = direct_workspace(h->g.n, n);
   if (dws_bytes < need) return fail(EST_ENOMEM, "direct workspace too small: %zu < %zu", dws_bytes, need);
   ProfScope ps(h, kPDirect);
-  return dev_err(launch_direct(h->g, pos, dtype, n, dws, out, h->stream), "direct sum");
+  return dev_err(launch_direct(h->g, pos, dtype, n, h->weights, dws, out, h->stream), "direct sum");
 }
 
 est_status estimator_export_delta(est_handle h, int32_t mock, double* out) {

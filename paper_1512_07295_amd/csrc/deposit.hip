@@ -30,17 +30,109 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np) {
+__global__ void k_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
+                             double* norm) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= batch) return;
-  np[i] = offsets ? (offsets[i + 1] - offsets[i]) : n_total;
+  const int64_t c = offsets ? (offsets[i + 1] - offsets[i]) : n_total;
+  np[i] = c;
+  norm[2 * i] = (double)c;
+  norm[2 * i + 1] = (double)c;
 }
 
 hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
-                             hipStream_t s) {
+                             double* norm, hipStream_t s) {
   hipLaunchKernelGGL(k_set_counts, dim3((batch + 63) / 64), dim3(64), 0, s, offsets, n_total,
-                     batch, np);
+                     batch, np, norm);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ masses
+// Per set, kWSlices workgroups each sum w and w^2 over a fixed slice of the
+// set's particles (strided per thread, then a fixed tree over the
+// workgroup), and a second pass adds the slices in order: the totals do not
+// depend on scheduling.  The largest mass goes to stats[4] (non-negative
+// floats order like their bit patterns) and any negative, NaN or infinite
+// mass sets stats[5].
+constexpr int kWThreads = 256;
+
+__global__ __launch_bounds__(kWThreads) void k_weight_stats(const float* __restrict__ w,
+                                                            const int64_t* __restrict__ offsets,
+                                                            int64_t n_total,
+                                                            double* __restrict__ wpart,
+                                                            uint32_t* __restrict__ stats) {
+  __shared__ double sa[kWThreads / 64], sb[kWThreads / 64];
+  const int m = blockIdx.y, slice = blockIdx.x;
+  const int64_t j0 = offsets ? offsets[m] : 0, j1 = offsets ? offsets[m + 1] : n_total;
+  const int64_t len = j1 - j0;
+  const int64_t s0 = j0 + len * slice / kWSlices, s1 = j0 + len * (slice + 1) / kWSlices;
+  double a = 0.0, b = 0.0;
+  float mx = 0.0f;
+  bool bad = false;
+  for (int64_t j = s0 + threadIdx.x; j < s1; j += kWThreads) {
+    const float v = w[j];
+    if (!(v >= 0.0f && v <= 3.402823466e38f)) {
+      bad = true;
+    } else {
+      a += (double)v;
+      b += (double)v * (double)v;
+      if (v > mx) mx = v;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+    mx = fmaxf(mx, __shfl_down(mx, off, 64));
+  }
+  const unsigned long long anybad = __ballot(bad);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sa[wave] = a;
+    sb[wave] = b;
+    if (mx > 0.0f) atomicMax(&stats[4], __float_as_uint(mx));
+    if (anybad) atomicOr(&stats[5], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int i = 0; i < kWThreads / 64; ++i) {
+      ta += sa[i];
+      tb += sb[i];
+    }
+    double* dst = wpart + 2 * ((int64_t)m * kWSlices + slice);
+    dst[0] = ta;
+    dst[1] = tb;
+  }
+}
+
+__global__ void k_weight_final(const double* __restrict__ wpart, int batch, double* __restrict__ norm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= batch) return;
+  double ta = 0.0, tb = 0.0;
+  for (int i = 0; i < kWSlices; ++i) {
+    ta += wpart[2 * ((int64_t)m * kWSlices + i)];
+    tb += wpart[2 * ((int64_t)m * kWSlices + i) + 1];
+  }
+  norm[2 * m] = ta;
+  norm[2 * m + 1] = tb;
+}
+
+hipError_t launch_weight_stats(const float* w, const int64_t* offsets, int64_t n_total, int batch,
+                               double* wpart, double* norm, uint32_t* stats, hipStream_t s) {
+  hipError_t e = launch_fill_u32(stats + 4, 2, 0u, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_weight_stats, dim3(kWSlices, batch), dim3(kWThreads), 0, s, w, offsets,
+                     n_total, wpart, stats);
+  hipLaunchKernelGGL(k_weight_final, dim3((batch + 63) / 64), dim3(64), 0, s, wpart, batch, norm);
+  return hipGetLastError();
+}
+
+// mass of particle j divided by the largest mass (in [0, 1]; 0 if every mass is 0)
+__device__ __forceinline__ float scaled_mass(const float* w, int64_t j, const uint32_t* stats) {
+  const float wmax = __uint_as_float(stats[4]);
+  const float v = w[j];
+  return (wmax > 0.0f && v >= 0.0f && v <= wmax) ? v / wmax : 0.0f;
 }
 
 // set index of particle j: largest i with offsets[i] <= j (offsets has batch+1 entries)
@@ -151,7 +243,10 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ p
                                                         const uint32_t* __restrict__ boff,
                                                         const uint32_t* __restrict__ rank,
                                                         TP* __restrict__ sorted,
-                                                        uint64_t* __restrict__ cells) {
+                                                        uint64_t* __restrict__ cells,
+                                                        const float* __restrict__ w,
+                                                        float* __restrict__ sw,
+                                                        const uint32_t* __restrict__ stats) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_total) return;
   TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
@@ -168,6 +263,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ p
   sorted[3 * dst + 1] = py;
   sorted[3 * dst + 2] = pz;
   cells[dst] = cell_record(ux, uy, uz, g);
+  if (w) sw[dst] = scaled_mass(w, j, stats);
 }
 
 // exclusive scan of n items in place, 2048 items per block
@@ -255,8 +351,8 @@ static hipError_t scan_in_place(uint32_t* data, size_t n, uint32_t* tmp, uint32_
 // Counting sort with device-scope atomics: the general path, used when there
 // are more super-buckets than one workgroup can histogram.
 static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
-                              const int64_t* offsets, int64_t n_total, const Buffers& b,
-                              hipStream_t s) {
+                              const int64_t* offsets, int64_t n_total, const float* w,
+                              const Buffers& b, hipStream_t s) {
   const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
   hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
   if (e != hipSuccess) return e;
@@ -273,11 +369,12 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
   if ((e = scan_in_place(b.boff, nkeys + 1, b.scan_tmp, b.stats, s)) != hipSuccess) return e;
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
-                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells);
+                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells, w, b.sw,
+                       b.stats);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3(pblocks), dim3(256), 0, s,
                        (const double*)pos, n_total, offsets, g, b.boff, b.rank,
-                       (double*)b.sorted, b.cells);
+                       (double*)b.sorted, b.cells, w, b.sw, b.stats);
   return hipGetLastError();
 }
 
@@ -345,7 +442,7 @@ template <typename TP>
 __global__ __launch_bounds__(kSortThreads) void k_sort_super(
     const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
     int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ tpos,
-    uint64_t* __restrict__ trec) {
+    uint64_t* __restrict__ trec, const float* __restrict__ w, float* __restrict__ tw) {
   __shared__ uint32_t cur[kMaxSuper];
   for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
     cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
@@ -379,6 +476,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
         tpos[3 * (int64_t)p + 1] = py[q];
         tpos[3 * (int64_t)p + 2] = pz[q];
         trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
+        if (w) tw[p] = w[j];
       }
     }
   }
@@ -389,7 +487,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
     const TP* __restrict__ tpos, const uint64_t* __restrict__ trec, int64_t n_total, Geom g,
     int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ sorted,
     uint64_t* __restrict__ cells, uint32_t* __restrict__ boff, uint32_t* __restrict__ bcnt,
-    uint32_t* __restrict__ stats) {
+    uint32_t* __restrict__ stats, const float* __restrict__ tw, float* __restrict__ sw) {
   constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
   __shared__ uint32_t hist[kFineMax * kFineMax * kFineMax];
   __shared__ uint32_t wtot[kSortThreads / 64];
@@ -473,6 +571,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
         sorted[3 * (int64_t)p + 1] = py[q];
         sorted[3 * (int64_t)p + 2] = pz[q];
         cells[p] = r[q] & ((1ull << kRecFineShift) - 1ull);
+        if (tw) sw[p] = scaled_mass(tw, ib + q * kSortThreads, stats);
       }
     }
   }
@@ -480,7 +579,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
 
 template <typename TP>
 static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* offsets,
-                                 int64_t n_total, const Buffers& b, hipStream_t s) {
+                                 int64_t n_total, const float* w, const Buffers& b, hipStream_t s) {
   int nblk = (int)((n_total + 4095) / 4096);
   if (nblk > kMaxSortBlocks) nblk = kMaxSortBlocks;
   const int64_t chunk = (n_total + nblk - 1) / nblk;
@@ -492,20 +591,20 @@ static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* of
   if ((e = scan_in_place(b.hsup, (size_t)g.nsup * nblk, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
-                     offsets, g, chunk, nblk, b.hsup, (TP*)b.tpos, b.trec);
+                     offsets, g, chunk, nblk, b.hsup, (TP*)b.tpos, b.trec, w, b.tw);
   hipLaunchKernelGGL(k_sort_fine<TP>, dim3(g.nsup), dim3(kSortThreads), 0, s, (const TP*)b.tpos,
                      b.trec, n_total, g, nblk, b.hsup, (TP*)b.sorted, b.cells, b.boff, b.bcnt,
-                     b.stats);
+                     b.stats, w ? b.tw : nullptr, b.sw);
   return hipGetLastError();
 }
 
 hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                       int64_t n_total, const Buffers& b, hipStream_t s) {
+                       int64_t n_total, const float* w, const Buffers& b, hipStream_t s) {
   hipError_t e = launch_fill_u32(b.stats, 4, 0u, s);
   if (e != hipSuccess) return e;
-  if (g.nsup > kMaxSuper) return sort_atomic(g, pos, dt, offsets, n_total, b, s);
-  if (dt == EST_F32) return sort_two_level(g, (const float*)pos, offsets, n_total, b, s);
-  return sort_two_level(g, (const double*)pos, offsets, n_total, b, s);
+  if (g.nsup > kMaxSuper) return sort_atomic(g, pos, dt, offsets, n_total, w, b, s);
+  if (dt == EST_F32) return sort_two_level(g, (const float*)pos, offsets, n_total, w, b, s);
+  return sort_two_level(g, (const double*)pos, offsets, n_total, w, b, s);
 }
 
 // ------------------------------------------------------------------ stencils
@@ -724,21 +823,28 @@ __device__ __forceinline__ int first_cell(double u) {
 // needs N >= kTileMax + P - 1); for a tile that is the whole grid (t0 = 0)
 // it lies in [0, n).  `first` is a record cell (in [0, N)) minus the stencil
 // offset plus the interlacing step, so first - t0 lies in [-(P-1) - N + 1, N].
-template <int P, bool PERIODIC>
+// WRAP: kPeriodic (the tile is the whole grid), kMasked (tile smaller than a
+// power-of-two grid: the residue is a mask), kGeneral (any other N).
+constexpr int kPeriodic = 0, kMasked = 1, kGeneral = 2;
+
+template <int P, int WRAP>
 __device__ __forceinline__ int rel_first(int first, int t0, int n) {
   int r = first - t0;
-  if constexpr (PERIODIC) {
+  if constexpr (WRAP == kPeriodic) {
     r = r < 0 ? r + n : r;
     return r >= n ? r - n : r;
+  } else if constexpr (WRAP == kMasked) {
+    r &= n - 1;
+    return (r >= n - (P - 1)) ? r - n : r;
   } else {
     r = r < -(P - 1) ? r + n : r;
     return (r >= n - (P - 1)) ? r - n : r;
   }
 }
 
-template <int P, bool PERIODIC>
+template <int P, int WRAP>
 __device__ __forceinline__ bool reaches_tile(int rx, int ry, int rz) {
-  if constexpr (PERIODIC) return true;
+  if constexpr (WRAP == kPeriodic) return true;
   else return rx < kTileMax && ry < kTileMax && rz < kTileMax;
 }
 
@@ -748,7 +854,7 @@ __device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
 }
 
 // Adds one grid's footprint of one particle to the tile.
-template <int P, typename AT, bool PERIODIC>
+template <int P, typename AT, int WRAP>
 __device__ __forceinline__ void deposit_item(double x, double y, double z, int gi, const Geom& g,
                                              int t0x, int t0y, int t0z, AT* sm, float scale) {
   const int n = g.n;
@@ -757,9 +863,10 @@ __device__ __forceinline__ void deposit_item(double x, double y, double z, int g
   const int fx = stencil_first<P>(grid_coord(x, g.box, g.inv) + sh, scale, wx);
   const int fy = stencil_first<P>(grid_coord(y, g.box, g.inv) + sh, 1.0f, wy);
   const int fz = stencil_first<P>(grid_coord(z, g.box, g.inv) + sh, 1.0f, wz);
-  const int rx = rel_first<P, PERIODIC>(fx, t0x, n);
-  const int ry = rel_first<P, PERIODIC>(fy, t0y, n);
-  const int rz = rel_first<P, PERIODIC>(fz, t0z, n);
+  constexpr bool PERIODIC = WRAP == kPeriodic;
+  const int rx = rel_first<P, WRAP>(fx, t0x, n);
+  const int ry = rel_first<P, WRAP>(fy, t0y, n);
+  const int rz = rel_first<P, WRAP>(fz, t0z, n);
   const int region = (acc_first_word<AT>() * 4 / (int)sizeof(AT)) + gi * kGridWords;
   if constexpr (PERIODIC) {
     // the tile is the whole grid (n <= kTileMax): x and y wrap, z runs into
@@ -826,13 +933,16 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // the sort) instead of one tile per workgroup.  `xcd`: consecutive tiles go
 // to the same XCD (workgroup b runs on XCD b mod 8), so the buckets that
 // neighbouring tiles share are read through one L2.
-template <int P, bool IL, typename TP, bool WIDE, bool PERIODIC>
+// WT: per-particle masses (sw, bucket order, divided by the largest mass);
+// a separate instantiation so that the equal-mass kernel keeps its registers
+template <int P, bool IL, typename TP, bool WIDE, int WRAP, bool WT>
 __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
                                                   const uint64_t* __restrict__ cells,
                                                   const uint32_t* __restrict__ boff,
                                                   const uint32_t* __restrict__ bcnt, float* grid,
                                                   Geom g, uint32_t* __restrict__ stats,
-                                                  int exclusive, int dynamic, int xcd) {
+                                                  int exclusive, int dynamic, int xcd,
+                                                  const float* __restrict__ sw) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int NG = IL ? 2 : 1;
   constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
@@ -855,6 +965,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
   const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
   const double inv_scale = 1.0 / (double)scale;
+  // masses: items carry w / w_max (in [0, 1], so the bounds above hold) and
+  // the tile is multiplied back by w_max; an invalid mass makes it NaN
+  float wmul = 1.0f;
+  if constexpr (WT) wmul = stats[5] ? __builtin_nanf("") : __uint_as_float(stats[4]);
 
   const int n = g.n, T = g.tile, nb = g.nb;
   const int tpa = (n + T - 1) / T;  // tiles per axis; the last one is ragged when T does not divide N
@@ -986,10 +1100,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
             const int sx = gi ? (int)((r >> 48) & 1) : 0;
             const int sy = gi ? (int)((r >> 49) & 1) : 0;
             const int sz = gi ? (int)((r >> 50) & 1) : 0;
-            const int rx = rel_first<P, PERIODIC>(cx + sx, t0x, n);
-            const int ry = rel_first<P, PERIODIC>(cy + sy, t0y, n);
-            const int rz = rel_first<P, PERIODIC>(cz + sz, t0z, n);
-            ok[gi] = reaches_tile<P, PERIODIC>(rx, ry, rz);
+            const int rx = rel_first<P, WRAP>(cx + sx, t0x, n);
+            const int ry = rel_first<P, WRAP>(cy + sy, t0y, n);
+            const int rz = rel_first<P, WRAP>(cz + sz, t0z, n);
+            ok[gi] = reaches_tile<P, WRAP>(rx, ry, rz);
             cls[gi] = bank_class<P>(rx, ry, rz);
           }
         }
@@ -1075,9 +1189,12 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
               ny = sorted[3 * jq + 1];
               nz = sorted[3 * jq + 2];
             }
-            if (e_cur >= 0)
-              deposit_item<P, AT, PERIODIC>((double)px, (double)py, (double)pz,
-                                            item_meta[e_cur] >> 6, g, t0x, t0y, t0z, sm, scale);
+            if (e_cur >= 0) {
+              float sc = scale;
+              if constexpr (WT) sc *= sw[item_j[e_cur]];
+              deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz,
+                                            item_meta[e_cur] >> 6, g, t0x, t0y, t0z, sm, sc);
+            }
             e_cur = e_nxt;
             px = nx;
             py = ny;
@@ -1093,7 +1210,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     }
 
     // (3) write the tile (halo cells dropped, or folded back when periodic)
-    if constexpr (!PERIODIC) {
+    if constexpr (WRAP != kPeriodic) {
       // four consecutive z cells per thread; the narrow scale is a power of
       // two, so float(sum) * 2^-F rounds exactly like the double product
       constexpr int TT = kTileMax;
@@ -1108,7 +1225,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const AT s = sm[a + q];
-            v[gi][q] = WIDE ? (float)((double)s * inv_scale) : (float)s * inv_f;
+            v[gi][q] = (WIDE ? (float)((double)s * inv_scale) : (float)s * inv_f) * wmul;
           }
         }
         if constexpr (IL) {
@@ -1130,7 +1247,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
           const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
           AT s = sm[a];
           if (lz < zhalo<P>()) s += sm[a + T];
-          v[gi] = (float)((double)s * inv_scale);
+          v[gi] = (float)((double)s * inv_scale) * wmul;
         }
         if constexpr (IL) {
           reinterpret_cast<float2*>(grid)[complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] =
@@ -1152,57 +1269,68 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   }
 }
 
-template <int P, bool IL, typename TP, bool PER>
+template <int P, bool IL, typename TP, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
-                           hipStream_t s) {
+                           const float* sw, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   if (narrow)
-    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, PER>), dim3((unsigned)ntiles), dim3(threads),
+    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT>), dim3((unsigned)ntiles), dim3(threads),
                        0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0,
-                       0, xcd ? 1 : 0);
+                       0, xcd ? 1 : 0, sw);
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
   const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
-  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, PER>), dim3(wblocks), dim3(threads), 0, s,
+  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, WRAP, WT>), dim3(wblocks), dim3(threads), 0, s,
                      (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats,
-                     narrow ? 0 : 1, 1, 0);
+                     narrow ? 0 : 1, 1, 0, sw);
+}
+
+template <int P, bool IL, int WRAP>
+static void dispatch_deposit_w(const Geom& g, est_dtype dt, const Buffers& b, int threads,
+                               bool narrow, bool xcd, const float* sw, hipStream_t s) {
+  if (sw) {
+    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, true>(g, b, threads, narrow, xcd, sw, s);
+    else deposit_launch<P, IL, double, WRAP, true>(g, b, threads, narrow, xcd, sw, s);
+  } else {
+    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, false>(g, b, threads, narrow, xcd, nullptr, s);
+    else deposit_launch<P, IL, double, WRAP, false>(g, b, threads, narrow, xcd, nullptr, s);
+  }
 }
 
 template <int P, bool IL>
 static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                               int threads, hipStream_t s) {
+                               int threads, const float* sw, hipStream_t s) {
   const bool narrow = tu.dep_narrow != 0;
   const bool xcd = tu.dep_xcd != 0;
-  const bool per = g.tile == g.n;
-  if (dt == EST_F32) {
-    if (per) deposit_launch<P, IL, float, true>(g, b, threads, narrow, xcd, s);
-    else deposit_launch<P, IL, float, false>(g, b, threads, narrow, xcd, s);
-  } else {
-    if (per) deposit_launch<P, IL, double, true>(g, b, threads, narrow, xcd, s);
-    else deposit_launch<P, IL, double, false>(g, b, threads, narrow, xcd, s);
-  }
+  if (g.tile == g.n)
+    dispatch_deposit_w<P, IL, kPeriodic>(g, dt, b, threads, narrow, xcd, sw, s);
+  else if ((g.n & (g.n - 1)) == 0)
+    dispatch_deposit_w<P, IL, kMasked>(g, dt, b, threads, narrow, xcd, sw, s);
+  else
+    dispatch_deposit_w<P, IL, kGeneral>(g, dt, b, threads, narrow, xcd, sw, s);
 }
 
 template <int P>
 static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                               int threads, hipStream_t s) {
-  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, tu, threads, s);
-  else dispatch_deposit_t<P, false>(g, dt, b, tu, threads, s);
+                               int threads, const float* sw, hipStream_t s) {
+  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, tu, threads, sw, s);
+  else dispatch_deposit_t<P, false>(g, dt, b, tu, threads, sw, s);
 }
 
 hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                          hipStream_t s) {
+                          bool weighted, hipStream_t s) {
   int threads = tu.dep_threads;
   if (threads != 256 && threads != 512 && threads != 1024) threads = 1024;
+  const float* sw = weighted ? b.sw : nullptr;
   switch (g.order) {
-    case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, s); break;
-    case 2: dispatch_deposit_p<2>(g, dt, b, tu, threads, s); break;
-    case 3: dispatch_deposit_p<3>(g, dt, b, tu, threads, s); break;
-    case 4: dispatch_deposit_p<4>(g, dt, b, tu, threads, s); break;
-    case 5: dispatch_deposit_p<5>(g, dt, b, tu, threads, s); break;
-    default: dispatch_deposit_p<6>(g, dt, b, tu, threads, s); break;
+    case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, sw, s); break;
+    case 2: dispatch_deposit_p<2>(g, dt, b, tu, threads, sw, s); break;
+    case 3: dispatch_deposit_p<3>(g, dt, b, tu, threads, sw, s); break;
+    case 4: dispatch_deposit_p<4>(g, dt, b, tu, threads, sw, s); break;
+    case 5: dispatch_deposit_p<5>(g, dt, b, tu, threads, sw, s); break;
+    default: dispatch_deposit_p<6>(g, dt, b, tu, threads, sw, s); break;
   }
   return hipGetLastError();
 }
@@ -1236,6 +1364,7 @@ template <int P, bool IL, typename TP>
 __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos, int64_t n_total,
                                                      const int64_t* __restrict__ offsets,
                                                      const float* __restrict__ grid, Geom g,
+                                                     const float* __restrict__ w,
                                                      TP* __restrict__ grad) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_total) return;
@@ -1272,7 +1401,8 @@ __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos,
       }
     }
   }
-  const double sc = -(double)n / g.box;
+  // a particle of mass w_j deposits w_j times the kernel
+  const double sc = -(double)n / g.box * (w ? (double)w[j] : 1.0);
   grad[3 * j + 0] = (TP)(sc * gx);
   grad[3 * j + 1] = (TP)(sc * gy);
   grad[3 * j + 2] = (TP)(sc * gz);
@@ -1280,36 +1410,38 @@ __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos,
 
 template <int P>
 static void dispatch_gather(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                            int64_t n_total, const Buffers& b, void* grad, hipStream_t s) {
+                            int64_t n_total, const float* w, const Buffers& b, void* grad,
+                            hipStream_t s) {
   const unsigned blocks = (unsigned)((n_total + 255) / 256);
   if (dt == EST_F32) {
     if (g.il)
       hipLaunchKernelGGL((k_gather_grad<P, true, float>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, (float*)grad);
+                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, w, (float*)grad);
     else
       hipLaunchKernelGGL((k_gather_grad<P, false, float>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, (float*)grad);
+                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, w, (float*)grad);
   } else {
     if (g.il)
       hipLaunchKernelGGL((k_gather_grad<P, true, double>), dim3(blocks), dim3(256), 0, s,
-                         (const double*)pos, n_total, offsets, (const float*)b.grid, g,
+                         (const double*)pos, n_total, offsets, (const float*)b.grid, g, w,
                          (double*)grad);
     else
       hipLaunchKernelGGL((k_gather_grad<P, false, double>), dim3(blocks), dim3(256), 0, s,
-                         (const double*)pos, n_total, offsets, (const float*)b.grid, g,
+                         (const double*)pos, n_total, offsets, (const float*)b.grid, g, w,
                          (double*)grad);
   }
 }
 
 hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                              int64_t n_total, const Buffers& b, void* grad, hipStream_t s) {
+                              int64_t n_total, const float* w, const Buffers& b, void* grad,
+                              hipStream_t s) {
   switch (g.order) {
-    case 1: dispatch_gather<1>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    case 2: dispatch_gather<2>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    case 3: dispatch_gather<3>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    case 4: dispatch_gather<4>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    case 5: dispatch_gather<5>(g, pos, dt, offsets, n_total, b, grad, s); break;
-    default: dispatch_gather<6>(g, pos, dt, offsets, n_total, b, grad, s); break;
+    case 1: dispatch_gather<1>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
+    case 2: dispatch_gather<2>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
+    case 3: dispatch_gather<3>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
+    case 4: dispatch_gather<4>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
+    case 5: dispatch_gather<5>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
+    default: dispatch_gather<6>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
   }
   return hipGetLastError();
 }

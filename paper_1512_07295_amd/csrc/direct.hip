@@ -2,6 +2,7 @@
 //   delta_DS(m) = N_P^-1 sum_j exp(-2 pi i m . x_j / L)
 // at every half-space mode of the grid (m_x, m_y in [-N/2, N/2], m_z in
 // [0, N/2]), the alias-free reference the FFT estimator is compared with.
+// With masses w_j the sum is W^-1 sum_j w_j exp(...), W = sum_j w_j.
 //
 // Design (gfx950, ALU-bound, O(N_P N^3 / 2)):
 //  * each particle's position becomes three 32-bit fixed-point phases
@@ -35,11 +36,14 @@ __global__ void k_dir_prep(const TP* __restrict__ pos, int64_t n, double box,
 
 // partial[slice][mode] (complex128) of the half spectrum, mode index
 // (ix * N + iy) * (N/2 + 1) + mz with ix, iy the FFT indices
+template <bool WT>
 __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restrict__ q, int64_t n,
                                                         int ngrid, int nslices,
+                                                        const float* __restrict__ w,
                                                         double* __restrict__ partial) {
   __shared__ uint32_t sq[3 * kDirChunk];
   __shared__ float2 sstep[kDirChunk];
+  __shared__ float swt[WT ? kDirChunk : 1];
   const int nh = ngrid / 2 + 1;
   const int nzb = (nh + kDirMz - 1) / kDirMz;
   const int64_t nthreads_modes = (int64_t)ngrid * ngrid * nzb;
@@ -70,6 +74,10 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
       // exp(-2 pi i q_z / 2^32): sincospi of 2 q_z / 2^32 = q_z / 2^31
       sincospif((float)qz * 4.656612873077393e-10f, &s, &c);
       sstep[i] = make_float2(c, -s);
+      if constexpr (WT) {
+        const float v = w[c0 + i];
+        swt[i] = (v >= 0.0f && v <= 3.402823466e38f) ? v : 0.0f;
+      }
     }
     __syncthreads();
     if (active) {
@@ -82,6 +90,10 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
         float s, c;
         sincospif((float)ph * 4.656612873077393e-10f, &s, &c);
         float er = c, ei = -s;
+        if constexpr (WT) {
+          er *= swt[i];
+          ei *= swt[i];
+        }
         const float2 st = sstep[i];
 #pragma unroll
         for (int r = 0; r < kDirMz; ++r) {
@@ -113,13 +125,17 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
   }
 }
 
+// norm (with masses): (W, sum w^2) from the mass-sum pass, stats[5] set for an
+// invalid mass (then every mode is NaN)
 __global__ void k_dir_reduce(const double* __restrict__ partial, int64_t nmodes, int nslices,
-                             double inv_n, double* __restrict__ out) {
+                             double inv_n, const double* __restrict__ norm,
+                             const uint32_t* __restrict__ stats, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 2 * nmodes) return;
   double s = 0.0;
   for (int k = 0; k < nslices; ++k) s += partial[2 * nmodes * k + i];
-  out[i] = s * inv_n;
+  if (norm) out[i] = stats[5] ? __builtin_nan("") : s / norm[0];
+  else out[i] = s * inv_n;
 }
 
 int direct_slices(int ngrid, int64_t n) {
@@ -133,20 +149,32 @@ int direct_slices(int ngrid, int64_t n) {
   return (int)s;
 }
 
+// workspace: fixed-point phases, the mass sums (partials, totals, flags),
+// then the per-slice partial spectra
+constexpr size_t kDirMassBytes = 256 * ((2 * kWSlices * 8 + 2 * 8 + 64 * 4 + 255) / 256);
+
 size_t direct_workspace(int ngrid, int64_t n) {
   const int64_t nmodes = (int64_t)ngrid * ngrid * (ngrid / 2 + 1);
   const size_t qbytes = ((size_t)n * 3 * sizeof(uint32_t) + 255) / 256 * 256;
-  return qbytes + (size_t)direct_slices(ngrid, n) * nmodes * 2 * sizeof(double);
+  return qbytes + kDirMassBytes + (size_t)direct_slices(ngrid, n) * nmodes * 2 * sizeof(double);
 }
 
-hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, void* ws,
-                         double* out, hipStream_t s) {
+hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, const float* w,
+                         void* ws, double* out, hipStream_t s) {
   const int ngrid = g.n;
   const int nh = ngrid / 2 + 1;
   const int64_t nmodes = (int64_t)ngrid * ngrid * nh;
   const int nslices = direct_slices(ngrid, n);
   uint32_t* q = (uint32_t*)ws;
-  double* partial = (double*)((char*)ws + ((size_t)n * 3 * sizeof(uint32_t) + 255) / 256 * 256);
+  char* mass = (char*)ws + ((size_t)n * 3 * sizeof(uint32_t) + 255) / 256 * 256;
+  double* wpart = (double*)mass;
+  double* norm = wpart + 2 * kWSlices;
+  uint32_t* stats = (uint32_t*)(norm + 2);
+  double* partial = (double*)(mass + kDirMassBytes);
+  if (w) {
+    hipError_t e = launch_weight_stats(w, nullptr, n, 1, wpart, norm, stats, s);
+    if (e != hipSuccess) return e;
+  }
   const unsigned pb = (unsigned)((n + 255) / 256);
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_dir_prep<float>, dim3(pb), dim3(256), 0, s, (const float*)pos, n, g.box, q);
@@ -154,10 +182,15 @@ hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n
     hipLaunchKernelGGL(k_dir_prep<double>, dim3(pb), dim3(256), 0, s, (const double*)pos, n, g.box,
                        q);
   const int64_t threads = (int64_t)ngrid * ngrid * ((nh + kDirMz - 1) / kDirMz);
-  hipLaunchKernelGGL(k_direct, dim3((unsigned)((threads + kDirThreads - 1) / kDirThreads), nslices),
-                     dim3(kDirThreads), 0, s, q, n, ngrid, nslices, partial);
+  const dim3 grid((unsigned)((threads + kDirThreads - 1) / kDirThreads), nslices);
+  if (w)
+    hipLaunchKernelGGL(k_direct<true>, grid, dim3(kDirThreads), 0, s, q, n, ngrid, nslices, w,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_direct<false>, grid, dim3(kDirThreads), 0, s, q, n, ngrid, nslices, w,
+                       partial);
   hipLaunchKernelGGL(k_dir_reduce, dim3((unsigned)((2 * nmodes + 255) / 256)), dim3(256), 0, s,
-                     partial, nmodes, nslices, 1.0 / (double)n, out);
+                     partial, nmodes, nslices, 1.0 / (double)n, w ? norm : nullptr, stats, out);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ constexpr int kMaxBinBlocks = 2048;  // upper bound of P(k) reduction blocks per
 constexpr int kFineMax = 16;    // buckets per super-bucket edge (two-level sort)
 constexpr int kMaxSuper = 8192; // super-buckets one workgroup histograms in LDS
 constexpr int kMaxSortBlocks = 1024;  // workgroups of the super-bucket passes
+constexpr int kWSlices = 64;    // workgroups per set of the mass-sum pass
 
 // Geometry and per-call constants that device code needs.
 struct Geom {
@@ -58,7 +59,9 @@ struct Buffers {
   uint64_t* trec;          // max_particles cell records in super-bucket order
   uint32_t* hsup;          // kMaxSuper * kMaxSortBlocks + 1 histogram / offsets
   uint32_t* scan_tmp;      // scan block sums
-  uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter
+  uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter,
+                           // [4] largest mass (float bits), [5] nonzero if a mass is
+                           // negative or not finite
   float2* tw_n;            // exp(-2 pi i n / N)
   float2* tw_nz;           // exp(-2 pi i n / nz)
   float* inv_w2;           // 1 / W_1D(m(i))^2 for FFT index i (N entries)
@@ -68,6 +71,11 @@ struct Buffers {
   int64_t* mode_n;         // kMaxBins
   double* mode_k;          // kMaxBins
   int64_t* np;             // batch particle counts
+  double* norm;            // batch x (W, sum w^2): total mass and sum of squared masses
+                           // (N_P, N_P for equal masses)
+  float* sw;               // max_particles masses / largest mass, bucket order (weighted handles)
+  float* tw;               // max_particles masses in super-bucket order (weighted, two-level)
+  double* wpart;           // batch x kWSlices x 2 partial mass sums (weighted handles)
   double* coef;            // batch * kMaxBins adjoint coefficients
   uint64_t* mode_partials_n;  // kMaxBinBlocks * kMaxBins
   double* mode_partials_k;    // kMaxBinBlocks * kMaxBins
@@ -103,16 +111,25 @@ __device__ __forceinline__ double grid_coord(double x, double box, double inv) {
 
 // ---- launchers (return hipError_t of the last launch) ----
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+// particle counts per set; norm = (N_P, N_P) per set (equal masses)
 hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
-                             hipStream_t s);
+                             double* norm, hipStream_t s);
+// masses w (original order): norm = (W, sum w^2) per set in a fixed summation
+// order, stats[4] = largest mass, stats[5] = flag for invalid masses
+hipError_t launch_weight_stats(const float* w, const int64_t* offsets, int64_t n_total, int batch,
+                               double* wpart, double* norm, uint32_t* stats, hipStream_t s);
+// w: masses in original order (null: equal masses); their bucket-order
+// copy, divided by the largest mass, goes to b.sw
 hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                       int64_t n_total, const Buffers& b, hipStream_t s);
+                       int64_t n_total, const float* w, const Buffers& b, hipStream_t s);
+// weighted: read b.sw and scale the grids by the largest mass
 hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                          hipStream_t s);
+                          bool weighted, hipStream_t s);
 hipError_t launch_copy_grid(const Geom& g, const Buffers& b, int which, int mock, float* dst,
                             hipStream_t s);
 hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                              int64_t n_total, const Buffers& b, void* grad, hipStream_t s);
+                              int64_t n_total, const float* w, const Buffers& b, void* grad,
+                              hipStream_t s);
 
 hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s);
 // direction: -1 forward, +1 inverse.  axis 0 = x (stride N*nz), 1 = y (stride nz), 2 = z (rows).
@@ -136,7 +153,9 @@ hipError_t launch_spectrum_power(const Geom& g, const Buffers& b, const double* 
                                  int64_t* nmodes, hipStream_t s);
 // direct summation (eq. deltaDS) over every half-space mode
 size_t direct_workspace(int ngrid, int64_t n);
-hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, void* ws,
+// w: masses (null: equal masses), normalised by their sum
+hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, const float* w,
+                         void* ws,
                          double* out, hipStream_t s);
 // bispectrum
 hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,

@@ -371,12 +371,13 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   }
 }
 
-// P_b = V S_b / (N_P^2 N_b) [- V/N_P], k_b = k_f K_b / N_b; one wave per
+// P_b = V S_b / (W^2 N_b) [- V sum w^2 / W^2], k_b = k_f K_b / N_b, with W the
+// total mass (W = sum w^2 = N_P for equal masses); one wave per
 // (bin, set) sums the per-workgroup partials in a fixed order.
 __global__ __launch_bounds__(64) void k_power_finalize(const double* __restrict__ partials, int nblk,
                                                        int n_bins, const int64_t* __restrict__ mode_n,
                                                        const double* __restrict__ mode_k,
-                                                       const int64_t* __restrict__ np, double box,
+                                                       const double* __restrict__ norm, double box,
                                                        int subtract, double* k, double* p,
                                                        int64_t* nmodes) {
   const int b = blockIdx.x;
@@ -389,10 +390,11 @@ __global__ __launch_bounds__(64) void k_power_finalize(const double* __restrict_
   if (threadIdx.x != 0) return;
   const double vol = box * box * box;
   const double nb = (double)mode_n[b];
-  const double npart = (double)np[mock];
+  // total mass W (N_P for equal masses); shot noise V (sum w^2 / W) / W
+  const double npart = norm[2 * mock];
   double pk = vol * s / (npart * npart * nb);
-  if (subtract) pk -= vol / npart;
-  if (np[mock] <= 0) pk = __builtin_nan("");
+  if (subtract) pk -= vol * (norm[2 * mock + 1] / npart) / npart;
+  if (!(npart > 0.0)) pk = __builtin_nan("");
   const int64_t o = (int64_t)mock * n_bins + b;
   p[o] = pk;
   k[o] = (2.0 * M_PI / box) * mode_k[b] / nb;
@@ -401,14 +403,14 @@ __global__ __launch_bounds__(64) void k_power_finalize(const double* __restrict_
 
 // coefficient 2 g_b V / (N_b N_P^2) of the adjoint spectrum
 __global__ void k_adjoint_coef(const double* __restrict__ dldp, int n_bins, const int64_t* __restrict__ mode_n,
-                               const int64_t* __restrict__ np, double box, double* coef) {
+                               const double* __restrict__ norm, double box, double* coef) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int mock = blockIdx.y;
   if (b >= n_bins) return;
   const double vol = box * box * box;
-  const double npart = (double)np[mock];
+  const double npart = norm[2 * mock];
   const int64_t o = (int64_t)mock * n_bins + b;
-  coef[o] = (np[mock] > 0) ? 2.0 * dldp[o] * vol / ((double)mode_n[b] * npart * npart) : 0.0;
+  coef[o] = (npart > 0.0) ? 2.0 * dldp[o] * vol / ((double)mode_n[b] * npart * npart) : 0.0;
 }
 
 template <int L, bool IL, int MODE>
@@ -482,7 +484,7 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
                         : pairs_dispatch<1>(g, b, nblk, n_dk, n_bins, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_power_finalize, dim3(n_bins, g.batch), dim3(64), 0, s,
-                     b.partials, nblk, n_bins, b.mode_n, b.mode_k, b.np, g.box, subtract_shot, k, p,
+                     b.partials, nblk, n_bins, b.mode_n, b.mode_k, b.norm, g.box, subtract_shot, k, p,
                      nmodes);
   return hipGetLastError();
 }
@@ -490,7 +492,7 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
 hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& tu,
                                    const double* dldp, int n_dk, int n_bins, hipStream_t s) {
   hipLaunchKernelGGL(k_adjoint_coef, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s, dldp,
-                     n_bins, b.mode_n, b.np, g.box, b.coef);
+                     n_bins, b.mode_n, b.norm, g.box, b.coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nblk = pair_blocks(g, tu);
@@ -606,20 +608,20 @@ __device__ void delta_at(const float2* __restrict__ data, const Geom& g, int moc
 
 __global__ void k_sample_delta(const float2* __restrict__ data, Geom g, int mock,
                                const int32_t* __restrict__ modes, int64_t nm,
-                               const int64_t* __restrict__ np, double* __restrict__ out) {
+                               const double* __restrict__ norm, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nm) return;
-  delta_at(data, g, mock, modes[3 * i], modes[3 * i + 1], modes[3 * i + 2], (double)np[mock],
+  delta_at(data, g, mock, modes[3 * i], modes[3 * i + 1], modes[3 * i + 2], norm[2 * mock],
            out[2 * i], out[2 * i + 1]);
 }
 
 // every half-space mode, index (ix * N + iy) * (N/2 + 1) + m_z (FFT indices
 // ix, iy; index N/2 is +N/2)
 __global__ void k_export_delta(const float2* __restrict__ data, Geom g, int mock,
-                               const int64_t* __restrict__ np, double* __restrict__ out) {
+                               const double* __restrict__ norm, double* __restrict__ out) {
   const int n = g.n, nh = n / 2 + 1;
   const int64_t nm = (int64_t)n * n * nh;
-  const double npart = (double)np[mock];
+  const double npart = norm[2 * mock];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nm;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int mz = (int)(i % nh);
@@ -631,7 +633,7 @@ __global__ void k_export_delta(const float2* __restrict__ data, Geom g, int mock
 
 hipError_t launch_export_delta(const Geom& g, const Buffers& b, int mock, double* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_export_delta, dim3(4096), dim3(256), 0, s, b.grid, g, mock, b.np, out);
+  hipLaunchKernelGGL(k_export_delta, dim3(4096), dim3(256), 0, s, b.grid, g, mock, b.norm, out);
   return hipGetLastError();
 }
 
@@ -714,7 +716,7 @@ hipError_t launch_spectrum_power(const Geom& g, const Buffers& b, const double* 
 hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,
                                int64_t n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sample_delta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.grid, g,
-                     mock, modes, n, b.np, out);
+                     mock, modes, n, b.norm, out);
   return hipGetLastError();
 }
 
@@ -725,12 +727,12 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
                                                     int n_dk, int b1, int b2, int counts_only,
                                                     const float2* __restrict__ phase,
                                                     const float* __restrict__ win1,
-                                                    const int64_t* __restrict__ np,
+                                                    const double* __restrict__ norm,
                                                     float2* __restrict__ out) {
   const int n = g.n;
   const int64_t n3 = (int64_t)n * n * n;
   const int L = g.nz;
-  const float inv_np = 1.0f / (float)np[mock];
+  const float inv_np = 1.0f / (float)norm[2 * mock];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(i / ((int64_t)n * n)), y = (int)((i / n) % n), z = (int)(i % n);
@@ -763,7 +765,7 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
 hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
                              bool counts_only, float2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_shell_pair, dim3(8192), dim3(256), 0, s, b.grid, g, mock, n_dk, b1, b2,
-                     counts_only ? 1 : 0, b.phase, b.win1, b.np, out);
+                     counts_only ? 1 : 0, b.phase, b.win1, b.norm, out);
   return hipGetLastError();
 }
 

@@ -8,11 +8,12 @@ estimator runs in the HIP kernels of ``libfsest.so``.
 import numpy as np
 import torch
 
-from . import (EST_F32, EST_F64, EST_FLAG_ATOMIC_SORT, estimator_autotune, estimator_backward, estimator_bispectrum,
+from . import (EST_F32, EST_F64, EST_FLAG_ATOMIC_SORT, EST_FLAG_WEIGHTS, estimator_autotune, estimator_backward, estimator_bispectrum,
                estimator_bispectrum_workspace_bytes, estimator_copy_grid, estimator_create,
                estimator_deposit, estimator_destroy, estimator_direct_delta,
                estimator_direct_workspace_bytes, estimator_export_delta, estimator_graph_capture,
                estimator_graph_launch, estimator_power, estimator_sample_delta, estimator_set_launch,
+               estimator_set_weights,
                estimator_spectrum_power, estimator_transform, estimator_workspace_bytes,
                make_config)
 
@@ -42,20 +43,36 @@ class Estimator:
     """One handle: grid size N, box L, order p, interlacing, batch of sets."""
 
     def __init__(self, n_grid, box, order=4, interlace=True, batch=1, max_particles=1 << 20,
-                 device="cuda", stream=None, atomic_sort=False):
+                 device="cuda", stream=None, atomic_sort=False, weighted=False):
         self.n_grid = int(n_grid)
         self.box = float(box)
         self.order = int(order)
         self.interlace = bool(interlace)
         self.batch = int(batch)
         self.device = torch.device(device)
-        self.cfg = make_config(n_grid, box, order, int(interlace), batch, max_particles,
-                               EST_FLAG_ATOMIC_SORT if atomic_sort else 0)
+        flags = (EST_FLAG_ATOMIC_SORT if atomic_sort else 0) | (EST_FLAG_WEIGHTS if weighted else 0)
+        self.cfg = make_config(n_grid, box, order, int(interlace), batch, max_particles, flags)
         self.ws_bytes = estimator_workspace_bytes(self.cfg)
         self._ws, self._ws_ptr = _aligned_workspace(self.ws_bytes, self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.h = estimator_create(self.cfg, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
         self._graph_bufs = None
+        self._weights = None
+
+    def set_weights(self, weights):
+        """Per-particle masses (float32 device tensor of n entries, in the
+        order of the positions of the following calls) or None for equal
+        masses.  The tensor is kept alive by the handle."""
+        if weights is not None:
+            if not weights.is_cuda or weights.dtype != torch.float32 or weights.dim() != 1 \
+                    or not weights.is_contiguous():
+                raise ValueError("weights must be a contiguous float32 device vector")
+        estimator_set_weights(self.h, weights)
+        self._weights = weights
+
+    def _check_weights(self, n):
+        if self._weights is not None and self._weights.shape[0] < n:
+            raise ValueError("weights hold %d entries, %d particles given" % (self._weights.shape[0], n))
 
     def close(self):
         if getattr(self, "h", None) is not None:
@@ -80,6 +97,7 @@ class Estimator:
     # ---- forward
     def deposit(self, pos, offsets=None):
         _check_pos(pos)
+        self._check_weights(pos.shape[0])
         estimator_deposit(self.h, pos, _dtype_code(pos), offsets, pos.shape[0])
 
     def transform(self):
@@ -121,6 +139,7 @@ class Estimator:
         dldp = dldp.to(device=self.device, dtype=torch.float64).contiguous()
         if dldp.numel() != self.batch * n_bins:
             raise ValueError("dL/dP must have batch * n_bins entries")
+        self._check_weights(pos.shape[0])
         grad = torch.empty_like(pos)
         estimator_backward(self.h, pos, _dtype_code(pos), offsets, pos.shape[0], dldp, n_dk,
                            n_bins, grad)
@@ -130,6 +149,7 @@ class Estimator:
     def capture(self, pos, offsets=None, n_dk=1, n_bins=None, subtract_shot=False):
         _check_pos(pos)
         n_bins = n_bins or self.default_bins(n_dk)
+        self._check_weights(pos.shape[0])
         k, p, nm = self._outputs(n_bins)
         estimator_graph_capture(self.h, pos, _dtype_code(pos), offsets, pos.shape[0], n_dk,
                                 n_bins, int(subtract_shot), k, p, nm)
@@ -143,6 +163,7 @@ class Estimator:
     def autotune(self, pos, offsets=None, n_dk=1, n_bins=None, iters=3):
         _check_pos(pos)
         n_bins = n_bins or self.default_bins(n_dk)
+        self._check_weights(pos.shape[0])
         return estimator_autotune(self.h, pos, _dtype_code(pos), offsets, pos.shape[0], n_dk,
                                   n_bins, iters)
 
@@ -170,6 +191,7 @@ class Estimator:
         """delta_DS on the half spectrum ([N, N, N/2+1, 2] float64) by direct summation."""
         _check_pos(pos)
         n = pos.shape[0]
+        self._check_weights(n)
         nbytes = estimator_direct_workspace_bytes(self.h, n)
         ws, ws_ptr = _aligned_workspace(nbytes, self.device)
         out = self._half()

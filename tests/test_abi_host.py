@@ -64,7 +64,7 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(box=float("nan")), fsest.EST_EINVAL),
     (dict(max_particles=0), fsest.EST_EINVAL),
     (dict(max_particles=1 << 31), fsest.EST_EINVAL),
-    (dict(flags=2), fsest.EST_EINVAL),
+    (dict(flags=4), fsest.EST_EINVAL),
     (dict(flags=-1), fsest.EST_EINVAL),
     (dict(n_grid=28), fsest.EST_EUNSUPPORTED),   # prime factor 7
     (dict(n_grid=90), fsest.EST_EUNSUPPORTED),   # not a multiple of the 4-cell bucket
@@ -136,6 +136,24 @@ def test_package_binds_to_one_hip_runtime():
 def test_mixed_radix_grid_sizes_accepted(n):
     """N = 2^a 3^b 5^c, a multiple of 4 (the paper's N_G = 100 and 480)."""
     assert fsest.estimator_workspace_bytes(_cfg(n_grid=n)) > 2 * 4 * n ** 3
+
+
+def test_weights_flag_reserves_mass_buffers():
+    """EST_FLAG_WEIGHTS adds the bucket-order and staging copies of the
+    masses (4 + 4 bytes per particle) and the per-set mass partial sums."""
+    base = fsest.estimator_workspace_bytes(_cfg(n_grid=64, max_particles=1 << 16))
+    wtd = fsest.estimator_workspace_bytes(_cfg(n_grid=64, max_particles=1 << 16,
+                                               flags=fsest.EST_FLAG_WEIGHTS))
+    both = fsest.estimator_workspace_bytes(_cfg(n_grid=64, max_particles=1 << 16,
+                                                flags=fsest.EST_FLAG_WEIGHTS | fsest.EST_FLAG_ATOMIC_SORT))
+    assert wtd >= base + 8 * (1 << 16)
+    assert both > 0
+
+
+def test_set_weights_null_handle():
+    with pytest.raises(fsest.FsestError) as ei:
+        fsest.estimator_set_weights(None, None)
+    assert ei.value.status == fsest.EST_EINVAL
 
 
 def test_atomic_sort_flag_accepted_and_drops_two_level_buffers():
