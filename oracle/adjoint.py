@@ -31,8 +31,8 @@ import scipy.fft
 
 from .assign import deposit_u, grid_coords, stencil
 from .kernels import dweight
-from .spectrum import (bin_index, fft_grid, half_axes, half_weights, interlace,
-                       mode_table, window)
+from .spectrum import (bin_index, combine, fft_grid, half_axes, half_weights, mask_shift,
+                       mode_table, shift_masks, window)
 
 
 def chi2_loss(pk, target, counts):
@@ -47,13 +47,9 @@ def grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights=None
     With masses, N_P above is the total mass W (the masses are constants)."""
     n_p = pos.shape[0] if weights is None else float(np.sum(np.asarray(weights, dtype=np.float64)))
     u = grid_coords(pos, box, n)
-    rho1 = deposit_u(u, p, n, weights)
-    f1 = fft_grid(rho1)
-    if interlace_on:
-        f2 = fft_grid(deposit_u(u + 0.5, p, n, weights))
-        c = interlace(f1, f2, n)
-    else:
-        c = f1
+    masks = shift_masks(interlace_on)
+    fs = [fft_grid(deposit_u(u + mask_shift(mk), p, n, weights)) for mk in masks]
+    c = combine(fs, masks, n) if len(masks) > 1 else fs[0]
     win = window(n, p)
     mx, my, mz = half_axes(n)
     m2 = mx * mx + my * my + mz * mz
@@ -66,28 +62,27 @@ def grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights=None
                     / (counts[bb] * float(n_p) ** 2), 0.0)
     gamma = coef * c / (win * win)
     w = np.broadcast_to(half_weights(n), m2.shape)
-    phases = [np.zeros(m2.shape)]
-    if interlace_on:
-        phases.append(np.broadcast_to(np.pi * (mx + my + mz) / n, m2.shape))
+    m = (mx, my, mz)
+    phases = [np.broadcast_to(np.pi * sum((m[a] if (mk >> a) & 1 else 0) for a in range(3)) / n,
+                              m2.shape).astype(np.float64) for mk in masks]
     grads = []
-    half = 0.5 if interlace_on else 1.0  # dC/dF_a: 1/2 with interlacing, 1 without
+    frac = 1.0 / len(masks)  # dC/dF_j = exp(+i phi_j) / G
     for ph in phases:
-        ga = half * gamma * np.exp(-1j * ph)
+        ga = frac * gamma * np.exp(-1j * ph)
         full = np.zeros((n, n, n), dtype=np.complex128)
         full[:, :, : n // 2 + 1] = w * ga
         grads.append(np.real(scipy.fft.ifftn(full, workers=-1)) * float(n) ** 3)
-    return u, grads
+    return u, grads, masks
 
 
 def position_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights=None):
     """dL/dx_j (N_P, 3) for a given dL/dP_b (n_bins,); a particle of mass
     w_j deposits w_j times the kernel, so its gradient carries the factor w_j."""
     pos = np.asarray(pos)
-    u, grads = grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights)
+    u, grads, masks = grid_gradient(pos, box, n, p, interlace_on, n_dk, n_bins, dldp, weights)
     out = np.zeros((pos.shape[0], 3), dtype=np.float64)
-    shifts = [0.0, 0.5][: len(grads)]
-    for shift, gam in zip(shifts, grads):
-        ua = u + shift
+    for mk, gam in zip(masks, grads):
+        ua = u + mask_shift(mk)
         sten = []
         for ax in range(3):
             cells, w = stencil(ua[:, ax], p, n)

@@ -93,13 +93,22 @@ def delta_modes(pos, box, n, p, interlace_on, modes):
     """delta(m) = C(m) / (N_P W(m)) at signed modes (the oracle's steps 1-3
     evaluated mode by mode through the footprint DFT)."""
     from .kernels import window_1d
+    from .spectrum import mask_shift, shift_masks
     modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
-    f1 = footprint_dft(pos, box, n, p, modes, 0.0)
-    if interlace_on:
+    masks = shift_masks(interlace_on)
+    if len(masks) == 1:
+        c = footprint_dft(pos, box, n, p, modes, 0.0)
+    elif len(masks) == 2:
+        f1 = footprint_dft(pos, box, n, p, modes, 0.0)
         f2 = footprint_dft(pos, box, n, p, modes, 0.5)
         c = 0.5 * (f1 + np.exp(1j * np.pi * modes.sum(axis=1) / n) * f2)
     else:
-        c = f1
+        c = 0.0
+        for mk in masks:
+            sel = np.array([(mk >> a) & 1 for a in range(3)])
+            c = c + np.exp(1j * np.pi * (modes * sel).sum(axis=1) / n) \
+                * footprint_dft(pos, box, n, p, modes, mask_shift(mk))
+        c = c / len(masks)
     w = np.prod(window_1d(p, modes, n), axis=1)
     return c / (len(pos) * w)
 
@@ -108,6 +117,10 @@ def delta_half(pos, box, n, p, interlace_on):
     """Same as ``spectrum.delta_half`` with the deposit done by the C loops."""
     from . import spectrum
     pos = np.asarray(pos)
+    masks = spectrum.shift_masks(interlace_on)
+    if len(masks) > 2:
+        fs = [spectrum.fft_grid(deposit(pos, box, n, p, spectrum.mask_shift(mk))) for mk in masks]
+        return spectrum.combine(fs, masks, n) / (len(pos) * spectrum.window(n, p)), len(pos)
     f1 = spectrum.fft_grid(deposit(pos, box, n, p, 0.0))
     if interlace_on:
         f2 = spectrum.fft_grid(deposit(pos, box, n, p, 0.5))

@@ -9,6 +9,13 @@ Steps, in the paper's order:
    ``scipy.fft.rfftn``; half spectrum, last axis m_z = 0..N/2).
 2. Interlacing (eq. intdelta and the shift theorem above it):
    C = (F_1 + exp(+i pi (m_x+m_y+m_z)/N) F_2) / 2; without interlacing C = F_1.
+   More grids (Sec. 3.1 allows it without writing it out; reading): G grids
+   sampled at u + s_j, s_j in {0, 1/2}^3 forming a group under addition mod 1,
+   C = (1/G) sum_j F_j exp(+2 pi i m.s_j / N).  Image n then enters with
+   theta_n = 1 if n.s_j is an integer for every j, else 0.  Codes: 0 one
+   grid, 1 the paper's pair {0, (1,1,1)/2}, 2 the four face-centred shifts
+   {0, (1,1,0)/2, (1,0,1)/2, (0,1,1)/2} (no image with components of mixed
+   parity), 3 all eight shifts (no image with an odd component).
 3. Window deconvolution (eqs. windowcorrection, intkerFT):
    delta = C / (N_P W(m)),  W = prod_i [sin(pi m_i/N)/(pi m_i/N)]^p.
 4. Power in shells (eq. ps, the direct-summation estimator of Sec. 2.2, the
@@ -34,7 +41,7 @@ Readings (the paper is silent or garbled here):
 import numpy as np
 import scipy.fft
 
-from .assign import deposit
+from .assign import deposit, deposit_u, grid_coords
 from .kernels import window_1d
 
 
@@ -57,6 +64,31 @@ def fft_grid(rho, workers=None):
     if workers is None:
         workers = -1
     return scipy.fft.rfftn(rho, workers=workers)
+
+
+# shift sets: bit a of a mask shifts axis a by half a cell
+SHIFT_SETS = {0: (0,), 1: (0, 7), 2: (0, 3, 5, 6), 3: tuple(range(8))}
+
+
+def shift_masks(code):
+    """Masks of the grids for an interlacing code (bool True = 1)."""
+    return SHIFT_SETS[int(code)]
+
+
+def mask_shift(mask):
+    """Grid-coordinate shift (3,) of a mask: 1/2 on the axes whose bit is set."""
+    return 0.5 * np.array([(mask >> a) & 1 for a in range(3)], dtype=np.float64)
+
+
+def combine(fs, masks, n):
+    """C = (1/G) sum_j F_j exp(+i pi (sum of m_a over the shifted axes of j) / N)."""
+    mx, my, mz = half_axes(n)
+    m = (mx, my, mz)
+    c = 0.0
+    for f, mk in zip(fs, masks):
+        s = sum((m[a] if (mk >> a) & 1 else 0) for a in range(3))
+        c = c + np.exp(1j * np.pi * np.asarray(s, dtype=np.float64) / n) * f
+    return c / len(fs)
 
 
 def interlace(f1, f2, n):
@@ -146,6 +178,11 @@ def delta_half(pos, box, n, p, interlace_on, workers=None, weights=None):
     """delta(m) on the half spectrum (steps 1-3 above) and the total mass W
     (N_P for equal masses), which normalises it."""
     n_p, _ = total_weight(pos, weights)
+    if int(interlace_on) >= 2:
+        u = grid_coords(pos, box, n)
+        masks = shift_masks(interlace_on)
+        fs = [fft_grid(deposit_u(u + mask_shift(mk), p, n, weights), workers) for mk in masks]
+        return combine(fs, masks, n) / (n_p * window(n, p)), n_p
     rho1, rho2 = deposit(pos, box, n, p, interlace_on, weights)
     f1 = fft_grid(rho1, workers)
     if interlace_on:

@@ -85,8 +85,25 @@ def fres_1d_hurwitz(x, p, interlace=False):
 def white_noise_power(m, n_grid, p, interlace, deconvolve, vol, n_p):
     """Expected P(m) of uniformly random particles (see module docstring).
 
-    ``m`` has shape (..., 3) of signed integer frequencies.
+    ``m`` has shape (..., 3) of signed integer frequencies.  ``interlace`` is
+    the interlacing code (False/0, True/1, 2 face-centred, 3 all eight
+    shifts): for a shift set S, theta_n = (1/G) sum_{s in S} (-1)^(2 n.s), so
+    the expectation is V/N_P (1/G) sum_{s in S} prod_i (B_i if s_i = 1/2
+    else A_i), which gives the pair formula above for S = {0, (1,1,1)/2}.
     """
+    if int(interlace) >= 2:
+        from .spectrum import shift_masks
+        x = np.asarray(m, dtype=np.float64) / n_grid
+        a = image_sum_closed(x, p)
+        b = image_sum_closed(x, p, alternate=True)
+        if deconvolve:
+            win2 = np.sinc(x) ** (2 * p)
+            a, b = a / win2, b / win2
+        masks = shift_masks(interlace)
+        tot = 0.0
+        for mk in masks:
+            tot = tot + np.prod([b[..., i] if (mk >> i) & 1 else a[..., i] for i in range(3)], axis=0)
+        return vol / n_p * tot / len(masks)
     x = np.asarray(m, dtype=np.float64) / n_grid
     s = image_sum_closed(x, p)
     if deconvolve:

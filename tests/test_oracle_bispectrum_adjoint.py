@@ -94,7 +94,7 @@ def test_fft_shell_sum_matches_bruteforce_triplets(n, p, il):
     assert np.allclose(bk, box ** 6 * np.real(sums) / counts, rtol=1e-9)
 
 
-@pytest.mark.parametrize("p,il", [(4, True), (3, True), (2, False), (4, False)])
+@pytest.mark.parametrize("p,il", [(4, True), (3, True), (2, False), (4, False), (4, 2), (2, 3)])
 def test_adjoint_matches_finite_differences(p, il):
     n, box, n_dk, nb = 8, 100.0, 1, 4
     pos = synth.uniform(40, box, 77 + p, np.float64)
