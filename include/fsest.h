@@ -84,7 +84,15 @@ typedef struct {
                          /* above 16 also N >= 15 + order                      */
   int32_t order;         /* p = 1..6: NGP, CIC, TSC, PCS (Sec. 2.3), then the  */
                          /* order-5/6 B-splines (p-fold box convolutions)      */
-  int32_t interlace;     /* 0 or 1: second grid shifted by H/2 (Sec. 3.1)     */
+  int32_t interlace;     /* 0: one grid; 1: second grid shifted by H/2 on     */
+                         /* every axis (Sec. 3.1, eq. intdelta); more grids    */
+                         /* (Sec. 3.1 mentions them without writing them out): */
+                         /* 2: four grids, shifts 0, (1,1,0), (1,0,1), (0,1,1) */
+                         /* times H/2 (no alias image of mixed parity); 3: all */
+                         /* eight H/2 shift combinations (no image with an odd */
+                         /* component).  delta = (1/G) sum_j F_j e^{ik.s_j}.   */
+                         /* Codes 2, 3 take G/2 complex grids per set and no   */
+                         /* estimator_backward (EUNSUPPORTED).                 */
   int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
   double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */
   int64_t max_particles; /* upper bound of n_total per call, 1 .. 2^31-1      */
@@ -162,7 +170,8 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk,
  * dL/dP_b (device float64 [batch][n_bins]) writes dL/dx (device, same dtype
  * and layout as pos) for every particle.  The grids are recomputed from pos
  * (nothing is kept from the forward); the handle's grids are overwritten.
- * Same argument rules as estimator_deposit and estimator_power. */
+ * Same argument rules as estimator_deposit and estimator_power;
+ * EUNSUPPORTED for interlace codes 2 and 3. */
 est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype,
                               const int64_t* offsets, int64_t n_total,
                               const double* dldp, int32_t n_dk, int32_t n_bins,
@@ -214,7 +223,8 @@ est_status estimator_set_launch(est_handle h, int32_t choice);
  * EST_FLAG_WEIGHTS. */
 est_status estimator_set_weights(est_handle h, const float* weights);
 
-/* Test hook: copy grid `which` (1 = primary, 2 = interlaced) of set `mock`
+/* Test hook: copy grid `which` (1 = primary, 2 = interlaced; up to 8 with
+ * interlace codes 2, 3, in the order of their shifts) of set `mock`
  * as float32 [N][N][N] (z fastest) to dst (device).  ESTATE unless the last
  * call was estimator_deposit. */
 est_status estimator_copy_grid(est_handle h, int32_t which, int32_t mock,

@@ -128,8 +128,8 @@ void prof_fold(est_ctx* h) {
 est_status check_config(const est_config* c) {
   if (!c) return fail(EST_EINVAL, "config is NULL");
   if (c->order < 1 || c->order > 6) return fail(EST_EINVAL, "order must be 1..6 (got %d)", c->order);
-  if (c->interlace != 0 && c->interlace != 1)
-    return fail(EST_EINVAL, "interlace must be 0 or 1 (got %d)", c->interlace);
+  if (c->interlace < 0 || c->interlace > 3)
+    return fail(EST_EINVAL, "interlace must be 0, 1, 2 or 3 (got %d)", c->interlace);
   if (c->batch < 1 || c->batch > 65535) return fail(EST_EINVAL, "batch must be 1..65535 (got %d)", c->batch);
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return fail(EST_EINVAL, "box must be finite and > 0");
   if (c->max_particles < 1 || c->max_particles > 2147483647LL)
@@ -154,8 +154,11 @@ Geom make_geom(const est_config& c) {
   Geom g;
   g.n = c.n_grid;
   g.nz = c.interlace ? c.n_grid : c.n_grid / 2;
+  g.code = c.interlace;
+  g.ng = 1 << (c.interlace == 0 ? 0 : c.interlace);  // 1, 2, 4, 8
+  g.npair = g.ng > 1 ? g.ng / 2 : 1;
   g.order = c.order;
-  g.il = c.interlace;
+  g.il = c.interlace ? 1 : 0;
   g.batch = c.batch;
   g.nb = c.n_grid / kBucket;
   // largest divisor of nb up to kFineMax (at least 5 whenever nb > kFineMax,
@@ -187,7 +190,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   };
   const size_t nkeys = batch * (size_t)g.nb * g.nb * g.nb + 1;
   Buffers bb;
-  bb.grid = (float2*)take(batch * n * (size_t)g.ps * sizeof(float2));
+  bb.grid = (float2*)take(batch * g.npair * n * (size_t)g.ps * sizeof(float2));
   bb.sorted = take((size_t)c.max_particles * 3 * sizeof(double));
   bb.cells = (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t));
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
@@ -297,30 +300,33 @@ est_status run_xy(est_handle h, int dir) {
   if (dir < 0) {
     {
       ProfScope ps(h, kPFftX);
-      st = dev_err(launch_fft_axis(h->g, h->b.grid, 0, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft x");
+      st = dev_err(launch_fft_axis(h->g, h->b.grid, 0, -1, h->g.batch * h->g.npair, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft x");
       if (st) return st;
     }
     ProfScope ps(h, kPFftY);
-    return dev_err(launch_fft_axis(h->g, h->b.grid, 1, -1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft y");
+    return dev_err(launch_fft_axis(h->g, h->b.grid, 1, -1, h->g.batch * h->g.npair, h->g.nz, h->b.tw_n, h->tu, h->stream), "fft y");
   }
   {
     ProfScope ps(h, kPIfftY);
-    st = dev_err(launch_fft_axis(h->g, h->b.grid, 1, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft y");
+    st = dev_err(launch_fft_axis(h->g, h->b.grid, 1, +1, h->g.batch * h->g.npair, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft y");
     if (st) return st;
   }
   ProfScope ps(h, kPIfftX);
-  return dev_err(launch_fft_axis(h->g, h->b.grid, 0, +1, h->g.batch, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft x");
+  return dev_err(launch_fft_axis(h->g, h->b.grid, 0, +1, h->g.batch * h->g.npair, h->g.nz, h->b.tw_n, h->tu, h->stream), "ifft x");
 }
 
 est_status to_spectrum(est_handle h) {
   if (h->state == kSpectrum) return ok();
   if (h->state != kXY) return fail(EST_ESTATE, "needs estimator_transform first");
   ProfScope ps(h, kPFftZ);
-  est_status st = dev_err(launch_fft_axis(h->g, h->b.grid, 2, -1, h->g.batch, h->g.nz, h->b.tw_nz, h->tu, h->stream), "fft z");
+  est_status st = dev_err(launch_fft_axis(h->g, h->b.grid, 2, -1, h->g.batch * h->g.npair, h->g.nz, h->b.tw_nz, h->tu, h->stream), "fft z");
   if (st) return st;
   h->state = kSpectrum;
   return ok();
 }
+
+// state after a forward pass: the multi-grid power needs the z pass first
+int forward_state(est_handle h) { return h->g.npair > 1 ? kSpectrum : kXY; }
 
 est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
                        int64_t n_total, int n_dk, int n_bins, int sub, double* k, double* p,
@@ -329,6 +335,13 @@ est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_
   if (st) return st;
   st = run_xy(h, -1);
   if (st) return st;
+  if (h->g.npair > 1) {
+    // several slabs per set: separate z pass, then the multi-grid shell sums
+    h->state = kXY;
+    if ((st = to_spectrum(h))) return st;
+    ProfScope ps(h, kPPower);
+    return dev_err(launch_power(h->g, h->b, h->tu, false, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
+  }
   ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, true, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
 }
@@ -419,6 +432,7 @@ est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins, int32_t s
   if (h->state != kXY && h->state != kSpectrum)
     return fail(EST_ESTATE, "estimator_power needs estimator_transform first");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
+  if (h->g.npair > 1 && (st = to_spectrum(h))) return st;
   ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, h->state == kXY, n_dk, n_bins, subtract_shot, k, p,
                               nmodes, h->stream),
@@ -527,6 +541,8 @@ est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype, co
   if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
   if ((st = check_bins(h, n_dk, n_bins))) return st;
   if (!dldp || !grad) return fail(EST_EINVAL, "NULL device pointer");
+  if (h->g.npair > 1)
+    return fail(EST_EUNSUPPORTED, "the adjoint supports one grid or the interlaced pair only");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
   h->state = kCreated;
   if ((st = run_deposit(h, pos, dtype, offsets, n_total))) return st;
@@ -586,7 +602,7 @@ est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtyp
   h->stream = saved;
   h->capturing = false;
   hipStreamDestroy(cs);
-  h->state = (st == EST_OK) ? kXY : kCreated;
+  h->state = (st == EST_OK) ? forward_state(h) : kCreated;
   return st;
 }
 
@@ -595,7 +611,7 @@ est_status estimator_graph_launch(est_handle h) {
   if (st) return st;
   if (!h->exec) return fail(EST_ESTATE, "no captured graph");
   if ((st = dev_err(hipGraphLaunch(h->exec, h->stream), "graph launch"))) return st;
-  h->state = kXY;
+  h->state = forward_state(h);
   return ok();
 }
 
@@ -688,7 +704,7 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   h->tu = (st == EST_OK) ? make(idx) : saved;
-  h->state = (st == EST_OK) ? kXY : kCreated;
+  h->state = (st == EST_OK) ? forward_state(h) : kCreated;
   if (st == EST_OK && choice) *choice = (((idx[0] * 3 + idx[1]) * 2 + idx[2]) * 2 + idx[3]) * 2 + idx[4];
   return st;
 }
@@ -696,8 +712,8 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
 est_status estimator_copy_grid(est_handle h, int32_t which, int32_t mock, float* dst) {
   est_status st = check_handle(h);
   if (st) return st;
-  if (which != 1 && which != 2) return fail(EST_EINVAL, "which must be 1 or 2");
-  if (which == 2 && !h->g.il) return fail(EST_EINVAL, "grid 2 exists only with interlacing");
+  if (which < 1 || which > h->g.ng)
+    return fail(EST_EINVAL, "which must be 1..%d (grids of this handle)", h->g.ng);
   if (mock < 0 || mock >= h->g.batch) return fail(EST_EINVAL, "mock out of range");
   if (!dst) return fail(EST_EINVAL, "dst is NULL");
   if (h->state != kDeposited) return fail(EST_ESTATE, "grids are only available right after a deposit");

@@ -856,13 +856,14 @@ __device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
 // Adds one grid's footprint of one particle to the tile.
 template <int P, typename AT, int WRAP>
 __device__ __forceinline__ void deposit_item(double x, double y, double z, int gi, const Geom& g,
-                                             int t0x, int t0y, int t0z, AT* sm, float scale) {
+                                             int t0x, int t0y, int t0z, AT* sm, float scale,
+                                             int mk) {
   const int n = g.n;
-  const double sh = gi ? 0.5 : 0.0;
+  // grid gi is sampled at u + 1/2 on the axes whose bit is set in its mask mk
   float wx[P], wy[P], wz[P];
-  const int fx = stencil_first<P>(grid_coord(x, g.box, g.inv) + sh, scale, wx);
-  const int fy = stencil_first<P>(grid_coord(y, g.box, g.inv) + sh, 1.0f, wy);
-  const int fz = stencil_first<P>(grid_coord(z, g.box, g.inv) + sh, 1.0f, wz);
+  const int fx = stencil_first<P>(grid_coord(x, g.box, g.inv) + ((mk & 1) ? 0.5 : 0.0), scale, wx);
+  const int fy = stencil_first<P>(grid_coord(y, g.box, g.inv) + ((mk & 2) ? 0.5 : 0.0), 1.0f, wy);
+  const int fz = stencil_first<P>(grid_coord(z, g.box, g.inv) + ((mk & 4) ? 0.5 : 0.0), 1.0f, wz);
   constexpr bool PERIODIC = WRAP == kPeriodic;
   const int rx = rel_first<P, WRAP>(fx, t0x, n);
   const int ry = rel_first<P, WRAP>(fy, t0y, n);
@@ -935,14 +936,17 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // neighbouring tiles share are read through one L2.
 // WT: per-particle masses (sw, bucket order, divided by the largest mass);
 // a separate instantiation so that the equal-mass kernel keeps its registers
-template <int P, bool IL, typename TP, bool WIDE, int WRAP, bool WT>
+// IL: 0 one grid; 1 the interlaced pair (masks 0 and 7); 2 a pair of grids
+// with run-time masks (mask_a, mask_b) written to slab q of each set
+template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT>
 __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
                                                   const uint64_t* __restrict__ cells,
                                                   const uint32_t* __restrict__ boff,
                                                   const uint32_t* __restrict__ bcnt, float* grid,
                                                   Geom g, uint32_t* __restrict__ stats,
                                                   int exclusive, int dynamic, int xcd,
-                                                  const float* __restrict__ sw) {
+                                                  const float* __restrict__ sw, int q, int mask_a,
+                                                  int mask_b) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int NG = IL ? 2 : 1;
   constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
@@ -1097,9 +1101,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
           const int cz = (int)((r >> 32) & 0xFFFF) - off;
 #pragma unroll
           for (int gi = 0; gi < NG; ++gi) {
-            const int sx = gi ? (int)((r >> 48) & 1) : 0;
-            const int sy = gi ? (int)((r >> 49) & 1) : 0;
-            const int sz = gi ? (int)((r >> 50) & 1) : 0;
+            const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
+            const int sx = (mk & 1) ? (int)((r >> 48) & 1) : 0;
+            const int sy = (mk & 2) ? (int)((r >> 49) & 1) : 0;
+            const int sz = (mk & 4) ? (int)((r >> 50) & 1) : 0;
             const int rx = rel_first<P, WRAP>(cx + sx, t0x, n);
             const int ry = rel_first<P, WRAP>(cy + sy, t0y, n);
             const int rz = rel_first<P, WRAP>(cz + sz, t0z, n);
@@ -1192,8 +1197,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
             if (e_cur >= 0) {
               float sc = scale;
               if constexpr (WT) sc *= sw[item_j[e_cur]];
-              deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz,
-                                            item_meta[e_cur] >> 6, g, t0x, t0y, t0z, sm, sc);
+              const int gi = item_meta[e_cur] >> 6;
+              const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
+              deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz, gi, g, t0x, t0y, t0z,
+                                        sm, sc, mk);
             }
             e_cur = e_nxt;
             px = nx;
@@ -1210,6 +1217,7 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
     }
 
     // (3) write the tile (halo cells dropped, or folded back when periodic)
+    const int slab = (IL == 2) ? mock * g.npair + q : mock;
     if constexpr (WRAP != kPeriodic) {
       // four consecutive z cells per thread; the narrow scale is a power of
       // two, so float(sum) * 2^-F rounds exactly like the double product
@@ -1230,11 +1238,11 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
         }
         if constexpr (IL) {
           float4* dst = reinterpret_cast<float4*>(
-              reinterpret_cast<float2*>(grid) + complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz));
+              reinterpret_cast<float2*>(grid) + complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz));
           dst[0] = make_float4(v[0][0], v[NG - 1][0], v[0][1], v[NG - 1][1]);
           dst[1] = make_float4(v[0][2], v[NG - 1][2], v[0][3], v[NG - 1][3]);
         } else {
-          *reinterpret_cast<float4*>(grid + real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)) =
+          *reinterpret_cast<float4*>(grid + real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)) =
               make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
         }
       }
@@ -1250,10 +1258,10 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
           v[gi] = (float)((double)s * inv_scale) * wmul;
         }
         if constexpr (IL) {
-          reinterpret_cast<float2*>(grid)[complex_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] =
+          reinterpret_cast<float2*>(grid)[complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] =
               make_float2(v[0], v[NG - 1]);
         } else {
-          grid[real_cell_index(g, mock, t0x + lx, t0y + ly, t0z + lz)] = v[0];
+          grid[real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] = v[0];
         }
       }
     }
@@ -1269,54 +1277,65 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   }
 }
 
-template <int P, bool IL, typename TP, int WRAP, bool WT>
+template <int P, int IL, typename TP, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
-                           const float* sw, hipStream_t s) {
+                           const float* sw, int q, int ma, int mb, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   if (narrow)
     hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT>), dim3((unsigned)ntiles), dim3(threads),
                        0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0,
-                       0, xcd ? 1 : 0, sw);
+                       0, xcd ? 1 : 0, sw, q, ma, mb);
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
   const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
   hipLaunchKernelGGL((k_deposit<P, IL, TP, true, WRAP, WT>), dim3(wblocks), dim3(threads), 0, s,
                      (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats,
-                     narrow ? 0 : 1, 1, 0, sw);
+                     narrow ? 0 : 1, 1, 0, sw, q, ma, mb);
 }
 
-template <int P, bool IL, int WRAP>
+template <int P, int IL, int WRAP>
 static void dispatch_deposit_w(const Geom& g, est_dtype dt, const Buffers& b, int threads,
-                               bool narrow, bool xcd, const float* sw, hipStream_t s) {
+                               bool narrow, bool xcd, const float* sw, int q, int ma, int mb,
+                               hipStream_t s) {
   if (sw) {
-    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, true>(g, b, threads, narrow, xcd, sw, s);
-    else deposit_launch<P, IL, double, WRAP, true>(g, b, threads, narrow, xcd, sw, s);
+    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    else deposit_launch<P, IL, double, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
   } else {
-    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, false>(g, b, threads, narrow, xcd, nullptr, s);
-    else deposit_launch<P, IL, double, WRAP, false>(g, b, threads, narrow, xcd, nullptr, s);
+    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
+    else deposit_launch<P, IL, double, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
   }
 }
 
-template <int P, bool IL>
+template <int P, int IL>
 static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                               int threads, const float* sw, hipStream_t s) {
+                               int threads, const float* sw, int q, int ma, int mb, hipStream_t s) {
   const bool narrow = tu.dep_narrow != 0;
   const bool xcd = tu.dep_xcd != 0;
   if (g.tile == g.n)
-    dispatch_deposit_w<P, IL, kPeriodic>(g, dt, b, threads, narrow, xcd, sw, s);
+    dispatch_deposit_w<P, IL, kPeriodic>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
   else if ((g.n & (g.n - 1)) == 0)
-    dispatch_deposit_w<P, IL, kMasked>(g, dt, b, threads, narrow, xcd, sw, s);
+    dispatch_deposit_w<P, IL, kMasked>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
   else
-    dispatch_deposit_w<P, IL, kGeneral>(g, dt, b, threads, narrow, xcd, sw, s);
+    dispatch_deposit_w<P, IL, kGeneral>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
 }
 
 template <int P>
 static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
                                int threads, const float* sw, hipStream_t s) {
-  if (g.il) dispatch_deposit_t<P, true>(g, dt, b, tu, threads, sw, s);
-  else dispatch_deposit_t<P, false>(g, dt, b, tu, threads, sw, s);
+  if (g.code == 0) {
+    dispatch_deposit_t<P, 0>(g, dt, b, tu, threads, sw, 0, 0, 0, s);
+  } else if (g.code == 1) {
+    dispatch_deposit_t<P, 1>(g, dt, b, tu, threads, sw, 0, 0, 7, s);
+  } else {
+    // one pass per slab; the 64-bit kernel's tile counter restarts each time
+    for (int q = 0; q < g.npair; ++q) {
+      if (q > 0) launch_fill_u32(b.stats + 1, 1, 0u, s);
+      dispatch_deposit_t<P, 2>(g, dt, b, tu, threads, sw, q, grid_mask(g.code, 2 * q),
+                               grid_mask(g.code, 2 * q + 1), s);
+    }
+  }
 }
 
 hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
@@ -1343,10 +1362,12 @@ __global__ void k_copy_grid(const float* grid, Geom g, int which, int mock, floa
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n3; i += stride) {
     const int x = (int)(i / ((int64_t)n * n)), y = (int)((i / n) % n), z = (int)(i % n);
+    // grid `which` (1-based) is component (which - 1) % 2 of slab (which - 1) / 2
+    const int slab = mock * g.npair + (which - 1) / 2;
     if (g.il)
-      dst[i] = grid[2 * complex_index(g, mock, x, y, z) + (which - 1)];
+      dst[i] = grid[2 * complex_index(g, slab, x, y, z) + ((which - 1) & 1)];
     else
-      dst[i] = grid[real_cell_index(g, mock, x, y, z)];
+      dst[i] = grid[real_cell_index(g, slab, x, y, z)];
   }
 }
 

@@ -23,7 +23,11 @@ struct Geom {
   int n;          // N
   int nz;         // complex length of the contiguous axis: N (interlaced) or N/2
   int order;      // p
-  int il;         // interlacing on/off
+  int il;         // grids packed in pairs as complex (interlacing code >= 1)
+  int code;       // interlacing code: 0 one grid, 1 the pair {0, (1,1,1)/2}, 2 the four
+                  // face-centred half-cell shifts, 3 all eight half-cell shifts
+  int ng;         // grids per set: 1, 2, 4, 8
+  int npair;      // complex grids (slabs) per set: max(1, ng / 2); slab = set * npair + q
   int batch;
   int nb;         // buckets per axis = N / kBucket
   int tile;       // deposit tile edge
@@ -35,6 +39,14 @@ struct Geom {
   int64_t ps;     // complex elements between consecutive x planes: N*nz plus
                   // a pad that breaks the power-of-two stride of the x pass
 };
+
+// Shift mask of grid j (bit a: sampled at u_a + 1/2); grids 2q and 2q+1 share
+// slab q as real and imaginary parts.
+__host__ __device__ inline int grid_mask(int code, int j) {
+  if (code == 1) return j ? 7 : 0;
+  if (code == 2) return j == 0 ? 0 : (j == 1 ? 3 : (j == 2 ? 5 : 6));
+  return code == 3 ? j : 0;
+}
 
 // float index of real-grid cell (x, y, z) of set `mock` (plane stride ps
 // complex = 2 ps floats; without interlacing the N^3 reals are packed two per

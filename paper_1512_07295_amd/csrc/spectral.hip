@@ -122,6 +122,34 @@ __device__ __forceinline__ float pair_power(float2 za, float2 zb, float2 ph) {
   return cx * cx + cy * cy;
 }
 
+// C(m) of interlacing codes 2 and 3 (more than two grids): C = (1/G) sum_j
+// F_j(m) exp(+i pi s_j / N), s_j the sum of the components of m along the
+// axes grid j is shifted on, with F_2q and F_2q+1 unpacked from slab q's
+// Z(k) and Z(-k) as in combined_mode.  Signed m, |m_a| <= N/2.
+__device__ __forceinline__ float2 multi_mode(const float2* __restrict__ data, const Geom& g,
+                                             int mock, int mx, int my, int mz,
+                                             const float2* __restrict__ phase) {
+  const int n = g.n;
+  const int x = fft_index(mx, n), y = fft_index(my, n), z = fft_index(mz, n);
+  const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n), zm = neg_mod<false>(z, n);
+  const int m[3] = {mx, my, mz};
+  float2 c = make_float2(0.f, 0.f);
+  for (int q = 0; q < g.npair; ++q) {
+    const int slab = mock * g.npair + q;
+    const float2 za = data[complex_index(g, slab, x, y, z)];
+    const float2 zb = data[complex_index(g, slab, xm, ym, zm)];
+    const float2 f[2] = {make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y)),
+                         make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x))};
+    for (int h = 0; h < 2; ++h) {
+      const int mk = grid_mask(g.code, 2 * q + h);
+      int sj = 0;
+      for (int a = 0; a < 3; ++a) sj += ((mk >> a) & 1) ? m[a] : 0;
+      c = cadd(c, cmul(phase[mod_2n<false>(sj, n)], f[h]));
+    }
+  }
+  return cscale(c, 1.0f / (float)g.ng);
+}
+
 template <int L>
 struct PairShape {
   static constexpr int TPL = LinePlan<L>::TPL;
@@ -476,9 +504,66 @@ static int pair_blocks(const Geom& g, const Tune& tu) {
   return (int)nblk;
 }
 
+// Shell sums of w |C(m)|^2 / W(m)^2 over the half space for more than two
+// grids, from the stored spectra (after the z pass); runs of up to 16 m_z
+// per thread as in the mode table.
+constexpr int kMultiBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_multi_bins(const float2* __restrict__ data, Geom g,
+                                                    const float2* __restrict__ phase,
+                                                    const float* __restrict__ inv_w2, int n_dk,
+                                                    int n_bins, double* __restrict__ partials) {
+  __shared__ double hist[kMaxBins];
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
+  __syncthreads();
+  const int n = g.n, nm = n / 2 + 1;
+  const int mock = blockIdx.y;
+  constexpr int CH = 16;
+  const int chunks = (nm + CH - 1) / CH;
+  const int64_t items = (int64_t)n * n * chunks;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = it / chunks;
+    const int ch = (int)(it % chunks);
+    const int x = (int)(row / n), y = (int)(row % n);
+    const int mx = signed_freq(x, n), my = signed_freq(y, n);
+    const int r2 = mx * mx + my * my;
+    const float wxy = inv_w2[x] * inv_w2[y];
+    int cur_b = -1;
+    float cur = 0.0f;
+    for (int mz = ch * CH; mz < min(ch * CH + CH, nm); ++mz) {
+      const int m2 = r2 + mz * mz;
+      if (m2 == 0) continue;
+      const int b = shell_of(m2, n_dk);
+      if (b < 1 || b > n_bins) continue;
+      const float2 c = multi_mode(data, g, mock, mx, my, mz, phase);
+      const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
+      const float val = wgt * (c.x * c.x + c.y * c.y) * inv_w2[mz];
+      if (b != cur_b) {
+        if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)(cur * wxy));
+        cur_b = b;
+        cur = 0.0f;
+      }
+      cur += val;
+    }
+    if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)(cur * wxy));
+  }
+  __syncthreads();
+  double* dst = partials + ((int64_t)mock * gridDim.x + blockIdx.x) * n_bins;
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) dst[i] = hist[i];
+}
+
 hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do_fft, int n_dk,
                         int n_bins, int subtract_shot, double* k, double* p, int64_t* nmodes,
                         hipStream_t s) {
+  if (g.npair > 1) {
+    hipLaunchKernelGGL(k_multi_bins, dim3(kMultiBlocks, g.batch), dim3(256), 0, s, b.grid, g,
+                       b.phase, b.inv_w2, n_dk, n_bins, b.partials);
+    hipLaunchKernelGGL(k_power_finalize, dim3(n_bins, g.batch), dim3(64), 0, s, b.partials,
+                       kMultiBlocks, n_bins, b.mode_n, b.mode_k, b.norm, g.box, subtract_shot, k, p,
+                       nmodes);
+    return hipGetLastError();
+  }
   const int nblk = pair_blocks(g, tu);
   hipError_t e = do_fft ? pairs_dispatch<0>(g, b, nblk, n_dk, n_bins, s)
                         : pairs_dispatch<1>(g, b, nblk, n_dk, n_bins, s);
@@ -576,11 +661,44 @@ __device__ void delta_at(const float2* __restrict__ data, const Geom& g, int moc
   const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n);
   const int L = g.nz;
   const int z = ((mz % L) + L) % L, zm = neg_mod<false>(z, L);
+  double cr, ci;
+  if (g.npair > 1) {
+    // more than two grids: (1/G) sum_j F_j exp(+i pi s_j / N)
+    const int m[3] = {mx, my, mz};
+    cr = ci = 0.0;
+    for (int q = 0; q < g.npair; ++q) {
+      const float2 za = data[complex_index(g, mock * g.npair + q, x, y, z)];
+      const float2 zb = data[complex_index(g, mock * g.npair + q, xm, ym, zm)];
+      const double fr[2] = {0.5 * ((double)za.x + zb.x), 0.5 * ((double)za.y + zb.y)};
+      const double fi[2] = {0.5 * ((double)za.y - zb.y), 0.5 * ((double)zb.x - za.x)};
+      for (int h = 0; h < 2; ++h) {
+        const int mk = grid_mask(g.code, 2 * q + h);
+        int sj = 0;
+        for (int a = 0; a < 3; ++a) sj += ((mk >> a) & 1) ? m[a] : 0;
+        double sn, cs;
+        sincospi((double)sj / n, &sn, &cs);
+        cr += cs * fr[h] - sn * fi[h];
+        ci += cs * fi[h] + sn * fr[h];
+      }
+    }
+    cr /= g.ng;
+    ci /= g.ng;
+    double w = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      if (m[a] != 0) {
+        const double xx = (double)m[a] / n;
+        const double sc = sinpi(xx) / (M_PI * xx);
+        for (int k = 0; k < g.order; ++k) w *= sc;
+      }
+    }
+    re = cr / (npart * w);
+    im = ci / (npart * w);
+    return;
+  }
   const float2 za = data[complex_index(g, mock, x, y, z)];
   const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
   const double f1r = 0.5 * ((double)za.x + zb.x), f1i = 0.5 * ((double)za.y - zb.y);
   const double f2r = 0.5 * ((double)za.y + zb.y), f2i = 0.5 * ((double)zb.x - za.x);
-  double cr, ci;
   if (g.il) {
     double s, c;
     sincospi((double)(mx + my + mz) / n, &s, &c);
@@ -747,11 +865,15 @@ __global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ d
       } else {
         const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n);
         const int zz = ((mz % L) + L) % L, zm = neg_mod<false>(zz, L);
-        const float2 za = data[complex_index(g, mock, x, y, zz)];
-        const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
         float2 c;
-        if (g.il) c = combined_mode<true, false>(za, zb, mx, my, mz, phase, n);
-        else c = combined_mode<false, false>(za, zb, mx, my, mz, phase, n);
+        if (g.npair > 1) {
+          c = multi_mode(data, g, mock, mx, my, mz, phase);
+        } else {
+          const float2 za = data[complex_index(g, mock, x, y, zz)];
+          const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
+          if (g.il) c = combined_mode<true, false>(za, zb, mx, my, mz, phase, n);
+          else c = combined_mode<false, false>(za, zb, mx, my, mz, phase, n);
+        }
         const float w = win1[x] * win1[y] * win1[z];
         d = cscale(c, inv_np / w);
       }

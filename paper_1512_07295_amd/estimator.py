@@ -47,7 +47,7 @@ class Estimator:
         self.n_grid = int(n_grid)
         self.box = float(box)
         self.order = int(order)
-        self.interlace = bool(interlace)
+        self.interlace = int(interlace)  # 0..3 (grids: 1, 2, 4, 8)
         self.batch = int(batch)
         self.device = torch.device(device)
         flags = (EST_FLAG_ATOMIC_SORT if atomic_sort else 0) | (EST_FLAG_WEIGHTS if weighted else 0)
