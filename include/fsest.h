@@ -91,8 +91,7 @@ typedef struct {
                          /* times H/2 (no alias image of mixed parity); 3: all */
                          /* eight H/2 shift combinations (no image with an odd */
                          /* component).  delta = (1/G) sum_j F_j e^{ik.s_j}.   */
-                         /* Codes 2, 3 take G/2 complex grids per set and no   */
-                         /* estimator_backward (EUNSUPPORTED).                 */
+                         /* Codes 2, 3 take G/2 complex grids per set.         */
   int32_t batch;         /* number of particle sets sharing the grid, >= 1    */
   double box;            /* L > 0, finite (periodic cube of side L, Sec. 2.1) */
   int64_t max_particles; /* upper bound of n_total per call, 1 .. 2^31-1      */
@@ -170,8 +169,9 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk,
  * dL/dP_b (device float64 [batch][n_bins]) writes dL/dx (device, same dtype
  * and layout as pos) for every particle.  The grids are recomputed from pos
  * (nothing is kept from the forward); the handle's grids are overwritten.
- * Same argument rules as estimator_deposit and estimator_power;
- * EUNSUPPORTED for interlace codes 2 and 3. */
+ * Same argument rules as estimator_deposit and estimator_power.  With
+ * interlace codes 2 and 3 the handle holds an extra half-spectrum buffer
+ * for the combined C(m) (8 bytes per mode and set). */
 est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype,
                               const int64_t* offsets, int64_t n_total,
                               const double* dldp, int32_t n_dk, int32_t n_bins,

@@ -130,6 +130,8 @@ est_status check_config(const est_config* c) {
   if (c->order < 1 || c->order > 6) return fail(EST_EINVAL, "order must be 1..6 (got %d)", c->order);
   if (c->interlace < 0 || c->interlace > 3)
     return fail(EST_EINVAL, "interlace must be 0, 1, 2 or 3 (got %d)", c->interlace);
+  if (c->interlace >= 2 && c->batch > 65535 / (1 << (c->interlace - 1)))
+    return fail(EST_EINVAL, "batch times complex grids per set must be <= 65535");
   if (c->batch < 1 || c->batch > 65535) return fail(EST_EINVAL, "batch must be 1..65535 (got %d)", c->batch);
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return fail(EST_EINVAL, "box must be finite and > 0");
   if (c->max_particles < 1 || c->max_particles > 2147483647LL)
@@ -218,6 +220,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   bb.sw = weighted ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
   bb.tw = weighted && two_level ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
   bb.wpart = weighted ? (double*)take(batch * kWSlices * 2 * sizeof(double)) : nullptr;
+  bb.cbuf = c.interlace >= 2 ? (float2*)take(batch * n * n * (half + 1) * sizeof(float2)) : nullptr;
   bb.coef = (double*)take(batch * half * sizeof(double));
   bb.mode_partials_n = (uint64_t*)take(512 * half * sizeof(uint64_t));
   bb.mode_partials_k = (double*)take(512 * half * sizeof(double));
@@ -541,13 +544,24 @@ est_status estimator_backward(est_handle h, const void* pos, est_dtype dtype, co
   if ((st = check_particles(h, pos, dtype, offsets, n_total))) return st;
   if ((st = check_bins(h, n_dk, n_bins))) return st;
   if (!dldp || !grad) return fail(EST_EINVAL, "NULL device pointer");
-  if (h->g.npair > 1)
-    return fail(EST_EUNSUPPORTED, "the adjoint supports one grid or the interlaced pair only");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
   h->state = kCreated;
   if ((st = run_deposit(h, pos, dtype, offsets, n_total))) return st;
   if ((st = run_xy(h, -1))) return st;
-  {
+  if (h->g.npair > 1) {
+    // more than two grids: separate z passes around the gradient spectra
+    h->state = kXY;
+    if ((st = to_spectrum(h))) return st;
+    {
+      ProfScope ps(h, kPAdjoint);
+      if ((st = dev_err(launch_multi_adjoint(h->g, h->b, dldp, n_dk, n_bins, h->stream), "adjoint spectrum")))
+        return st;
+    }
+    ProfScope ps(h, kPFftZ);
+    if ((st = dev_err(launch_fft_axis(h->g, h->b.grid, 2, +1, h->g.batch * h->g.npair, h->g.nz,
+                                      h->b.tw_nz, h->tu, h->stream), "ifft z")))
+      return st;
+  } else {
     ProfScope ps(h, kPAdjoint);
     if ((st = dev_err(launch_adjoint_spectrum(h->g, h->b, h->tu, dldp, n_dk, n_bins, h->stream), "adjoint spectrum")))
       return st;

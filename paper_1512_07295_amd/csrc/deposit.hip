@@ -1,717 +1,17 @@
-// Mass assignment (Sec. 2.3, eq. delgrid) onto the primary grid and the grid
-// shifted by H/2 on every axis (Sec. 3.1), and its adjoint gather.
+// Mass assignment (Sec. 2.3, eq. delgrid) onto the primary grid and the grids
+// shifted by half a cell (Sec. 3.1).
 //
-// Design (gfx950): particles are counting-sorted by bucket (kBucket^3 cells)
-// so that every deposit workgroup owns one output tile of T^3 cells outright:
-// it reads the particles of the buckets that can reach the tile, adds the
-// clipped footprints of both grids with LDS float atomics, and writes the
-// finished tile once with coalesced stores.  No global atomics touch the grid
-// and the grid needs no clearing.  A particle whose base cell is c reaches
-// cells c-1 .. c+3 of either grid for every p <= 4, so the buckets holding
-// cells t0-3 .. t0+T are enough.
+// Design (gfx950): the particles arrive sorted by bucket (sort.hip), so every
+// deposit workgroup owns one output tile of T^3 cells outright: it reads the
+// particles of the buckets that can reach the tile, adds the clipped
+// footprints of two grids with LDS integer atomics on a fixed-point format,
+// and writes the finished tile once with coalesced stores.  No global atomics
+// touch the grid and the grid needs no clearing.
 #include <type_traits>
 
-#include "fsest_internal.hpp"
+#include "particles.hpp"
 
 namespace fsest {
-
-// ------------------------------------------------------------------ utils
-__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = v;
-}
-
-hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-__global__ void k_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
-                             double* norm) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= batch) return;
-  const int64_t c = offsets ? (offsets[i + 1] - offsets[i]) : n_total;
-  np[i] = c;
-  norm[2 * i] = (double)c;
-  norm[2 * i + 1] = (double)c;
-}
-
-hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch, int64_t* np,
-                             double* norm, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_counts, dim3((batch + 63) / 64), dim3(64), 0, s, offsets, n_total,
-                     batch, np, norm);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ masses
-// Per set, kWSlices workgroups each sum w and w^2 over a fixed slice of the
-// set's particles (strided per thread, then a fixed tree over the
-// workgroup), and a second pass adds the slices in order: the totals do not
-// depend on scheduling.  The largest mass goes to stats[4] (non-negative
-// floats order like their bit patterns) and any negative, NaN or infinite
-// mass sets stats[5].
-constexpr int kWThreads = 256;
-
-__global__ __launch_bounds__(kWThreads) void k_weight_stats(const float* __restrict__ w,
-                                                            const int64_t* __restrict__ offsets,
-                                                            int64_t n_total,
-                                                            double* __restrict__ wpart,
-                                                            uint32_t* __restrict__ stats) {
-  __shared__ double sa[kWThreads / 64], sb[kWThreads / 64];
-  const int m = blockIdx.y, slice = blockIdx.x;
-  const int64_t j0 = offsets ? offsets[m] : 0, j1 = offsets ? offsets[m + 1] : n_total;
-  const int64_t len = j1 - j0;
-  const int64_t s0 = j0 + len * slice / kWSlices, s1 = j0 + len * (slice + 1) / kWSlices;
-  double a = 0.0, b = 0.0;
-  float mx = 0.0f;
-  bool bad = false;
-  for (int64_t j = s0 + threadIdx.x; j < s1; j += kWThreads) {
-    const float v = w[j];
-    if (!(v >= 0.0f && v <= 3.402823466e38f)) {
-      bad = true;
-    } else {
-      a += (double)v;
-      b += (double)v * (double)v;
-      if (v > mx) mx = v;
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-    mx = fmaxf(mx, __shfl_down(mx, off, 64));
-  }
-  const unsigned long long anybad = __ballot(bad);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    sa[wave] = a;
-    sb[wave] = b;
-    if (mx > 0.0f) atomicMax(&stats[4], __float_as_uint(mx));
-    if (anybad) atomicOr(&stats[5], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int i = 0; i < kWThreads / 64; ++i) {
-      ta += sa[i];
-      tb += sb[i];
-    }
-    double* dst = wpart + 2 * ((int64_t)m * kWSlices + slice);
-    dst[0] = ta;
-    dst[1] = tb;
-  }
-}
-
-__global__ void k_weight_final(const double* __restrict__ wpart, int batch, double* __restrict__ norm) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= batch) return;
-  double ta = 0.0, tb = 0.0;
-  for (int i = 0; i < kWSlices; ++i) {
-    ta += wpart[2 * ((int64_t)m * kWSlices + i)];
-    tb += wpart[2 * ((int64_t)m * kWSlices + i) + 1];
-  }
-  norm[2 * m] = ta;
-  norm[2 * m + 1] = tb;
-}
-
-hipError_t launch_weight_stats(const float* w, const int64_t* offsets, int64_t n_total, int batch,
-                               double* wpart, double* norm, uint32_t* stats, hipStream_t s) {
-  hipError_t e = launch_fill_u32(stats + 4, 2, 0u, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_weight_stats, dim3(kWSlices, batch), dim3(kWThreads), 0, s, w, offsets,
-                     n_total, wpart, stats);
-  hipLaunchKernelGGL(k_weight_final, dim3((batch + 63) / 64), dim3(64), 0, s, wpart, batch, norm);
-  return hipGetLastError();
-}
-
-// mass of particle j divided by the largest mass (in [0, 1]; 0 if every mass is 0)
-__device__ __forceinline__ float scaled_mass(const float* w, int64_t j, const uint32_t* stats) {
-  const float wmax = __uint_as_float(stats[4]);
-  const float v = w[j];
-  return (wmax > 0.0f && v >= 0.0f && v <= wmax) ? v / wmax : 0.0f;
-}
-
-// set index of particle j: largest i with offsets[i] <= j (offsets has batch+1 entries)
-__device__ __forceinline__ int mock_of(const int64_t* offsets, int batch, int64_t j) {
-  if (batch == 1 || offsets == nullptr) return 0;
-  int lo = 0, hi = batch;  // offsets[lo] <= j < offsets[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (offsets[mid] <= j) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-template <typename TP>
-__device__ __forceinline__ void load_pos(const TP* pos, int64_t j, double& x, double& y, double& z) {
-  x = (double)pos[3 * j + 0];
-  y = (double)pos[3 * j + 1];
-  z = (double)pos[3 * j + 2];
-}
-
-// floor(u) mod N for u in [0, N] (u = N can come out of the rounding of x N / L)
-__device__ __forceinline__ int base_cell(double u, int n) {
-  const int c = (int)floor(u);
-  return c >= n ? c - n : c;
-}
-
-// ------------------------------------------------------------------ sort
-// Bucket counts and each particle's rank inside its bucket.  A workgroup
-// first counts its particles per bucket key in an LDS hash table (open
-// addressing), then adds each distinct key's count to the global counter
-// with one atomic, whose old value becomes the base of that key's ranks.
-// Particles stored near each other in memory (simulation order) share
-// buckets, so this removes most of the device-scope atomics.
-constexpr int kCountThreads = 1024;
-constexpr int kCountHash = 2048;  // slots, load factor <= 1/2
-constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-
-template <typename TP>
-__global__ __launch_bounds__(kCountThreads) void k_bucket_count(
-    const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
-    uint32_t* __restrict__ counts, uint32_t* __restrict__ rank) {
-  __shared__ uint32_t hkey[kCountHash];
-  __shared__ uint32_t hval[kCountHash];
-  for (int i = threadIdx.x; i < kCountHash; i += kCountThreads) {
-    hkey[i] = kEmptyKey;
-    hval[i] = 0u;
-  }
-  const int64_t j = (int64_t)blockIdx.x * kCountThreads + threadIdx.x;
-  uint32_t key = kEmptyKey;
-  if (j < n_total) {
-    double x, y, z;
-    load_pos(pos, j, x, y, z);
-    const int mock = mock_of(offsets, g.batch, j);
-    const int bx = base_cell(grid_coord(x, g.box, g.inv), g.n) / kBucket;
-    const int by = base_cell(grid_coord(y, g.box, g.inv), g.n) / kBucket;
-    const int bz = base_cell(grid_coord(z, g.box, g.inv), g.n) / kBucket;
-    key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
-  }
-  __syncthreads();
-  int slot = 0;
-  uint32_t local = 0;
-  if (key != kEmptyKey) {
-    slot = (int)(key & (kCountHash - 1));
-    while (true) {
-      const uint32_t prev = atomicCAS(&hkey[slot], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) break;
-      slot = (slot + 1) & (kCountHash - 1);
-    }
-    local = atomicAdd(&hval[slot], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kCountHash; i += kCountThreads) {
-    const uint32_t k = hkey[i];
-    if (k != kEmptyKey) hval[i] = atomicAdd(&counts[k], hval[i]);
-  }
-  __syncthreads();
-  if (key != kEmptyKey) rank[j] = hval[slot] + local;
-}
-
-// Cell record of one particle, used by the deposit to decide which tiles a
-// particle's stencils reach without redoing the float64 cell arithmetic:
-// bits 16a .. 16a+15 hold the first-grid floor cell along axis a (floor(u)
-// for even p, floor(u + 1/2) for odd p; mod N), bit 48 + a holds the step
-// from it to the same floor on the grid shifted by H/2 (0 or 1).
-// bits kRecFineShift.. carry a particle's bucket inside its super-bucket
-// between the two passes of the two-level sort
-constexpr int kRecFineShift = 52;
-
-__device__ __forceinline__ uint64_t cell_record(double ux, double uy, double uz, const Geom& g) {
-  const bool even = (g.order % 2) == 0;
-  const double u[3] = {ux, uy, uz};
-  uint64_t rec = 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
-    const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
-    const double f2 = even ? floor(u2) : floor(u2 + 0.5);
-    const int c1 = (int)f1;  // in [0, N]
-    rec |= (uint64_t)(c1 >= g.n ? c1 - g.n : c1) << (16 * a);
-    rec |= (uint64_t)((int)(f2 - f1) & 1) << (48 + a);
-  }
-  return rec;
-}
-
-template <typename TP>
-__global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ pos, int64_t n_total,
-                                                        const int64_t* __restrict__ offsets, Geom g,
-                                                        const uint32_t* __restrict__ boff,
-                                                        const uint32_t* __restrict__ rank,
-                                                        TP* __restrict__ sorted,
-                                                        uint64_t* __restrict__ cells,
-                                                        const float* __restrict__ w,
-                                                        float* __restrict__ sw,
-                                                        const uint32_t* __restrict__ stats) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_total) return;
-  TP px = pos[3 * j + 0], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-  const int mock = mock_of(offsets, g.batch, j);
-  const double ux = grid_coord((double)px, g.box, g.inv);
-  const double uy = grid_coord((double)py, g.box, g.inv);
-  const double uz = grid_coord((double)pz, g.box, g.inv);
-  const int bx = base_cell(ux, g.n) / kBucket;
-  const int by = base_cell(uy, g.n) / kBucket;
-  const int bz = base_cell(uz, g.n) / kBucket;
-  const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
-  const int64_t dst = (int64_t)boff[key] + rank[j];
-  sorted[3 * dst + 0] = px;
-  sorted[3 * dst + 1] = py;
-  sorted[3 * dst + 2] = pz;
-  cells[dst] = cell_record(ux, uy, uz, g);
-  if (w) sw[dst] = scaled_mass(w, j, stats);
-}
-
-// exclusive scan of n items in place, 2048 items per block
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanBlock = kScanThreads * kScanItems;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
-  // Hillis-Steele over the block in LDS (256 entries)
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    uint32_t a = (t >= off) ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
-  }
-  total = sh[kScanThreads - 1];
-  uint32_t incl = sh[t];
-  __syncthreads();
-  return incl - v;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(uint32_t* data, size_t n, uint32_t* sums,
-                                                           uint32_t* maxcount) {
-  __shared__ uint32_t sh[kScanThreads];
-  const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t run = 0, mx = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? data[base + i] : 0u;
-    uint32_t c = v[i];
-    mx = max(mx, c);
-    v[i] = run;
-    run += c;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(maxcount, mx);
-  uint32_t total;
-  uint32_t pre = block_exclusive_scan(run, sh, total);
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) data[base + i] = v[i] + pre;
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t* sums, int nblk) {
-  __shared__ uint32_t sh[kScanThreads];
-  uint32_t carry = 0;
-  for (int c0 = 0; c0 < nblk; c0 += kScanThreads) {
-    int i = c0 + threadIdx.x;
-    uint32_t v = (i < nblk) ? sums[i] : 0u;
-    uint32_t total;
-    uint32_t pre = block_exclusive_scan(v, sh, total);
-    if (i < nblk) sums[i] = pre + carry;
-    carry += total;
-  }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t* data, size_t n, const uint32_t* sums) {
-  const uint32_t add = sums[blockIdx.x];
-  const size_t base = (size_t)blockIdx.x * kScanBlock;
-  for (int i = threadIdx.x; i < kScanBlock; i += kScanThreads)
-    if (base + i < n) data[base + i] += add;
-}
-
-__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = src[i];
-}
-
-static hipError_t scan_in_place(uint32_t* data, size_t n, uint32_t* tmp, uint32_t* maxcount,
-                                hipStream_t s) {
-  const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nblk), dim3(kScanThreads), 0, s, data, n, tmp, maxcount);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nblk);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblk), dim3(kScanThreads), 0, s, data, n, tmp);
-  return hipGetLastError();
-}
-
-// Counting sort with device-scope atomics: the general path, used when there
-// are more super-buckets than one workgroup can histogram.
-static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
-                              const int64_t* offsets, int64_t n_total, const float* w,
-                              const Buffers& b, hipStream_t s) {
-  const size_t nkeys = (size_t)g.batch * g.nb * g.nb * g.nb;
-  hipError_t e = launch_fill_u32(b.boff, nkeys + 1, 0u, s);
-  if (e != hipSuccess) return e;
-  const unsigned pblocks = (unsigned)((n_total + 255) / 256);
-  const unsigned cblocks = (unsigned)((n_total + kCountThreads - 1) / kCountThreads);
-  if (dt == EST_F32)
-    hipLaunchKernelGGL(k_bucket_count<float>, dim3(cblocks), dim3(kCountThreads), 0, s,
-                       (const float*)pos, n_total, offsets, g, b.boff, b.rank);
-  else
-    hipLaunchKernelGGL(k_bucket_count<double>, dim3(cblocks), dim3(kCountThreads), 0, s,
-                       (const double*)pos, n_total, offsets, g, b.boff, b.rank);
-  hipLaunchKernelGGL(k_copy_u32, dim3(2048), dim3(256), 0, s, b.boff, b.bcnt, nkeys);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_in_place(b.boff, nkeys + 1, b.scan_tmp, b.stats, s)) != hipSuccess) return e;
-  if (dt == EST_F32)
-    hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
-                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells, w, b.sw,
-                       b.stats);
-  else
-    hipLaunchKernelGGL(k_bucket_scatter<double>, dim3(pblocks), dim3(256), 0, s,
-                       (const double*)pos, n_total, offsets, g, b.boff, b.rank,
-                       (double*)b.sorted, b.cells, w, b.sw, b.stats);
-  return hipGetLastError();
-}
-
-// ---- two-level sort without device-scope atomics
-// Super-buckets are cubes of g.fb^3 buckets (g.nsup of them).  (A) each of
-// nblk workgroups histograms a contiguous chunk of particles over the
-// super-buckets in LDS; (B) the histograms, laid out super-major, are
-// scanned, giving every (super-bucket, workgroup) pair its output offset;
-// (C) each workgroup re-reads its chunk and moves every particle (position
-// and cell record) into its super-bucket segment, ranking with LDS
-// counters; (D) one workgroup per super-bucket counts its particles per
-// bucket, writes the bucket offsets and counts, and moves the particles into
-// bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
-// the deposit splits its bucket runs at super-bucket boundaries.
-constexpr int kSortThreads = 1024;
-constexpr int kSortBatch = 1;  // particles per thread handled together (loads in flight together)
-
-__device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
-                                                 int& bx, int& by, int& bz) {
-  bx = base_cell(ux, g.n) / kBucket;
-  by = base_cell(uy, g.n) / kBucket;
-  bz = base_cell(uz, g.n) / kBucket;
-}
-
-__device__ __forceinline__ int super_of(int mock, int bx, int by, int bz, const Geom& g) {
-  return ((mock * g.sa + bx / g.fb) * g.sa + by / g.fb) * g.sa + bz / g.fb;
-}
-
-template <typename TP>
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict__ pos,
-                                                            int64_t n_total,
-                                                            const int64_t* __restrict__ offsets,
-                                                            Geom g, int64_t chunk, int nblk,
-                                                            uint32_t* __restrict__ hsup) {
-  __shared__ uint32_t hist[kMaxSuper];
-  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads) hist[i] = 0u;
-  __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * chunk;
-  const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
-  // kSortBatch particles per thread at a time, their loads issued together
-  for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
-    double x[kSortBatch], y[kSortBatch], z[kSortBatch];
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const int64_t j = jb + (int64_t)q * kSortThreads;
-      if (j < j1) load_pos(pos, j, x[q], y[q], z[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const int64_t j = jb + (int64_t)q * kSortThreads;
-      if (j < j1) {
-        int bx, by, bz;
-        particle_buckets(grid_coord(x[q], g.box, g.inv), grid_coord(y[q], g.box, g.inv),
-                         grid_coord(z[q], g.box, g.inv), g, bx, by, bz);
-        atomicAdd(&hist[super_of(mock_of(offsets, g.batch, j), bx, by, bz, g)], 1u);
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
-    hsup[(int64_t)i * nblk + blockIdx.x] = hist[i];
-}
-
-template <typename TP>
-__global__ __launch_bounds__(kSortThreads) void k_sort_super(
-    const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
-    int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ tpos,
-    uint64_t* __restrict__ trec, const float* __restrict__ w, float* __restrict__ tw) {
-  __shared__ uint32_t cur[kMaxSuper];
-  for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
-    cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
-  __syncthreads();
-  const int64_t j0 = (int64_t)blockIdx.x * chunk;
-  const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
-  for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
-    TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const int64_t j = jb + (int64_t)q * kSortThreads;
-      if (j < j1) {
-        px[q] = pos[3 * j + 0];
-        py[q] = pos[3 * j + 1];
-        pz[q] = pos[3 * j + 2];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const int64_t j = jb + (int64_t)q * kSortThreads;
-      if (j < j1) {
-        const double ux = grid_coord((double)px[q], g.box, g.inv);
-        const double uy = grid_coord((double)py[q], g.box, g.inv);
-        const double uz = grid_coord((double)pz[q], g.box, g.inv);
-        int bx, by, bz;
-        particle_buckets(ux, uy, uz, g, bx, by, bz);
-        const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
-        const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
-        const uint32_t p = atomicAdd(&cur[sup], 1u);
-        tpos[3 * (int64_t)p + 0] = px[q];
-        tpos[3 * (int64_t)p + 1] = py[q];
-        tpos[3 * (int64_t)p + 2] = pz[q];
-        trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
-        if (w) tw[p] = w[j];
-      }
-    }
-  }
-}
-
-template <typename TP>
-__global__ __launch_bounds__(kSortThreads) void k_sort_fine(
-    const TP* __restrict__ tpos, const uint64_t* __restrict__ trec, int64_t n_total, Geom g,
-    int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ sorted,
-    uint64_t* __restrict__ cells, uint32_t* __restrict__ boff, uint32_t* __restrict__ bcnt,
-    uint32_t* __restrict__ stats, const float* __restrict__ tw, float* __restrict__ sw) {
-  constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
-  __shared__ uint32_t hist[kFineMax * kFineMax * kFineMax];
-  __shared__ uint32_t wtot[kSortThreads / 64];
-  const int sup = blockIdx.x;
-  const int nf = g.fb * g.fb * g.fb;
-  const uint32_t seg0 = hoff[(int64_t)sup * nblk];
-  const uint32_t seg1 = (sup + 1 < g.nsup) ? hoff[(int64_t)(sup + 1) * nblk] : (uint32_t)n_total;
-  for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
-  __syncthreads();
-  for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
-    uint64_t r[kSortBatch];
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const uint32_t i = ib + q * kSortThreads;
-      r[q] = (i < seg1) ? trec[i] : 0ull;
-    }
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q)
-      if (ib + q * kSortThreads < seg1) atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
-  }
-  __syncthreads();
-  // exclusive scan of hist[0, nf): kPer consecutive buckets per thread
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  uint32_t c[kPer], run = 0, mx = 0;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int f = t * kPer + q;
-    c[q] = (f < nf) ? hist[f] : 0u;
-    mx = max(mx, c[q]);
-    run += c[q];
-  }
-  uint32_t incl = run;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
-    if (lane >= o) incl += v;
-  }
-  if (lane == 63) wtot[wave] = incl;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, o, 64));
-  if (lane == 0) atomicMax(&stats[0], mx);
-  __syncthreads();
-  uint32_t before = 0;
-  for (int w = 0; w < wave; ++w) before += wtot[w];
-  uint32_t start = seg0 + before + incl - run;
-  // bucket offsets and counts, in global key order
-  const int ms = sup / (g.sa * g.sa * g.sa), srem = sup % (g.sa * g.sa * g.sa);
-  const int sx = srem / (g.sa * g.sa), sy = (srem / g.sa) % g.sa, sz = srem % g.sa;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int f = t * kPer + q;
-    if (f < nf) {
-      const int fx = f / (g.fb * g.fb), fy = (f / g.fb) % g.fb, fz = f % g.fb;
-      const int64_t key = (((int64_t)ms * g.nb + sx * g.fb + fx) * g.nb + sy * g.fb + fy) * g.nb +
-                          sz * g.fb + fz;
-      boff[key] = start;
-      bcnt[key] = c[q];
-      hist[f] = start - seg0;
-    }
-    start += c[q];
-  }
-  __syncthreads();
-  for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
-    uint64_t r[kSortBatch];
-    TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      const uint32_t i = ib + q * kSortThreads;
-      if (i < seg1) {
-        r[q] = trec[i];
-        px[q] = tpos[3 * (int64_t)i + 0];
-        py[q] = tpos[3 * (int64_t)i + 1];
-        pz[q] = tpos[3 * (int64_t)i + 2];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kSortBatch; ++q) {
-      if (ib + q * kSortThreads < seg1) {
-        const uint32_t p = seg0 + atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
-        sorted[3 * (int64_t)p + 0] = px[q];
-        sorted[3 * (int64_t)p + 1] = py[q];
-        sorted[3 * (int64_t)p + 2] = pz[q];
-        cells[p] = r[q] & ((1ull << kRecFineShift) - 1ull);
-        if (tw) sw[p] = scaled_mass(tw, ib + q * kSortThreads, stats);
-      }
-    }
-  }
-}
-
-template <typename TP>
-static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* offsets,
-                                 int64_t n_total, const float* w, const Buffers& b, hipStream_t s) {
-  int nblk = (int)((n_total + 4095) / 4096);
-  if (nblk > kMaxSortBlocks) nblk = kMaxSortBlocks;
-  const int64_t chunk = (n_total + nblk - 1) / nblk;
-  hipLaunchKernelGGL(k_sort_hist<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
-                     offsets, g, chunk, nblk, b.hsup);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // the scan's largest-entry output is not a bucket count here
-  if ((e = scan_in_place(b.hsup, (size_t)g.nsup * nblk, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
-                     offsets, g, chunk, nblk, b.hsup, (TP*)b.tpos, b.trec, w, b.tw);
-  hipLaunchKernelGGL(k_sort_fine<TP>, dim3(g.nsup), dim3(kSortThreads), 0, s, (const TP*)b.tpos,
-                     b.trec, n_total, g, nblk, b.hsup, (TP*)b.sorted, b.cells, b.boff, b.bcnt,
-                     b.stats, w ? b.tw : nullptr, b.sw);
-  return hipGetLastError();
-}
-
-hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                       int64_t n_total, const float* w, const Buffers& b, hipStream_t s) {
-  hipError_t e = launch_fill_u32(b.stats, 4, 0u, s);
-  if (e != hipSuccess) return e;
-  if (g.nsup > kMaxSuper) return sort_atomic(g, pos, dt, offsets, n_total, w, b, s);
-  if (dt == EST_F32) return sort_two_level(g, (const float*)pos, offsets, n_total, w, b, s);
-  return sort_two_level(g, (const double*)pos, offsets, n_total, w, b, s);
-}
-
-// ------------------------------------------------------------------ stencils
-// Orders above 4 (the higher-order B-splines of Sec. 2.3): the weights of
-// the p stencil cells are N_p(t + i), i = 0..p-1, of the cardinal B-spline
-// N_p (the p-fold convolution of the unit box on [0, 1], support [0, p]),
-// with t = 1 - f for even p and t = 1/2 - f for odd p (f = u - floor(...)
-// as below), from the recursion
-//   N_{k+1}(t + j) = ((t + j) N_k(t + j) + (k + 1 - t - j) N_k(t + j - 1)) / k,
-// N_1(t) = 1 (convex combinations: no cancellation).  d/ds of the order-p
-// weight is N_{p-1}(t + i) - N_{p-1}(t + i - 1), from the previous level.
-template <int P>
-__device__ __forceinline__ void bspline_weights(float t, float (&w)[P], float (&wd)[P]) {
-  float v[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) v[j] = (j == 0) ? 1.0f : 0.0f;
-#pragma unroll
-  for (int k = 1; k < P; ++k) {
-    if (k == P - 1) {
-#pragma unroll
-      for (int j = 0; j < P; ++j) wd[j] = (j < k ? v[j] : 0.0f) - (j >= 1 ? v[j - 1] : 0.0f);
-    }
-    float nv[P];
-    const float rk = 1.0f / (float)k;
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const float a = (j < k) ? v[j] : 0.0f;
-      const float b = (j >= 1 && j <= k) ? v[j - 1] : 0.0f;
-      nv[j] = (j <= k) ? ((t + (float)j) * a + ((float)(k + 1 - j) - t) * b) * rk : 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) v[j] = nv[j];
-  }
-#pragma unroll
-  for (int j = 0; j < P; ++j) w[j] = v[j];
-}
-
-// Cells (mod N) and weights of the p-point stencil of one axis, for grid
-// coordinate u (float64).  Even p: first cell floor(u) - (p/2 - 1); odd p:
-// first cell floor(u + 1/2) - (p-1)/2.  Weights are W^(p)(cell - u) of
-// Sec. 2.3 written per offset with f = u - floor(...).
-template <int P>
-__device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], float (&w)[P]) {
-  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
-  const int first = (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
-  const float f = (float)(u - fl);
-  if constexpr (P == 1) {
-    w[0] = 1.0f;
-  } else if constexpr (P == 2) {
-    w[0] = 1.0f - f;
-    w[1] = f;
-  } else if constexpr (P == 3) {
-    const float a = 0.5f - f, c = 0.5f + f;
-    w[0] = 0.5f * a * a;
-    w[1] = 0.75f - f * f;
-    w[2] = 0.5f * c * c;
-  } else if constexpr (P == 4) {
-    const float t = 1.0f - f;
-    const float f2 = f * f, t2 = t * t;
-    w[0] = t2 * t * (1.0f / 6.0f);
-    w[1] = (4.0f - 6.0f * f2 + 3.0f * f2 * f) * (1.0f / 6.0f);
-    w[2] = (4.0f - 6.0f * t2 + 3.0f * t2 * t) * (1.0f / 6.0f);
-    w[3] = f2 * f * (1.0f / 6.0f);
-  } else {
-    float wd[P];
-    bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, wd);
-  }
-  // first + i lies in [-(p-1), N + p - 1]
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int c = first + i;
-    cell[i] = c < 0 ? c + n : (c >= n ? c - n : c);
-  }
-}
-
-// derivative dW/ds of the same weights (s = cell - u)
-template <int P>
-__device__ __forceinline__ void stencil_1d_deriv(double u, float (&dw)[P]) {
-  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
-  const float f = (float)(u - fl);
-  if constexpr (P == 1) {
-    dw[0] = 0.0f;
-  } else if constexpr (P == 2) {
-    // s = -f (|s|<1, s<=0) -> W' = +1 ; s = 1-f > 0 -> W' = -1
-    // at f == 0: s = 0 gives sign(0) = 0 and s = 1 lies outside |s| < 1
-    dw[0] = (f > 0.0f) ? 1.0f : 0.0f;
-    dw[1] = (f > 0.0f) ? -1.0f : 0.0f;
-  } else if constexpr (P == 3) {
-    // s0 = -1-f, s1 = -f, s2 = 1-f
-    dw[0] = (0.5f - f);           // W' = -(3/2-|s|) sgn(s), s<0 -> +(1/2 - f)
-    dw[1] = 2.0f * f;             // -2 s
-    dw[2] = -(0.5f + f);          // s>0 -> -(3/2 - (1-f))
-  } else if constexpr (P > 4) {
-    float w[P];
-    bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, dw);
-  } else {
-    const float t = 1.0f - f;
-    // s0 = -1-f (|s| in [1,2)): W' = +(1/2)(2-|s|)^2 = t^2/2
-    dw[0] = 0.5f * t * t;
-    // s1 = -f: W' = -2 s + 1.5 s |s| = 2 f - 1.5 f^2
-    dw[1] = 2.0f * f - 1.5f * f * f;
-    // s2 = 1 - f = t: W' = -2 t + 1.5 t^2
-    dw[2] = -2.0f * t + 1.5f * t * t;
-    // s3 = 2 - f (|s| in (1,2]): W' = -(1/2)(2-|s|)^2 = -f^2/2
-    dw[3] = -0.5f * f * f;
-  }
-}
 
 // ------------------------------------------------------------------ deposit
 // Fixed-point accumulation.  LDS float atomics are ~20x slower than integer
@@ -1375,95 +675,6 @@ hipError_t launch_copy_grid(const Geom& g, const Buffers& b, int which, int mock
                             hipStream_t s) {
   hipLaunchKernelGGL(k_copy_grid, dim3(4096), dim3(256), 0, s, (const float*)b.grid, g, which,
                      mock, dst);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ adjoint gather
-// dL/dx_{j,alpha} = -(N/L) sum_a sum_{g in stencil_a} G_a(g) W'(s_alpha) prod_{beta != alpha} W(s_beta)
-// where G_a = dL/drho_a sits in the grid buffer with the deposit's layout.
-template <int P, bool IL, typename TP>
-__global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos, int64_t n_total,
-                                                     const int64_t* __restrict__ offsets,
-                                                     const float* __restrict__ grid, Geom g,
-                                                     const float* __restrict__ w,
-                                                     TP* __restrict__ grad) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_total) return;
-  double x, y, z;
-  load_pos(pos, j, x, y, z);
-  const int mock = mock_of(offsets, g.batch, j);
-  const int n = g.n;
-  const double u[3] = {grid_coord(x, g.box, g.inv), grid_coord(y, g.box, g.inv),
-                       grid_coord(z, g.box, g.inv)};
-  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-  constexpr int NG = IL ? 2 : 1;
-#pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const double sh = gi ? 0.5 : 0.0;
-    int c[3][P];
-    float w[3][P], d[3][P];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      stencil_1d<P>(u[ax] + sh, n, c[ax], w[ax]);
-      stencil_1d_deriv<P>(u[ax] + sh, d[ax]);
-    }
-#pragma unroll
-    for (int a = 0; a < P; ++a) {
-#pragma unroll
-      for (int bq = 0; bq < P; ++bq) {
-#pragma unroll
-        for (int cq = 0; cq < P; ++cq) {
-          const float gv = IL ? grid[2 * complex_index(g, mock, c[0][a], c[1][bq], c[2][cq]) + gi]
-                              : grid[real_cell_index(g, mock, c[0][a], c[1][bq], c[2][cq])];
-          gx += gv * d[0][a] * w[1][bq] * w[2][cq];
-          gy += gv * w[0][a] * d[1][bq] * w[2][cq];
-          gz += gv * w[0][a] * w[1][bq] * d[2][cq];
-        }
-      }
-    }
-  }
-  // a particle of mass w_j deposits w_j times the kernel
-  const double sc = -(double)n / g.box * (w ? (double)w[j] : 1.0);
-  grad[3 * j + 0] = (TP)(sc * gx);
-  grad[3 * j + 1] = (TP)(sc * gy);
-  grad[3 * j + 2] = (TP)(sc * gz);
-}
-
-template <int P>
-static void dispatch_gather(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                            int64_t n_total, const float* w, const Buffers& b, void* grad,
-                            hipStream_t s) {
-  const unsigned blocks = (unsigned)((n_total + 255) / 256);
-  if (dt == EST_F32) {
-    if (g.il)
-      hipLaunchKernelGGL((k_gather_grad<P, true, float>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, w, (float*)grad);
-    else
-      hipLaunchKernelGGL((k_gather_grad<P, false, float>), dim3(blocks), dim3(256), 0, s,
-                         (const float*)pos, n_total, offsets, (const float*)b.grid, g, w, (float*)grad);
-  } else {
-    if (g.il)
-      hipLaunchKernelGGL((k_gather_grad<P, true, double>), dim3(blocks), dim3(256), 0, s,
-                         (const double*)pos, n_total, offsets, (const float*)b.grid, g, w,
-                         (double*)grad);
-    else
-      hipLaunchKernelGGL((k_gather_grad<P, false, double>), dim3(blocks), dim3(256), 0, s,
-                         (const double*)pos, n_total, offsets, (const float*)b.grid, g, w,
-                         (double*)grad);
-  }
-}
-
-hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
-                              int64_t n_total, const float* w, const Buffers& b, void* grad,
-                              hipStream_t s) {
-  switch (g.order) {
-    case 1: dispatch_gather<1>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-    case 2: dispatch_gather<2>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-    case 3: dispatch_gather<3>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-    case 4: dispatch_gather<4>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-    case 5: dispatch_gather<5>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-    default: dispatch_gather<6>(g, pos, dt, offsets, n_total, w, b, grad, s); break;
-  }
   return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ struct Buffers {
   float* sw;               // max_particles masses / largest mass, bucket order (weighted handles)
   float* tw;               // max_particles masses in super-bucket order (weighted, two-level)
   double* wpart;           // batch x kWSlices x 2 partial mass sums (weighted handles)
+  float2* cbuf;            // batch x N x N x (N/2+1) combined C(m) (interlace codes 2, 3)
   double* coef;            // batch * kMaxBins adjoint coefficients
   uint64_t* mode_partials_n;  // kMaxBinBlocks * kMaxBins
   double* mode_partials_k;    // kMaxBinBlocks * kMaxBins
@@ -155,6 +156,10 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
 // adjoint: coefficients from dL/dP, then fused z-forward, gradient spectrum, z-inverse
 hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& tu,
                                    const double* dldp, int n_dk, int n_bins, hipStream_t s);
+// adjoint for more than two grids: from the stored spectra (after the z pass)
+// to the gradient spectra of every slab; the inverse z, y, x passes follow
+hipError_t launch_multi_adjoint(const Geom& g, const Buffers& b, const double* dldp, int n_dk,
+                                int n_bins, hipStream_t s);
 hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const int32_t* modes,
                                int64_t n, double* out, hipStream_t s);
 hipError_t launch_export_delta(const Geom& g, const Buffers& b, int mock, double* out,

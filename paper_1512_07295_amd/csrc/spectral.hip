@@ -574,6 +574,100 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
   return hipGetLastError();
 }
 
+// ---- adjoint with more than two grids (from the stored spectra, after the z
+// pass).  (1) C(m) of every half-space mode goes to cbuf; (2) every element
+// k of every slab q gets dZ_q(k) from the modes m = k and m' = -k that are
+// stored (the transposes of the unpacking, as in the fused pair kernel),
+// with dC/dF_j = exp(+i pi s_j/N)/G; (3) the inverse FFT passes follow.
+__global__ __launch_bounds__(256) void k_multi_cbuf(const float2* __restrict__ data, Geom g,
+                                                    const float2* __restrict__ phase,
+                                                    float2* __restrict__ cbuf) {
+  const int n = g.n, nh = n / 2 + 1;
+  const int64_t per = (int64_t)n * n * nh;
+  const int mock = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int mz = (int)(i % nh);
+    const int y = (int)((i / nh) % n), x = (int)(i / ((int64_t)n * nh));
+    cbuf[(int64_t)mock * per + i] = multi_mode(data, g, mock, signed_freq(x, n), signed_freq(y, n), mz, phase);
+  }
+}
+
+// gradient with respect to C at half-space mode (x, y, mz) times the half-space weight and
+// 1/W^2 (zero outside the bins)
+__device__ __forceinline__ float2 multi_grad_c(const float2* __restrict__ cb, const Geom& g, int x,
+                                               int y, int mz, const double* __restrict__ cf,
+                                               const float* __restrict__ inv_w2, int n_dk,
+                                               int n_bins) {
+  const int n = g.n, nh = n / 2 + 1;
+  const int mx = signed_freq(x, n), my = signed_freq(y, n);
+  const int m2 = mx * mx + my * my + mz * mz;
+  const int b = m2 ? shell_of(m2, n_dk) : 0;
+  if (b < 1 || b > n_bins) return make_float2(0.f, 0.f);
+  const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
+  const float s = wgt * (float)cf[b - 1] * inv_w2[x] * inv_w2[y] * inv_w2[mz];
+  return cscale(cb[((int64_t)x * n + y) * nh + mz], s);
+}
+
+__global__ __launch_bounds__(256) void k_multi_adjoint(float2* __restrict__ data, Geom g,
+                                                       const float2* __restrict__ cbuf,
+                                                       const float2* __restrict__ phase,
+                                                       const float* __restrict__ inv_w2,
+                                                       const double* __restrict__ coef, int n_dk,
+                                                       int n_bins) {
+  const int n = g.n, nh = n / 2 + 1;
+  const int64_t n3 = (int64_t)n * n * n;
+  const int slab = blockIdx.y;
+  const int mock = slab / g.npair, q = slab % g.npair;
+  const float2* cb = cbuf + (int64_t)mock * n * n * nh;
+  const double* cf = coef + (int64_t)mock * n_bins;
+  const float inv_g = 1.0f / (float)g.ng;
+  const int ma = grid_mask(g.code, 2 * q), mb = grid_mask(g.code, 2 * q + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / ((int64_t)n * n));
+    float2 acc = make_float2(0.f, 0.f);
+    // (a) m = k stored: Z_q(k) enters F_2q(m) and F_2q+1(m) directly
+    if (z <= n / 2) {
+      const float2 gc = multi_grad_c(cb, g, x, y, z, cf, inv_w2, n_dk, n_bins);
+      const int m[3] = {signed_freq(x, n), signed_freq(y, n), z};
+      int sa = 0, sb = 0;
+      for (int a = 0; a < 3; ++a) {
+        sa += ((ma >> a) & 1) ? m[a] : 0;
+        sb += ((mb >> a) & 1) ? m[a] : 0;
+      }
+      const float2 ga = cscale(cmul(cconj(phase[mod_2n<false>(sa, n)]), gc), inv_g);
+      const float2 gb = cscale(cmul(cconj(phase[mod_2n<false>(sb, n)]), gc), inv_g);
+      acc = cadd(acc, make_float2(0.5f * (ga.x - gb.y), 0.5f * (ga.y + gb.x)));
+    }
+    // (b) m' = -k stored: Z_q(k) = Z_q(-m') enters through the conjugate
+    const int xp = neg_mod<false>(x, n), yp = neg_mod<false>(y, n), zp = neg_mod<false>(z, n);
+    if (zp <= n / 2) {
+      const float2 gc = multi_grad_c(cb, g, xp, yp, zp, cf, inv_w2, n_dk, n_bins);
+      const int m[3] = {signed_freq(xp, n), signed_freq(yp, n), zp};
+      int sa = 0, sb = 0;
+      for (int a = 0; a < 3; ++a) {
+        sa += ((ma >> a) & 1) ? m[a] : 0;
+        sb += ((mb >> a) & 1) ? m[a] : 0;
+      }
+      const float2 ga = cscale(cmul(cconj(phase[mod_2n<false>(sa, n)]), gc), inv_g);
+      const float2 gb = cscale(cmul(cconj(phase[mod_2n<false>(sb, n)]), gc), inv_g);
+      acc = cadd(acc, make_float2(0.5f * (ga.x + gb.y), 0.5f * (-ga.y + gb.x)));
+    }
+    data[complex_index(g, slab, x, y, z)] = acc;
+  }
+}
+
+hipError_t launch_multi_adjoint(const Geom& g, const Buffers& b, const double* dldp, int n_dk,
+                                int n_bins, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_coef, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s, dldp,
+                     n_bins, b.mode_n, b.norm, g.box, b.coef);
+  hipLaunchKernelGGL(k_multi_cbuf, dim3(4096, g.batch), dim3(256), 0, s, b.grid, g, b.phase, b.cbuf);
+  hipLaunchKernelGGL(k_multi_adjoint, dim3(4096, g.batch * g.npair), dim3(256), 0, s, b.grid, g,
+                     b.cbuf, b.phase, b.inv_w2, b.coef, n_dk, n_bins);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_spectrum(const Geom& g, const Buffers& b, const Tune& tu,
                                    const double* dldp, int n_dk, int n_bins, hipStream_t s) {
   hipLaunchKernelGGL(k_adjoint_coef, dim3((n_bins + 127) / 128, g.batch), dim3(128), 0, s, dldp,

@@ -57,6 +57,7 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(order=0), fsest.EST_EINVAL),
     (dict(order=7), fsest.EST_EINVAL),
     (dict(interlace=4), fsest.EST_EINVAL),
+    (dict(interlace=3, batch=20000), fsest.EST_EINVAL),  # 4 complex grids per set
     (dict(interlace=-1), fsest.EST_EINVAL),
     (dict(batch=0), fsest.EST_EINVAL),
     (dict(box=0.0), fsest.EST_EINVAL),
@@ -159,12 +160,14 @@ def test_set_weights_null_handle():
 
 @pytest.mark.parametrize("code,slabs", [(0, 1), (1, 1), (2, 2), (3, 4)])
 def test_interlace_codes_reserve_one_complex_grid_per_pair(code, slabs):
-    """Codes 2 and 3 hold 4 and 8 real grids as 2 and 4 complex grids."""
+    """Codes 2 and 3 hold 4 and 8 real grids as 2 and 4 complex grids, plus a
+    half-spectrum buffer of the combined C(m)."""
     base = fsest.estimator_workspace_bytes(_cfg(n_grid=64, interlace=1))
     ws = fsest.estimator_workspace_bytes(_cfg(n_grid=64, interlace=code))
     grid = 64 * (64 * 64) * 8  # one complex grid: 64 planes of 4096 elements (no pad)
+    cbuf = 64 * 64 * 33 * 8 if code >= 2 else 0  # combined C(m) for the adjoint
     if code >= 1:
-        assert ws - base == (slabs - 1) * grid
+        assert ws - base == (slabs - 1) * grid + cbuf
 
 
 def test_atomic_sort_flag_accepted_and_drops_two_level_buffers():

@@ -125,13 +125,43 @@ def test_batched_weighted_graph_with_four_grids(torch):
     est.close()
 
 
-def test_backward_unsupported_for_more_grids(torch):
-    import paper_1512_07295_amd as F
-    est = _est(16, 100.0, 4, 3, maxp=100)
-    pos = to_dev(torch, synth.uniform(100, 100.0, 1, np.float32))
-    with pytest.raises(F.FsestError) as ei:
-        est.backward(pos, torch.zeros((1, 8), dtype=torch.float64, device="cuda"), n_bins=8)
-    assert ei.value.status == F.EST_EUNSUPPORTED
+@pytest.mark.parametrize("n,p,code,dtype", [(32, 4, 2, np.float32), (32, 2, 3, np.float32),
+                                            (24, 3, 3, np.float64), (16, 4, 3, np.float32)])
+def test_backward_matches_oracle_gradient(torch, n, p, code, dtype):
+    from oracle import adjoint
+    box, nb = 1000.0, 8
+    pos = synth.zeldovich(16, box, 5, dtype=dtype)
+    tgt = synth.zeldovich(16, box, 6, dtype=dtype)
+    _, target, counts = oracle.power(tgt, box, n, p, code, 1, nb)
+    _, pk, _ = oracle.power(pos, box, n, p, code, 1, nb)
+    _, dldp = adjoint.chi2_loss(pk, target, counts)
+    est = _est(n, box, p, code, maxp=len(pos))
+    g = est.backward(to_dev(torch, pos), to_dev(torch, dldp[None, :]), n_bins=nb).cpu().numpy()
+    ref = adjoint.position_gradient(pos, box, n, p, code, 1, nb, dldp)
+    assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+    # the handle computes the forward again afterwards
+    k, pk2, _ = est.power(to_dev(torch, pos), n_bins=nb)
+    assert rel_err(pk2.cpu().numpy()[0], pk) < P_TOL
+    est.close()
+
+
+def test_backward_batched_weighted_four_grids(torch):
+    from oracle import adjoint
+    n, box, nb, code = 32, 800.0, 10, 2
+    a = synth.zeldovich(12, box, 1, dtype=np.float32)
+    b = synth.uniform(3000, box, 2, np.float32)
+    pos = np.concatenate([a, b])
+    offs = np.array([0, len(a), len(pos)], dtype=np.int64)
+    w = np.random.default_rng(4).exponential(1.0, len(pos)).astype(np.float32)
+    dldp = np.random.default_rng(0).normal(size=(2, nb))
+    est = _est(n, box, 4, code, batch=2, maxp=len(pos), weighted=True)
+    est.set_weights(to_dev(torch, w))
+    g = est.backward(to_dev(torch, pos), to_dev(torch, dldp), offsets=to_dev(torch, offs),
+                     n_bins=nb).cpu().numpy()
+    for i in range(2):
+        s = slice(offs[i], offs[i + 1])
+        ref = adjoint.position_gradient(pos[s], box, n, 4, code, 1, nb, dldp[i], weights=w[s])
+        assert np.max(np.abs(g[s] - ref)) <= 1e-4 * np.max(np.abs(ref)), i
     est.close()
 
 
