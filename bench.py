@@ -7,8 +7,9 @@ float32) -> PCS deposit on a 1024^3 grid and on the grid shifted by H/2 ->
 (512 bins).  A step is one deposit -> transform -> power over the resident
 particles.  Beside it (same JSON line): a batch of 64 uneven mocks on 128^3
 grids replayed as one HIP graph, forward + backward of a P(k) loss for
-128^3 particles on a 256^3 grid, the direct-summation engine, and the
-paper's own Zel'dovich shape (360^3 particles on a 480^3 mixed-radix grid).
+128^3 particles on a 256^3 grid, the direct-summation engine, the
+paper's own Zel'dovich shape (360^3 particles on a 480^3 mixed-radix grid),
+and the extensions (order 6, eight interlaced grids, masses) at 512^3.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -34,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 MEASURED_TRAFFIC = {
     "deposit": {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
+                    "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
         "sha256_16": "8664c27fa7bfd38c",
         "workload": "pcs_il_n1024_za512",
@@ -267,6 +269,53 @@ def paper_za_leg(args, torch, F, est_mod, synth):
                        "n_particles": npart}}
 
 
+def variants_leg(args, torch, F, est_mod, synth):
+    """The headline step with the paper's extensions, on 256^3 Zel'dovich
+    particles and a 512^3 grid (L = 1000): order 6, eight interlaced grids,
+    per-particle masses; each against the plain PCS + pair at the same size."""
+    n_side, box, n = 256, 1000.0, 512
+    pos = torch.as_tensor(synth.zeldovich(n_side, box, 9, dtype=np.float32), device="cuda")
+    npart = pos.shape[0]
+    masses = torch.as_tensor(np.random.default_rng(1).exponential(1.0, npart).astype(np.float32),
+                             device="cuda")
+    out = {}
+    for name, order, code, weighted in (("pcs_pair", 4, 1, False), ("order6_pair", 6, 1, False),
+                                        ("pcs_eight_grids", 4, 3, False),
+                                        ("pcs_pair_masses", 4, 1, True)):
+        est = est_mod.Estimator(n, box, order, code, 1, npart, weighted=weighted)
+        if weighted:
+            est.set_weights(masses)
+        n_bins = n // 2
+        k = torch.empty((1, n_bins), dtype=torch.float64, device="cuda")
+        pk = torch.empty_like(k)
+        nm = torch.empty((1, n_bins), dtype=torch.int64, device="cuda")
+
+        def step():
+            F.estimator_deposit(est.h, pos, F.EST_F32, None, npart)
+            F.estimator_transform(est.h)
+            F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        F.estimator_profile(est.h, 1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F.estimator_profile(est.h, 0)
+        prof = F.profile_table(est.h)
+        est.close()
+        out[name] = {"value": round(npart * args.steps / dt / 1e6, 2), "unit": "Mparticles/s",
+                     "ms_per_step": round(1e3 * dt / args.steps, 4),
+                     "stage_ms": {kname: round(v[0] / v[1], 4) for kname, v in prof.items()}}
+        log("variant %s: %.3f ms per step" % (name, 1e3 * dt / args.steps))
+    out["config"] = {"workload": "256^3 Zel'dovich particles, L=1000, 512^3 grid, P(k) in k_f shells "
+                                 "to Nyquist; default launch shapes", "n_particles": npart}
+    return out
+
+
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
@@ -396,6 +445,7 @@ def main():
         extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth)
         extra["direct_sum"] = direct_leg(args, torch, est_mod, synth)
         extra["paper_za_480"] = paper_za_leg(args, torch, F, est_mod, synth)
+        extra["variants"] = variants_leg(args, torch, F, est_mod, synth)
     out = {
         "metric": "Mparticles/s end-to-end P(k), PCS+interlace 1024^3 grid; fwd+bwd & batched vs plain",
         "value": round(head["value"], 2),

@@ -219,7 +219,7 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   const bool weighted = (c.flags & EST_FLAG_WEIGHTS) != 0;
   bb.sw = weighted ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
   bb.tw = weighted && two_level ? (float*)take((size_t)c.max_particles * sizeof(float)) : nullptr;
-  bb.wpart = weighted ? (double*)take(batch * kWSlices * 2 * sizeof(double)) : nullptr;
+  bb.wpart = weighted ? (double*)take(batch * weight_slices(c.batch) * 2 * sizeof(double)) : nullptr;
   bb.cbuf = c.interlace >= 2 ? (float2*)take(batch * n * n * (half + 1) * sizeof(float2)) : nullptr;
   bb.coef = (double*)take(batch * half * sizeof(double));
   bb.mode_partials_n = (uint64_t*)take(512 * half * sizeof(uint64_t));

@@ -151,7 +151,7 @@ int direct_slices(int ngrid, int64_t n) {
 
 // workspace: fixed-point phases, the mass sums (partials, totals, flags),
 // then the per-slice partial spectra
-constexpr size_t kDirMassBytes = 256 * ((2 * kWSlices * 8 + 2 * 8 + 64 * 4 + 255) / 256);
+constexpr size_t kDirMassBytes = 256 * ((2 * kWSlicesMax * 8 + 2 * 8 + 64 * 4 + 255) / 256);
 
 size_t direct_workspace(int ngrid, int64_t n) {
   const int64_t nmodes = (int64_t)ngrid * ngrid * (ngrid / 2 + 1);
@@ -168,7 +168,7 @@ hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n
   uint32_t* q = (uint32_t*)ws;
   char* mass = (char*)ws + ((size_t)n * 3 * sizeof(uint32_t) + 255) / 256 * 256;
   double* wpart = (double*)mass;
-  double* norm = wpart + 2 * kWSlices;
+  double* norm = wpart + 2 * kWSlicesMax;
   uint32_t* stats = (uint32_t*)(norm + 2);
   double* partial = (double*)(mass + kDirMassBytes);
   if (w) {

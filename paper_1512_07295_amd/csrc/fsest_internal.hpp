@@ -16,7 +16,12 @@ constexpr int kMaxBinBlocks = 2048;  // upper bound of P(k) reduction blocks per
 constexpr int kFineMax = 16;    // buckets per super-bucket edge (two-level sort)
 constexpr int kMaxSuper = 8192; // super-buckets one workgroup histograms in LDS
 constexpr int kMaxSortBlocks = 1024;  // workgroups of the super-bucket passes
-constexpr int kWSlices = 64;    // workgroups per set of the mass-sum pass
+constexpr int kWSlicesMax = 1024;  // workgroups per set of the mass-sum pass, at most
+// workgroups per set of the mass-sum pass: ~2048 in all, 16 .. 1024 per set
+__host__ __device__ inline int weight_slices(int batch) {
+  const int s = 2048 / batch;
+  return s < 16 ? 16 : (s > kWSlicesMax ? kWSlicesMax : s);
+}
 
 // Geometry and per-call constants that device code needs.
 struct Geom {
@@ -87,7 +92,7 @@ struct Buffers {
                            // (N_P, N_P for equal masses)
   float* sw;               // max_particles masses / largest mass, bucket order (weighted handles)
   float* tw;               // max_particles masses in super-bucket order (weighted, two-level)
-  double* wpart;           // batch x kWSlices x 2 partial mass sums (weighted handles)
+  double* wpart;           // batch x weight_slices(batch) x 2 partial mass sums (weighted)
   float2* cbuf;            // batch x N x N x (N/2+1) combined C(m) (interlace codes 2, 3)
   double* coef;            // batch * kMaxBins adjoint coefficients
   uint64_t* mode_partials_n;  // kMaxBinBlocks * kMaxBins

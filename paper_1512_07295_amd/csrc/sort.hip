@@ -44,10 +44,10 @@ hipError_t launch_set_counts(const int64_t* offsets, int64_t n_total, int batch,
 }
 
 // ------------------------------------------------------------------ masses
-// Per set, kWSlices workgroups each sum w and w^2 over a fixed slice of the
-// set's particles (strided per thread, then a fixed tree over the
-// workgroup), and a second pass adds the slices in order: the totals do not
-// depend on scheduling.  The largest mass goes to stats[4] (non-negative
+// Per set, weight_slices(batch) workgroups each sum w and w^2 over a fixed
+// slice of the set's particles (strided per thread, then a fixed tree over
+// the workgroup), and a second pass adds the slices in order: the totals
+// depend on the batch size only, not on scheduling.  The largest mass goes to stats[4] (non-negative
 // floats order like their bit patterns) and any negative, NaN or infinite
 // mass sets stats[5].
 constexpr int kWThreads = 256;
@@ -58,10 +58,10 @@ __global__ __launch_bounds__(kWThreads) void k_weight_stats(const float* __restr
                                                             double* __restrict__ wpart,
                                                             uint32_t* __restrict__ stats) {
   __shared__ double sa[kWThreads / 64], sb[kWThreads / 64];
-  const int m = blockIdx.y, slice = blockIdx.x;
+  const int m = blockIdx.y, slice = blockIdx.x, ns = gridDim.x;
   const int64_t j0 = offsets ? offsets[m] : 0, j1 = offsets ? offsets[m + 1] : n_total;
   const int64_t len = j1 - j0;
-  const int64_t s0 = j0 + len * slice / kWSlices, s1 = j0 + len * (slice + 1) / kWSlices;
+  const int64_t s0 = j0 + len * slice / ns, s1 = j0 + len * (slice + 1) / ns;
   double a = 0.0, b = 0.0;
   float mx = 0.0f;
   bool bad = false;
@@ -96,19 +96,20 @@ __global__ __launch_bounds__(kWThreads) void k_weight_stats(const float* __restr
       ta += sa[i];
       tb += sb[i];
     }
-    double* dst = wpart + 2 * ((int64_t)m * kWSlices + slice);
+    double* dst = wpart + 2 * ((int64_t)m * ns + slice);
     dst[0] = ta;
     dst[1] = tb;
   }
 }
 
-__global__ void k_weight_final(const double* __restrict__ wpart, int batch, double* __restrict__ norm) {
+__global__ void k_weight_final(const double* __restrict__ wpart, int batch, int ns,
+                               double* __restrict__ norm) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= batch) return;
   double ta = 0.0, tb = 0.0;
-  for (int i = 0; i < kWSlices; ++i) {
-    ta += wpart[2 * ((int64_t)m * kWSlices + i)];
-    tb += wpart[2 * ((int64_t)m * kWSlices + i) + 1];
+  for (int i = 0; i < ns; ++i) {
+    ta += wpart[2 * ((int64_t)m * ns + i)];
+    tb += wpart[2 * ((int64_t)m * ns + i) + 1];
   }
   norm[2 * m] = ta;
   norm[2 * m + 1] = tb;
@@ -118,9 +119,11 @@ hipError_t launch_weight_stats(const float* w, const int64_t* offsets, int64_t n
                                double* wpart, double* norm, uint32_t* stats, hipStream_t s) {
   hipError_t e = launch_fill_u32(stats + 4, 2, 0u, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_weight_stats, dim3(kWSlices, batch), dim3(kWThreads), 0, s, w, offsets,
+  const int ns = weight_slices(batch);
+  hipLaunchKernelGGL(k_weight_stats, dim3(ns, batch), dim3(kWThreads), 0, s, w, offsets,
                      n_total, wpart, stats);
-  hipLaunchKernelGGL(k_weight_final, dim3((batch + 63) / 64), dim3(64), 0, s, wpart, batch, norm);
+  hipLaunchKernelGGL(k_weight_final, dim3((batch + 63) / 64), dim3(64), 0, s, wpart, batch, ns,
+                     norm);
   return hipGetLastError();
 }
 
