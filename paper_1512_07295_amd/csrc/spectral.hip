@@ -505,38 +505,80 @@ static int pair_blocks(const Geom& g, const Tune& tu) {
 }
 
 // Shell sums of w |C(m)|^2 / W(m)^2 over the half space for more than two
-// grids, from the stored spectra (after the z pass); runs of up to 16 m_z
-// per thread as in the mode table.
+// grids, from the stored spectra (after the z pass).  A workgroup takes row
+// pairs (x, y), (-x, -y) as the fused pair kernel does: it stages both rows
+// of every slab in LDS with coalesced loads, then half the threads finish
+// the half-space modes of each row (runs of m_z per thread, shells
+// advancing along the run).
 constexpr int kMultiBlocks = 1024;
+constexpr int kMultiThreads = 256;
 
-__global__ __launch_bounds__(256) void k_multi_bins(const float2* __restrict__ data, Geom g,
-                                                    const float2* __restrict__ phase,
-                                                    const float* __restrict__ inv_w2, int n_dk,
-                                                    int n_bins, double* __restrict__ partials) {
+__global__ __launch_bounds__(kMultiThreads) void k_multi_pairs(
+    const float2* __restrict__ data, Geom g, const float2* __restrict__ phase,
+    const float* __restrict__ inv_w2, int n_dk, int n_bins, double* __restrict__ partials) {
+  extern __shared__ float2 rows[];  // 2 npair rows of N + N/16 + 1 elements
   __shared__ double hist[kMaxBins];
-  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
-  __syncthreads();
   const int n = g.n, nm = n / 2 + 1;
   const int mock = blockIdx.y;
-  constexpr int CH = 16;
-  const int chunks = (nm + CH - 1) / CH;
-  const int64_t items = (int64_t)n * n * chunks;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = it / chunks;
-    const int ch = (int)(it % chunks);
-    const int x = (int)(row / n), y = (int)(row % n);
-    const int mx = signed_freq(x, n), my = signed_freq(y, n);
+  const int rowp = n + n / 16 + 1;
+  const int nr = 2 * g.npair;
+  const int64_t npairs = (int64_t)n * n / 2 + 2;
+  for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
+  const int side = threadIdx.x / (kMultiThreads / 2);
+  const int t = threadIdx.x % (kMultiThreads / 2);
+  const int per = (nm + kMultiThreads / 2 - 1) / (kMultiThreads / 2);
+  const float inv_g = 1.0f / (float)g.ng;
+  for (int64_t pg = blockIdx.x; pg < npairs; pg += gridDim.x) {
+    int xa, ya;
+    pair_rows(pg, n, xa, ya);
+    const int xb = neg_mod<false>(xa, n), yb = neg_mod<false>(ya, n);
+    const bool self = (xa == xb) && (ya == yb);
+    __syncthreads();  // the previous pair's rows are consumed
+    // row r: slab r / 2, side r % 2 (0: (xa, ya), 1: (xb, yb))
+    for (int idx = threadIdx.x; idx < nr * n; idx += blockDim.x) {
+      const int r = idx / n, j = idx % n;
+      const int xr = (r & 1) ? xb : xa, yr = (r & 1) ? yb : ya;
+      rows[r * rowp + lds_index<1>(j)] = data[complex_index(g, mock * g.npair + r / 2, xr, yr, j)];
+    }
+    __syncthreads();
+    if (side == 1 && self) continue;
+    const int xr = side ? xb : xa, yr = side ? yb : ya;
+    const int mx = signed_freq(xr, n), my = signed_freq(yr, n);
+    const int z0 = t * per, z1 = min(z0 + per, nm);
+    if (z0 >= z1) continue;
+    const float wxy = inv_w2[xr] * inv_w2[yr];
     const int r2 = mx * mx + my * my;
-    const float wxy = inv_w2[x] * inv_w2[y];
+    const int m2_0 = r2 + z0 * z0;
+    int b = m2_0 ? shell_of(m2_0, n_dk) : 0;
+    int edge = (2 * b + 1) * n_dk;
+    edge *= edge;
     int cur_b = -1;
     float cur = 0.0f;
-    for (int mz = ch * CH; mz < min(ch * CH + CH, nm); ++mz) {
-      const int m2 = r2 + mz * mz;
-      if (m2 == 0) continue;
-      const int b = shell_of(m2, n_dk);
-      if (b < 1 || b > n_bins) continue;
-      const float2 c = multi_mode(data, g, mock, mx, my, mz, phase);
+    for (int mz = z0; mz < z1; ++mz) {
+      const int m4 = 4 * (r2 + mz * mz);
+      while (edge <= m4) {
+        ++b;
+        edge = (2 * b + 1) * n_dk;
+        edge *= edge;
+      }
+      if (b > n_bins) break;
+      if (b < 1) continue;  // below the first shell (and the k = 0 mode)
+      const int m[3] = {mx, my, mz};
+      const int zm = neg_mod<false>(mz, n);
+      float2 c = make_float2(0.f, 0.f);
+      for (int q = 0; q < g.npair; ++q) {
+        const float2 za = rows[(2 * q + side) * rowp + lds_index<1>(mz)];
+        const float2 zb = rows[(2 * q + (side ^ 1)) * rowp + lds_index<1>(zm)];
+        const float2 f[2] = {make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y)),
+                             make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x))};
+        for (int h = 0; h < 2; ++h) {
+          const int mk = grid_mask(g.code, 2 * q + h);
+          int sj = 0;
+          for (int a = 0; a < 3; ++a) sj += ((mk >> a) & 1) ? m[a] : 0;
+          c = cadd(c, cmul(phase[mod_2n<false>(sj, n)], f[h]));
+        }
+      }
+      c = cscale(c, inv_g);
       const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
       const float val = wgt * (c.x * c.x + c.y * c.y) * inv_w2[mz];
       if (b != cur_b) {
@@ -557,8 +599,15 @@ hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do
                         int n_bins, int subtract_shot, double* k, double* p, int64_t* nmodes,
                         hipStream_t s) {
   if (g.npair > 1) {
-    hipLaunchKernelGGL(k_multi_bins, dim3(kMultiBlocks, g.batch), dim3(256), 0, s, b.grid, g,
-                       b.phase, b.inv_w2, n_dk, n_bins, b.partials);
+    const size_t lds = sizeof(float2) * 2 * g.npair * (size_t)(g.n + g.n / 16 + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipFuncSetAttribute((const void*)k_multi_pairs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(float2) * 2 * 4 * (1024 + 64 + 1)));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_multi_pairs, dim3(kMultiBlocks, g.batch), dim3(kMultiThreads), lds, s,
+                       b.grid, g, b.phase, b.inv_w2, n_dk, n_bins, b.partials);
     hipLaunchKernelGGL(k_power_finalize, dim3(n_bins, g.batch), dim3(64), 0, s, b.partials,
                        kMultiBlocks, n_bins, b.mode_n, b.mode_k, b.norm, g.box, subtract_shot, k, p,
                        nmodes);
