@@ -328,8 +328,8 @@ est_status to_spectrum(est_handle h) {
   return ok();
 }
 
-// state after a forward pass: the multi-grid power needs the z pass first
-int forward_state(est_handle h) { return h->g.npair > 1 ? kSpectrum : kXY; }
+// state after a forward pass (the last FFT axis is fused with the shell sums)
+int forward_state(est_handle) { return kXY; }
 
 est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_t* offsets,
                        int64_t n_total, int n_dk, int n_bins, int sub, double* k, double* p,
@@ -338,13 +338,6 @@ est_status run_forward(est_handle h, const void* pos, est_dtype dt, const int64_
   if (st) return st;
   st = run_xy(h, -1);
   if (st) return st;
-  if (h->g.npair > 1) {
-    // several slabs per set: separate z pass, then the multi-grid shell sums
-    h->state = kXY;
-    if ((st = to_spectrum(h))) return st;
-    ProfScope ps(h, kPPower);
-    return dev_err(launch_power(h->g, h->b, h->tu, false, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
-  }
   ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, true, n_dk, n_bins, sub, k, p, nm, h->stream), "power");
 }
@@ -435,7 +428,6 @@ est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins, int32_t s
   if (h->state != kXY && h->state != kSpectrum)
     return fail(EST_ESTATE, "estimator_power needs estimator_transform first");
   if ((st = ensure_modes(h, n_dk, n_bins))) return st;
-  if (h->g.npair > 1 && (st = to_spectrum(h))) return st;
   ProfScope ps(h, kPPower);
   return dev_err(launch_power(h->g, h->b, h->tu, h->state == kXY, n_dk, n_bins, subtract_shot, k, p,
                               nmodes, h->stream),

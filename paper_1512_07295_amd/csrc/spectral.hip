@@ -505,28 +505,36 @@ static int pair_blocks(const Geom& g, const Tune& tu) {
 }
 
 // Shell sums of w |C(m)|^2 / W(m)^2 over the half space for more than two
-// grids, from the stored spectra (after the z pass).  A workgroup takes row
-// pairs (x, y), (-x, -y) as the fused pair kernel does: it stages both rows
-// of every slab in LDS with coalesced loads, then half the threads finish
-// the half-space modes of each row (runs of m_z per thread, shells
-// advancing along the run).
+// grids.  A workgroup takes row pairs (x, y), (-x, -y) as the fused pair
+// kernel does and stages both rows of every slab in LDS: with FFT, TPL
+// threads per row load it after the x and y passes and run its z transform
+// (compile-time length L, or L = 0 for a run-time plan); without, the stored
+// spectra are loaded cooperatively.  Then half the threads finish the
+// half-space modes of each row (runs of m_z per thread, shells advancing
+// along the run).
 constexpr int kMultiBlocks = 1024;
 constexpr int kMultiThreads = 256;
 
-__global__ __launch_bounds__(kMultiThreads) void k_multi_pairs(
-    const float2* __restrict__ data, Geom g, const float2* __restrict__ phase,
-    const float* __restrict__ inv_w2, int n_dk, int n_bins, double* __restrict__ partials) {
+template <int L, bool FFT>
+__global__ __launch_bounds__(1024) void k_multi_pairs(
+    float2* __restrict__ data, Geom g, const float2* __restrict__ tw,
+    const float2* __restrict__ phase, const float* __restrict__ inv_w2, int n_dk, int n_bins,
+    double* __restrict__ partials, RtLine rt) {
   extern __shared__ float2 rows[];  // 2 npair rows of N + N/16 + 1 elements
   __shared__ double hist[kMaxBins];
+  constexpr bool P2 = L != 0;
+  constexpr int EPT = P2 ? LinePlan<(P2 ? L : 16)>::EPT : 16;
+  const int TPL = P2 ? LinePlan<(P2 ? L : 16)>::TPL : rt.tpl;
   const int n = g.n, nm = n / 2 + 1;
   const int mock = blockIdx.y;
   const int rowp = n + n / 16 + 1;
   const int nr = 2 * g.npair;
   const int64_t npairs = (int64_t)n * n / 2 + 2;
   for (int i = threadIdx.x; i < n_bins; i += blockDim.x) hist[i] = 0.0;
-  const int side = threadIdx.x / (kMultiThreads / 2);
-  const int t = threadIdx.x % (kMultiThreads / 2);
-  const int per = (nm + kMultiThreads / 2 - 1) / (kMultiThreads / 2);
+  const int half = blockDim.x / 2;
+  const int side = threadIdx.x / half;
+  const int t = threadIdx.x % half;
+  const int per = (nm + half - 1) / half;
   const float inv_g = 1.0f / (float)g.ng;
   for (int64_t pg = blockIdx.x; pg < npairs; pg += gridDim.x) {
     int xa, ya;
@@ -535,10 +543,30 @@ __global__ __launch_bounds__(kMultiThreads) void k_multi_pairs(
     const bool self = (xa == xb) && (ya == yb);
     __syncthreads();  // the previous pair's rows are consumed
     // row r: slab r / 2, side r % 2 (0: (xa, ya), 1: (xb, yb))
-    for (int idx = threadIdx.x; idx < nr * n; idx += blockDim.x) {
-      const int r = idx / n, j = idx % n;
+    if constexpr (FFT) {
+      const int r = threadIdx.x / TPL, tr = threadIdx.x % TPL;
       const int xr = (r & 1) ? xb : xa, yr = (r & 1) ? yb : ya;
-      rows[r * rowp + lds_index<1>(j)] = data[complex_index(g, mock * g.npair + r / 2, xr, yr, j)];
+      const float2* gp = data + complex_index(g, mock * g.npair + r / 2, xr, yr, 0);
+      float2* own = rows + r * rowp;
+      float2 v[EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int j = tr + e * TPL;
+        v[e] = (P2 || j < n) ? gp[j] : make_float2(0.f, 0.f);
+      }
+      if constexpr (P2) line_fft<(P2 ? L : 16), -1, 1>(v, tr, own, tw);
+      else line_fft_rt<-1, 1>(v, tr, own, rt, tw);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int j = tr + e * TPL;
+        if (P2 || j < n) own[lds_index<1>(j)] = v[e];
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < nr * n; idx += blockDim.x) {
+        const int r = idx / n, j = idx % n;
+        const int xr = (r & 1) ? xb : xa, yr = (r & 1) ? yb : ya;
+        rows[r * rowp + lds_index<1>(j)] = data[complex_index(g, mock * g.npair + r / 2, xr, yr, j)];
+      }
     }
     __syncthreads();
     if (side == 1 && self) continue;
@@ -595,19 +623,56 @@ __global__ __launch_bounds__(kMultiThreads) void k_multi_pairs(
   for (int i = threadIdx.x; i < n_bins; i += blockDim.x) dst[i] = hist[i];
 }
 
+template <int L, bool FFT>
+static hipError_t multi_pairs_t(const Geom& g, const Buffers& b, int n_dk, int n_bins,
+                                hipStream_t s) {
+  RtLine rt{};
+  int threads = kMultiThreads;
+  if constexpr (FFT) {
+    int tpl;
+    if constexpr (L == 0) {
+      if (!make_rt_line(g.nz, &rt)) return hipErrorInvalidValue;
+      tpl = rt.tpl;
+    } else {
+      tpl = LinePlan<L>::TPL;
+    }
+    threads = 2 * g.npair * tpl;  // one row of TPL threads per staged row
+  }
+  const size_t lds = sizeof(float2) * 2 * g.npair * (size_t)(g.n + g.n / 16 + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_multi_pairs<L, FFT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(sizeof(float2) * 2 * 4 * (1024 + 64 + 1)));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_multi_pairs<L, FFT>), dim3(kMultiBlocks, g.batch), dim3(threads), lds, s,
+                     b.grid, g, b.tw_nz, b.phase, b.inv_w2, n_dk, n_bins, b.partials, rt);
+  return hipGetLastError();
+}
+
+static hipError_t multi_pairs_dispatch(const Geom& g, const Buffers& b, bool do_fft, int n_dk,
+                                       int n_bins, hipStream_t s) {
+  if (!do_fft) return multi_pairs_t<0, false>(g, b, n_dk, n_bins, s);
+  switch ((g.nz & (g.nz - 1)) == 0 ? g.nz : 0) {
+    case 8: return multi_pairs_t<8, true>(g, b, n_dk, n_bins, s);
+    case 16: return multi_pairs_t<16, true>(g, b, n_dk, n_bins, s);
+    case 32: return multi_pairs_t<32, true>(g, b, n_dk, n_bins, s);
+    case 64: return multi_pairs_t<64, true>(g, b, n_dk, n_bins, s);
+    case 128: return multi_pairs_t<128, true>(g, b, n_dk, n_bins, s);
+    case 256: return multi_pairs_t<256, true>(g, b, n_dk, n_bins, s);
+    case 512: return multi_pairs_t<512, true>(g, b, n_dk, n_bins, s);
+    case 1024: return multi_pairs_t<1024, true>(g, b, n_dk, n_bins, s);
+    default: return multi_pairs_t<0, true>(g, b, n_dk, n_bins, s);
+  }
+}
+
 hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do_fft, int n_dk,
                         int n_bins, int subtract_shot, double* k, double* p, int64_t* nmodes,
                         hipStream_t s) {
   if (g.npair > 1) {
-    const size_t lds = sizeof(float2) * 2 * g.npair * (size_t)(g.n + g.n / 16 + 1);
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipFuncSetAttribute((const void*)k_multi_pairs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(sizeof(float2) * 2 * 4 * (1024 + 64 + 1)));
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(k_multi_pairs, dim3(kMultiBlocks, g.batch), dim3(kMultiThreads), lds, s,
-                       b.grid, g, b.phase, b.inv_w2, n_dk, n_bins, b.partials);
+    hipError_t e = multi_pairs_dispatch(g, b, do_fft, n_dk, n_bins, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_power_finalize, dim3(n_bins, g.batch), dim3(64), 0, s, b.partials,
                        kMultiBlocks, n_bins, b.mode_n, b.mode_k, b.norm, g.box, subtract_shot, k, p,
                        nmodes);

@@ -190,3 +190,36 @@ def test_paper_za_configuration_n480(torch):
     w = np.prod([kernels.window_1d(p, modes[:, a], n) for a in range(3)], axis=0)
     assert np.all(np.abs(got - ref) * w <= 1e-5 * np.abs(ref) * w + 1e-10), (got, ref)
     est.close()
+
+
+def test_largest_mixed_grid_n1000(torch):
+    """N = 1000 = 2^3 5^3: the longest run-time FFT plan (radix 8, 5, 5, 5 on
+    63 threads per line, 1008-thread column workgroups) and ragged 8-cell last
+    tiles.  All 500 mode counts, sampled cells of both grids and sampled
+    delta(m) against the C oracle loops."""
+    box, n, p = 1500.0, 1000, 4
+    pos = synth.zeldovich(200, box, 13, dtype=np.float32)
+    dpos = to_dev(torch, pos)
+    est = _est(n, box, p, True, maxp=len(pos))
+    k, pk, nm = est.power(dpos)
+    counts, ksum = native.mode_table(n, 1, n // 2)
+    assert np.array_equal(nm.cpu().numpy()[0], counts)
+    assert rel_err(k.cpu().numpy()[0], 2 * np.pi / box * ksum / counts) < 1e-10
+    assert np.all(np.isfinite(pk.cpu().numpy()))
+    cells = np.array([[0, 0, 0], [999, 999, 999], [992, 991, 999], [991, 992, 0], [7, 8, 995],
+                      [500, 499, 996], [996, 3, 992], [123, 456, 789]])
+    est.deposit(dpos)
+    for which, shift in ((1, 0.0), (2, 0.5)):
+        g = est.copy_grid(which)
+        got = g[cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy().astype(np.float64)
+        del g
+        ref = native.cell_values(pos, box, n, p, cells, shift)
+        assert np.all(np.abs(got - ref) <= 1e-6 + 1e-6 * np.abs(ref)), (which, got - ref)
+    est.transform()
+    modes = np.array([[1, 0, 0], [3, -2, 5], [500, 0, 0], [0, 500, 500], [-77, 321, 33],
+                      [250, -250, 125]])
+    got = est.sample_delta(modes).cpu().numpy()
+    ref = native.delta_modes(pos, box, n, p, True, modes)
+    w = np.prod([kernels.window_1d(p, modes[:, a], n) for a in range(3)], axis=0)
+    assert np.all(np.abs(got - ref) * w <= 1e-5 * np.abs(ref) * w + 1e-10), (got, ref)
+    est.close()
