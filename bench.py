@@ -410,6 +410,8 @@ def main():
                     help="headline launch shapes (0..47) instead of autotuning them")
     ap.add_argument("--bias", action="store_true",
                     help="only run the aliasing comparison against direct summation (Sec. 3.2)")
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "direct_sum", "paper_za_480", "variants"],
+                    default=None, help="only run one of the extra legs (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -436,6 +438,14 @@ def main():
 
     if args.bias:
         bias_experiment(torch, est_mod, synth)
+        return
+    if args.leg:
+        legs = {"batched": lambda: batched(args, torch, F, est_mod, synth),
+                "fwd_bwd": lambda: fwd_bwd(args, torch, F, est_mod, synth),
+                "direct_sum": lambda: direct_leg(args, torch, est_mod, synth),
+                "paper_za_480": lambda: paper_za_leg(args, torch, F, est_mod, synth),
+                "variants": lambda: variants_leg(args, torch, F, est_mod, synth)}
+        print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
         return
 
     head = headline(args, torch, F, est_mod, synth)

@@ -21,11 +21,14 @@ namespace fsest {
 //    cell can overflow;
 //  * narrow (32-bit): S = 2^F with F chosen on the device from the largest
 //    bucket count M of this deposit.  A cell only receives particles whose
-//    base cell lies in a 5^3 block, which meets at most 8 buckets, so its sum
-//    is at most B = 8 M units plus half a unit per contribution; F is the
-//    largest value with B (2^F + 1) < 2^32.  When F < 24 (coarser than the
-//    float32 resolution of a unit weight) the wide kernel runs
-//    instead (both are launched; the one not selected returns at once).
+//    base cell lies in a 5^3 block, which meets at most 8 buckets (27 for
+//    p = 5, 6), and one particle gives a cell at most w_max^3 (w_max the
+//    largest 1D weight of the order: 1, 1, 3/4, 2/3, 115/192, 11/20), so its
+//    sum is at most K (w_max^3 S + 1/2) units with K = 8 M (27 M) possible
+//    contributors; F is the largest value keeping that below 2^32.  When
+//    F < 24 (coarser than the float32 resolution of a unit weight) the wide
+//    kernel runs instead (both are launched; the one not selected returns
+//    at once).
 // Integer sums are exact, so deposits are bitwise reproducible.
 constexpr float kFixWide = 4294967040.0f;  // 2^32 - 2^8
 constexpr int kNarrowMinBits = 24;
@@ -35,9 +38,13 @@ constexpr int kNarrowMinBits = 24;
 // 3 for p = 5, 6.
 template <int P>
 __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
-  const double bound = (P <= 4 ? 8.0 : 27.0) * (double)(maxcount > 0 ? maxcount : 1);
+  // w_max^3 of the order, with a margin for the float32 rounding of the
+  // weight products
+  constexpr double wmax = P <= 2 ? 1.0 : (P == 3 ? 0.75 : (P == 4 ? 2.0 / 3.0 : (P == 5 ? 115.0 / 192.0 : 0.55)));
+  constexpr double w3 = wmax * wmax * wmax * (1.0 + 1e-6);
+  const double k = (P <= 4 ? 8.0 : 27.0) * (double)(maxcount > 0 ? maxcount : 1);
   int f = 0;
-  while (f < 31 && bound * (ldexp(1.0, f + 1) + 1.0) < 4294967295.0) ++f;
+  while (f < 31 && k * (w3 * ldexp(1.0, f + 1) + 0.5) < 4294967295.0) ++f;
   return f;
 }
 

@@ -185,10 +185,11 @@ def test_paper_za_configuration_n480(torch):
                       [180, -180, 0]])
     got = est.sample_delta(modes).cpu().numpy()
     ref = native.delta_modes(pos, box, n, p, True, modes)
-    # FP32 rounding relative to the field's norm, amplified by 1/W(m) (down to
-    # (2/pi)^8 at [0, 240, 240]): the bound is on |delta error| W(m) per mode
+    # FP32 rounding is relative to the field's norm and amplified by 1/W(m)
+    # (down to (2/pi)^8 at [0, 240, 240]): the bound is on |delta error| W(m)
+    # against the largest |delta W| sampled
     w = np.prod([kernels.window_1d(p, modes[:, a], n) for a in range(3)], axis=0)
-    assert np.all(np.abs(got - ref) * w <= 1e-5 * np.abs(ref) * w + 1e-10), (got, ref)
+    assert np.max(np.abs(got - ref) * w) <= 1e-5 * np.max(np.abs(ref) * w), (got, ref)
     est.close()
 
 
@@ -221,5 +222,5 @@ def test_largest_mixed_grid_n1000(torch):
     got = est.sample_delta(modes).cpu().numpy()
     ref = native.delta_modes(pos, box, n, p, True, modes)
     w = np.prod([kernels.window_1d(p, modes[:, a], n) for a in range(3)], axis=0)
-    assert np.all(np.abs(got - ref) * w <= 1e-5 * np.abs(ref) * w + 1e-10), (got, ref)
+    assert np.max(np.abs(got - ref) * w) <= 1e-5 * np.max(np.abs(ref) * w), (got, ref)
     est.close()
