@@ -37,10 +37,10 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
                     "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
-        "sha256_16": "8664c27fa7bfd38c",
+        "sha256_16": "361fb8a542496350",
         "workload": "pcs_il_n1024_za512",
-        "read_bytes": 2 * 4500106 * 1024,
-        "write_bytes": 8388608 * 1024,
+        "read_bytes": 2 * 4500301 * 1024,
+        "write_bytes": 8388613 * 1024,
     },
 }
 
