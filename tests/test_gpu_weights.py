@@ -180,3 +180,27 @@ def test_set_weights_needs_flag(torch):
         est.set_weights(torch.ones(10, dtype=torch.float32, device="cuda"))
     assert ei.value.status == F.EST_EINVAL
     est.close()
+
+
+def test_weighted_batch_with_empty_and_massless_sets(torch):
+    """An empty set and a set whose masses are all zero give NaN P(k) for that
+    set only; the others match the oracle."""
+    box, n = 400.0, 32
+    parts = [synth.uniform(3000, box, 50, np.float32), np.zeros((0, 3), np.float32),
+             synth.uniform(500, box, 51, np.float32), synth.zeldovich(12, box, 52, dtype=np.float32)]
+    masses = [_masses(3000, 53), np.zeros(0, np.float32), np.zeros(500, np.float32),
+              _masses(12 ** 3, 54)]
+    pos = np.concatenate(parts)
+    w = np.concatenate(masses).astype(np.float32)
+    offs = np.zeros(len(parts) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(q) for q in parts])
+    est = _est(n, box, 4, True, batch=len(parts), maxp=len(pos))
+    est.set_weights(to_dev(torch, w))
+    _, pk, _ = est.power(to_dev(torch, pos), offsets=to_dev(torch, offs))
+    pk = pk.cpu().numpy()
+    for i in (1, 2):
+        assert np.all(np.isnan(pk[i])), i
+    for i in (0, 3):
+        _, p0, _ = oracle.power(parts[i], box, n, 4, True, weights=masses[i])
+        assert rel_err(pk[i], p0) < P_TOL, i
+    est.close()
