@@ -9,7 +9,8 @@ particles.  Beside it (same JSON line): a batch of 64 uneven mocks on 128^3
 grids replayed as one HIP graph, forward + backward of a P(k) loss for
 128^3 particles on a 256^3 grid, the direct-summation engine, the
 paper's own Zel'dovich shape (360^3 particles on a 480^3 mixed-radix grid),
-and the extensions (order 6, eight interlaced grids, masses) at 512^3.
+the extensions (order 6, eight interlaced grids, masses) at 512^3, and
+orders 1..4 with and without interlacing at the headline size.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -222,6 +223,49 @@ def fwd_bwd(args, torch, F, est_mod, synth):
                        "n_particles": npart}}
 
 
+def orders_leg(args, torch, F, est_mod, synth):
+    """The headline workload (512^3 Zel'dovich particles, 1024^3 grid) with
+    every order p = 1..4, with and without interlacing (same step; launch
+    shapes of the headline's autotuned choice for PCS + interlacing)."""
+    n_side, box, n = 512, 2000.0, 1024
+    pos = torch.as_tensor(synth.zeldovich(n_side, box, 3, dtype=np.float32), device="cuda")
+    npart = pos.shape[0]
+    n_bins = n // 2
+    k = torch.empty((1, n_bins), dtype=torch.float64, device="cuda")
+    pk = torch.empty_like(k)
+    nm = torch.empty((1, n_bins), dtype=torch.int64, device="cuda")
+    out = {}
+    for order in (1, 2, 3, 4):
+        for il in (0, 1):
+            est = est_mod.Estimator(n, box, order, il, 1, npart)
+            est.set_launch(42)
+
+            def step():
+                F.estimator_deposit(est.h, pos, F.EST_F32, None, npart)
+                F.estimator_transform(est.h)
+                F.estimator_power(est.h, 1, n_bins, 0, k, pk, nm)
+
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            est.close()
+            torch.cuda.empty_cache()
+            name = "p%d_%s" % (order, "interlaced" if il else "single")
+            out[name] = {"value": round(npart * args.steps / dt / 1e6, 2), "unit": "Mparticles/s",
+                         "ms_per_step": round(1e3 * dt / args.steps, 4)}
+            log("orders %s: %.3f ms per step" % (name, 1e3 * dt / args.steps))
+    out["config"] = {"workload": "512^3 Zel'dovich particles, L=2000, 1024^3 grid, P(k) in k_f "
+                                 "shells to Nyquist, launch shapes 42", "n_particles": npart}
+    del pos
+    torch.cuda.empty_cache()
+    return out
+
+
 def paper_za_leg(args, torch, F, est_mod, synth):
     """The paper's Zel'dovich measurement shape (Sec. 3.3): 360^3 particles,
     L = 2400 Mpc/h, N_G = 480 (2^5 3 5: mixed-radix FFT), PCS + interlacing,
@@ -410,7 +454,8 @@ def main():
                     help="headline launch shapes (0..47) instead of autotuning them")
     ap.add_argument("--bias", action="store_true",
                     help="only run the aliasing comparison against direct summation (Sec. 3.2)")
-    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "direct_sum", "paper_za_480", "variants"],
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "direct_sum", "paper_za_480", "variants",
+                                      "orders_1024"],
                     default=None, help="only run one of the extra legs (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
@@ -444,7 +489,8 @@ def main():
                 "fwd_bwd": lambda: fwd_bwd(args, torch, F, est_mod, synth),
                 "direct_sum": lambda: direct_leg(args, torch, est_mod, synth),
                 "paper_za_480": lambda: paper_za_leg(args, torch, F, est_mod, synth),
-                "variants": lambda: variants_leg(args, torch, F, est_mod, synth)}
+                "variants": lambda: variants_leg(args, torch, F, est_mod, synth),
+                "orders_1024": lambda: orders_leg(args, torch, F, est_mod, synth)}
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
         return
 
@@ -456,6 +502,7 @@ def main():
         extra["direct_sum"] = direct_leg(args, torch, est_mod, synth)
         extra["paper_za_480"] = paper_za_leg(args, torch, F, est_mod, synth)
         extra["variants"] = variants_leg(args, torch, F, est_mod, synth)
+        extra["orders_1024"] = orders_leg(args, torch, F, est_mod, synth)
     out = {
         "metric": "Mparticles/s end-to-end P(k), PCS+interlace 1024^3 grid; fwd+bwd & batched vs plain",
         "value": round(head["value"], 2),
