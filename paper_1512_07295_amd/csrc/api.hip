@@ -98,14 +98,14 @@ struct ProfScope {
   ProfScope(est_ctx* hh, int l) : h(hh), label(l) {
     if (h->prof && !h->capturing) {
       a = prof_event(h);
-      if (a) hipEventRecord(a, h->stream);
+      if (a) (void)hipEventRecord(a, h->stream);
     }
   }
   ~ProfScope() {
     if (!a) return;
     hipEvent_t b = prof_event(h);
     if (!b) return;
-    hipEventRecord(b, h->stream);
+    (void)hipEventRecord(b, h->stream);
     h->rec[label].pending.emplace_back(a, b);
   }
 };
@@ -388,12 +388,12 @@ est_status estimator_destroy(est_handle h) {
   if (!h) return ok();
   for (auto& r : h->rec)
     for (auto& pr : r.pending) {
-      hipEventDestroy(pr.first);
-      hipEventDestroy(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
-  for (hipEvent_t e : h->pool) hipEventDestroy(e);
-  if (h->exec) hipGraphExecDestroy(h->exec);
-  if (h->graph) hipGraphDestroy(h->graph);
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
   delete h;
   return ok();
 }
@@ -583,8 +583,8 @@ est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtyp
   if ((st = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, subtract_shot, k, p, nmodes)))
     return st;
   if ((st = dev_err(hipStreamSynchronize(h->stream), "synchronize"))) return st;
-  if (h->exec) { hipGraphExecDestroy(h->exec); h->exec = nullptr; }
-  if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
+  if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
   hipStream_t cs;
   if ((st = dev_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return st;
   hipStream_t saved = h->stream;
@@ -600,14 +600,14 @@ est_status estimator_graph_capture(est_handle h, const void* pos, est_dtype dtyp
       h->graph = graph;
       st = dev_err(hipGraphInstantiate(&h->exec, graph, nullptr, nullptr, 0), "instantiate graph");
     } else if (graph) {
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
     }
   } else {
     st = dev_err(e, "begin capture");
   }
   h->stream = saved;
   h->capturing = false;
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   h->state = (st == EST_OK) ? forward_state(h) : kCreated;
   return st;
 }
@@ -674,20 +674,19 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
   int64_t* nm = (int64_t*)(pp + per);
   hipEvent_t e0, e1;
   if ((st = dev_err(hipEventCreate(&e0), "event"))) return st;
-  if ((st = dev_err(hipEventCreate(&e1), "event"))) { hipEventDestroy(e0); return st; }
+  if ((st = dev_err(hipEventCreate(&e1), "event"))) { (void)hipEventDestroy(e0); return st; }
   const Tune saved = h->tu;
   auto measure = [&](const Tune& t, float* ms) -> est_status {
     h->tu = t;
     est_status s2 = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
     if (s2) return s2;
-    hipEventRecord(e0, h->stream);
+    if ((s2 = dev_err(hipEventRecord(e0, h->stream), "event record"))) return s2;
     for (int it = 0; it < iters && s2 == EST_OK; ++it)
       s2 = run_forward(h, pos, dtype, offsets, n_total, n_dk, n_bins, 0, kk, pp, nm);
-    hipEventRecord(e1, h->stream);
     if (s2) return s2;
+    if ((s2 = dev_err(hipEventRecord(e1, h->stream), "event record"))) return s2;
     if ((s2 = dev_err(hipEventSynchronize(e1), "synchronize"))) return s2;
-    hipEventElapsedTime(ms, e0, e1);
-    return EST_OK;
+    return dev_err(hipEventElapsedTime(ms, e0, e1), "elapsed time");
   };
   int idx[5] = {1, 1, 0, 1, 1};  // start from the defaults
   auto make = [&](const int* id) { return tune_from_index(id); };
@@ -707,8 +706,8 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
     }
     idx[p] = best_v;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   h->tu = (st == EST_OK) ? make(idx) : saved;
   h->state = (st == EST_OK) ? forward_state(h) : kCreated;
   if (st == EST_OK && choice) *choice = (((idx[0] * 3 + idx[1]) * 2 + idx[2]) * 2 + idx[3]) * 2 + idx[4];

@@ -72,7 +72,7 @@ static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int6
   const size_t lds = sizeof(float2) * (size_t)L * C;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_fft_cols<L, DIR, C>,
+    (void)hipFuncSetAttribute((const void*)k_fft_cols<L, DIR, C>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr_set = true;
   }
@@ -175,7 +175,7 @@ static hipError_t cols_rt(int L, float2* data, int64_t elem_stride, int64_t inne
   const size_t lds = sizeof(float2) * (size_t)L * C;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_fft_cols_rt<DIR, C>,
+    (void)hipFuncSetAttribute((const void*)k_fft_cols_rt<DIR, C>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * 1024 * C));
     attr_set = true;
   }

@@ -478,6 +478,7 @@ static hipError_t pairs_dispatch(const Geom& g, const Buffers& b, int nblk, int 
     FSEST_PAIRS_CASE(0)
   }
 #undef FSEST_PAIRS_CASE
+  return hipErrorInvalidValue;
 }
 
 static int pair_blocks(const Geom& g, const Tune& tu) {
@@ -641,7 +642,7 @@ static hipError_t multi_pairs_t(const Geom& g, const Buffers& b, int n_dk, int n
   const size_t lds = sizeof(float2) * 2 * g.npair * (size_t)(g.n + g.n / 16 + 1);
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_multi_pairs<L, FFT>,
+    (void)hipFuncSetAttribute((const void*)k_multi_pairs<L, FFT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(sizeof(float2) * 2 * 4 * (1024 + 64 + 1)));
     attr_set = true;
@@ -1170,7 +1171,7 @@ hipError_t launch_triple_sums(int64_t npts, const float2* ipairs, const float2* 
   const size_t lds = sizeof(float) * 2 * (size_t)n_bins * (kTriXC + 1);
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)k_triple, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_triple, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
   hipLaunchKernelGGL(k_triple, dim3(tb, n_xr), dim3(256), lds, s, npts, ipairs, jpairs, n_bins, tri,
