@@ -245,8 +245,10 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // a separate instantiation so that the equal-mass kernel keeps its registers
 // IL: 0 one grid; 1 the interlaced pair (masks 0 and 7); 2 a pair of grids
 // with run-time masks (mask_a, mask_b) written to slab q of each set
-template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT>
-__global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
+// CAP: registers capped at 64 (8 waves per SIMD) so that two 1024-thread
+// workgroups share a CU (two_groups_per_cu)
+template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT, bool CAP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 1))) void k_deposit(const TP* __restrict__ sorted,
                                                   const uint64_t* __restrict__ cells,
                                                   const uint32_t* __restrict__ boff,
                                                   const uint32_t* __restrict__ bcnt, float* grid,
@@ -584,20 +586,51 @@ __global__ __launch_bounds__(1024) void k_deposit(const TP* __restrict__ sorted,
   }
 }
 
+// A workgroup waits at a barrier several times per tile, and with one
+// workgroup per CU the whole CU waits with it.  The 32-bit pair kernel's LDS
+// (74.9 KB) leaves room for two workgroups per CU; those of 1024 threads need
+// 8 waves per SIMD, i.e. at most 64 VGPRs.  The instantiations listed here
+// fit in 64 without scratch (the others spill and keep their registers):
+// the interlaced pair, float32 positions, equal masses, orders 1 and 2, and
+// order 4 with a tile smaller than the grid.  Measured at 1024^3 with 2^27
+// particles (PCS): 11.8 ms with two 512-thread workgroups per CU, 10.8 ms
+// with two of 1024.
+template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT>
+__host__ __device__ constexpr bool two_groups_per_cu() {
+  return std::is_same<TP, float>::value && !WIDE && IL == 1 && !WT &&
+         (P <= 2 || (P == 4 && WRAP != kPeriodic));
+}
+
+// threads: 256, 512 or 1024 per deposit workgroup, or 0 for the kernel's
+// own choice (1024 where two_groups_per_cu, else 512)
 template <int P, int IL, typename TP, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
                            const float* sw, int q, int ma, int mb, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
-  if (narrow)
-    hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT>), dim3((unsigned)ntiles), dim3(threads),
-                       0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0,
-                       0, xcd ? 1 : 0, sw, q, ma, mb);
+  constexpr bool kTwo = two_groups_per_cu<P, IL, TP, false, WRAP, WT>();
+  if (narrow) {
+    const int tn = threads ? threads : (kTwo ? 1024 : 512);
+    bool capped = false;
+    if constexpr (kTwo) {
+      if (tn == 1024) {
+        hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT, true>), dim3((unsigned)ntiles),
+                           dim3(tn), 0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt,
+                           (float*)b.grid, g, b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+        capped = true;
+      }
+    }
+    if (!capped)
+      hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT, false>), dim3((unsigned)ntiles),
+                         dim3(tn), 0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt,
+                         (float*)b.grid, g, b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+  }
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
   const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
-  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, WRAP, WT>), dim3(wblocks), dim3(threads), 0, s,
+  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, WRAP, WT, false>), dim3(wblocks),
+                     dim3(threads ? threads : 512), 0, s,
                      (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats,
                      narrow ? 0 : 1, 1, 0, sw, q, ma, mb);
 }
@@ -648,7 +681,7 @@ static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, co
 hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
                           bool weighted, hipStream_t s) {
   int threads = tu.dep_threads;
-  if (threads != 256 && threads != 512 && threads != 1024) threads = 1024;
+  if (threads != 256 && threads != 512 && threads != 1024) threads = 0;  // per kernel
   const float* sw = weighted ? b.sw : nullptr;
   switch (g.order) {
     case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, sw, s); break;

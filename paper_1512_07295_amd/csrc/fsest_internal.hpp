@@ -103,7 +103,7 @@ struct Buffers {
 struct Tune {
   int cols_c = 16;        // lines per workgroup of the strided FFT passes
   int bin_blocks = 1024;  // reduction workgroups per set in the fused P(k) pass
-  int dep_threads = 512;  // threads per deposit workgroup
+  int dep_threads = 0;    // threads per deposit workgroup (0: chosen per kernel)
   int dep_narrow = 1;     // 32-bit fixed point when provably safe (else 64-bit)
   int dep_xcd = 1;        // consecutive deposit tiles on one XCD (shared L2)
 };
