@@ -233,8 +233,9 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // grid at a time.  Per tile: (1) the particles of the buckets that can
 // reach the tile are scanned in rounds of blockDim items; each grid whose
 // stencil reaches the tile becomes a work item in an LDS list and counts
-// towards its bank class; (2) whenever the list might overflow, it is
-// counting-sorted by class and deposited with LDS integer atomics, lane l of
+// towards its bank class; (2) before a round whose items would overflow the
+// list, and after the last round, the list is counting-sorted by class and
+// deposited with LDS integer atomics, lane l of
 // virtual wave r taking sorted item r + l * W (W = virtual waves in the
 // flush); (3) the finished tile is scaled back to float and written once.
 // `dynamic`: tiles are taken from a global counter (stats[1], zeroed with
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   __shared__ int wave_cnt[MAXW];
   __shared__ int cls_cnt[64];
   __shared__ int cls_cur[64];
-  __shared__ int fill, next_tile;
+  __shared__ int next_tile;
   uint32_t* item_j = smem;
   uint8_t* item_meta = reinterpret_cast<uint8_t*>(smem + kItemCap);
   uint16_t* item_order = reinterpret_cast<uint16_t*>(smem + kItemCap + kItemCap / 4);
@@ -308,7 +309,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
 
     if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) fill = 0;
 
     // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
     int cnt = T / kBucket + 2;
@@ -368,9 +368,74 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     const uint32_t total = rg.pref[rg.count];
     const int nr = rg.count;
 
+    // Sorts the m listed items by bank class and deposits them; every
+    // thread calls it with the same m, and it ends with a barrier.
+    auto deposit_list = [&](int m) __attribute__((always_inline)) {
+      if (wave == 0) {
+        const int c = cls_cnt[lane];
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int t = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += t;
+        }
+        cls_cur[lane] = incl - c;
+        cls_cnt[lane] = 0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < m; e += nthreads)
+        item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
+      __syncthreads();
+      // lane l of virtual wave r takes item r + l W; each item's position
+      // is loaded one iteration ahead
+      const int W = (m + 63) >> 6;
+      const int vend = 64 * W;
+      int e_cur = -1;
+      TP px = 0, py = 0, pz = 0;
+      {
+        const int v = threadIdx.x;
+        const int p = (v >> 6) + (v & 63) * W;
+        if (v < vend && p < m) {
+          e_cur = item_order[p];
+          const int64_t jq = item_j[e_cur];
+          px = sorted[3 * jq + 0];
+          py = sorted[3 * jq + 1];
+          pz = sorted[3 * jq + 2];
+        }
+      }
+      for (int v = threadIdx.x; v < vend; v += nthreads) {
+        const int vn = v + nthreads;
+        const int pn = (vn >> 6) + (vn & 63) * W;
+        int e_nxt = -1;
+        TP nx = 0, ny = 0, nz = 0;
+        if (vn < vend && pn < m) {
+          e_nxt = item_order[pn];
+          const int64_t jq = item_j[e_nxt];
+          nx = sorted[3 * jq + 0];
+          ny = sorted[3 * jq + 1];
+          nz = sorted[3 * jq + 2];
+        }
+        if (e_cur >= 0) {
+          float sc = scale;
+          if constexpr (WT) sc *= sw[item_j[e_cur]];
+          const int gi = item_meta[e_cur] >> 6;
+          const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
+          deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz, gi, g, t0x, t0y, t0z, sm,
+                                    sc, mk);
+        }
+        e_cur = e_nxt;
+        px = nx;
+        py = ny;
+        pz = nz;
+      }
+      __syncthreads();
+    };
+    int fill = 0;  // items in the list (the same value in every thread)
+
     // rounds of blockDim candidates; the cell records of kPre rounds are
-    // loaded together so that their latencies overlap
-    constexpr int kPre = 4;
+    // loaded together so that their latencies overlap (one round where the
+    // registers are capped: the other workgroup on the CU covers the wait)
+    constexpr int kPre = CAP ? 1 : 4;
     constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
     for (uint32_t rb = 0; rb < total; rb += kPre * nthreads) {
       uint32_t jj[kPre];
@@ -441,9 +506,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           before += (w < wave) ? c : 0;
           tot += c;
         }
-        const int f0 = fill;
+        // (2) the list is deposited first if this round's items would not fit
+        if (fill + tot > kItemCap) {
+          deposit_list(fill);
+          fill = 0;
+        }
         const unsigned long long below = (1ull << lane) - 1ull;
-        int pos = f0 + before;
+        int pos = fill + before;
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
           if (ok[gi]) {
@@ -455,76 +524,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           pos += __popcll(bal[gi]);
         }
         __syncthreads();
-        const int m = f0 + tot;
-        const bool last = r0 + nthreads >= total;
-        if (m + NG * nthreads > kItemCap || last) {
-          // (2) sort the items by bank class, then deposit them
-          if (wave == 0) {
-            const int c = cls_cnt[lane];
-            int incl = c;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-              const int t = __shfl_up(incl, o, 64);
-              if (lane >= o) incl += t;
-            }
-            cls_cur[lane] = incl - c;
-            cls_cnt[lane] = 0;
-          }
-          __syncthreads();
-          for (int e = threadIdx.x; e < m; e += nthreads)
-            item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
-          __syncthreads();
-          // lane l of virtual wave r takes item r + l W; each item's position
-          // is loaded one iteration ahead
-          const int W = (m + 63) >> 6;
-          const int vend = 64 * W;
-          int e_cur = -1;
-          TP px = 0, py = 0, pz = 0;
-          {
-            const int v = threadIdx.x;
-            const int p = (v >> 6) + (v & 63) * W;
-            if (v < vend && p < m) {
-              e_cur = item_order[p];
-              const int64_t jq = item_j[e_cur];
-              px = sorted[3 * jq + 0];
-              py = sorted[3 * jq + 1];
-              pz = sorted[3 * jq + 2];
-            }
-          }
-          for (int v = threadIdx.x; v < vend; v += nthreads) {
-            const int vn = v + nthreads;
-            const int pn = (vn >> 6) + (vn & 63) * W;
-            int e_nxt = -1;
-            TP nx = 0, ny = 0, nz = 0;
-            if (vn < vend && pn < m) {
-              e_nxt = item_order[pn];
-              const int64_t jq = item_j[e_nxt];
-              nx = sorted[3 * jq + 0];
-              ny = sorted[3 * jq + 1];
-              nz = sorted[3 * jq + 2];
-            }
-            if (e_cur >= 0) {
-              float sc = scale;
-              if constexpr (WT) sc *= sw[item_j[e_cur]];
-              const int gi = item_meta[e_cur] >> 6;
-              const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-              deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz, gi, g, t0x, t0y, t0z,
-                                        sm, sc, mk);
-            }
-            e_cur = e_nxt;
-            px = nx;
-            py = ny;
-            pz = nz;
-          }
-          __syncthreads();
-          if (threadIdx.x == 0) fill = 0;
-        } else if (threadIdx.x == 0) {
-          fill = m;
+        fill += tot;
+        if (r0 + nthreads >= total) {  // the last round: deposit what is left
+          deposit_list(fill);
+          fill = 0;
         }
-        __syncthreads();
       }
     }
-
     // (3) write the tile (halo cells dropped, or folded back when periodic)
     const int slab = (IL == 2) ? mock * g.npair + q : mock;
     if constexpr (WRAP != kPeriodic) {
