@@ -284,6 +284,25 @@ def test_clustered_input_uses_wide_fixed_point(torch, p):
         est.close()
 
 
+@pytest.mark.parametrize("choice", [2, 7, 4, None])
+def test_dense_tiles_deposit_their_item_list_several_times(torch, choice):
+    """About 2 x 6300 work items per 16^3 tile, several times the item list:
+    the list is deposited whenever a round of candidates would overflow it and
+    after the last round.  Choices: 512-thread workgroups (2), 1024-thread
+    workgroups with registers capped for two per CU (7), the 64-bit kernel
+    (4), the default shapes (None); the 32-bit format holds here (F = 24)."""
+    box, n = 100.0, 32
+    pos = synth.uniform(30000, box, 12, np.float32)
+    est = _est(torch, n, box, 4, True, maxp=len(pos))
+    if choice is not None:
+        est.set_launch(choice)
+    est.deposit(to_dev(torch, pos))
+    r1, r2 = assign.deposit(pos, box, n, 4, True)
+    assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+    assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+    est.close()
+
+
 def test_deposit_is_bitwise_reproducible(torch):
     box, n = 200.0, 32
     pos = to_dev(torch, synth.uniform(50000, box, 6, np.float32))
