@@ -358,7 +358,7 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
 // bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
 // the deposit splits its bucket runs at super-bucket boundaries.
 constexpr int kSortThreads = 1024;
-constexpr int kSortBatch = 1;  // particles per thread handled together (loads in flight together)
+constexpr int kSortBatch = 4;  // particles per thread whose loads are in flight together
 
 __device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
                                                  int& bx, int& by, int& bz) {
