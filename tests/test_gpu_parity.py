@@ -303,6 +303,27 @@ def test_dense_tiles_deposit_their_item_list_several_times(torch, choice):
     est.close()
 
 
+@pytest.mark.parametrize("n,p", [(16, 1), (16, 2), (32, 1), (32, 2), (32, 4), (24, 1), (24, 2),
+                                 (40, 4)])
+@pytest.mark.parametrize("choice", [None, 42])
+def test_register_capped_deposit_kernels(torch, n, p, choice):
+    """The interlaced-pair kernels built for two 1024-thread workgroups per CU
+    (orders 1, 2 and 4; the grid as one tile, a power-of-two grid, any other
+    N) at their default shapes and with 512-thread workgroups (42), which runs
+    the uncapped build of the same kernel.  14 particles per 4^3-cell bucket
+    on average keep the 32-bit format (F >= 24 for these seeds)."""
+    box = 400.0
+    pos = synth.uniform(14 * (n // 4) ** 3, box, 200 + n + p, np.float32)
+    est = _est(torch, n, box, p, True, maxp=len(pos))
+    if choice is not None:
+        est.set_launch(choice)
+    est.deposit(to_dev(torch, pos))
+    r1, r2 = assign.deposit(pos, box, n, p, True)
+    assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+    assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+    est.close()
+
+
 def test_deposit_is_bitwise_reproducible(torch):
     box, n = 200.0, 32
     pos = to_dev(torch, synth.uniform(50000, box, 6, np.float32))
