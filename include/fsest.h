@@ -203,7 +203,9 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype,
 
 /* Set the launch shapes directly from an index returned by
  * estimator_autotune (e.g. one cached from an earlier run).  EINVAL outside
- * [0, 48). */
+ * [0, 48).  Until a handle's shapes are set or tuned, its deposit workgroup
+ * size is chosen per kernel (1024 threads where two such workgroups fit on
+ * a CU, else 512). */
 est_status estimator_set_launch(est_handle h, int32_t choice);
 
 /* Per-particle masses (the paper takes equal masses for simplicity,
