@@ -38,10 +38,10 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
                     "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
-        "sha256_16": "89744c47eb605d39",
+        "sha256_16": "fcf6e98a7ee68a9e",
         "workload": "pcs_il_n1024_za512",
-        "read_bytes": 2 * 4500014 * 1024,
-        "write_bytes": 8388609 * 1024,
+        "read_bytes": 2 * 4500062 * 1024,
+        "write_bytes": 8388612 * 1024,
     },
 }
 

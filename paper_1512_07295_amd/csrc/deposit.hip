@@ -259,11 +259,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
                                                   int mask_b) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int NG = IL ? 2 : 1;
-  constexpr int MAXW = 16;  // waves per workgroup (1024 threads)
   constexpr int kWords = acc_first_word<AT>() + NG * kGridWords * (int)(sizeof(AT) / 4);
   __shared__ __align__(16) uint32_t smem[kWords];
   __shared__ DepRanges rg;
-  __shared__ int wave_cnt[MAXW];
+  __shared__ int round_cnt[2];
   __shared__ int cls_cnt[64];
   __shared__ int cls_cur[64];
   __shared__ int next_tile;
@@ -290,7 +289,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   const int64_t ntiles = (int64_t)g.batch * tiles_per_set;
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwaves = (nthreads + 63) >> 6;
   const bool remap = xcd && !dynamic && (int64_t)gridDim.x == ntiles && (ntiles & 7) == 0;
 
   int64_t b = blockIdx.x;
@@ -309,6 +307,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
 
     if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 2) round_cnt[threadIdx.x] = 0;
 
     // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
     int cnt = T / kBucket + 2;
@@ -431,6 +430,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
       __syncthreads();
     };
     int fill = 0;  // items in the list (the same value in every thread)
+    int rpar = 0;  // which of the two round counters this round uses
 
     // rounds of blockDim candidates; the cell records of kPre rounds are
     // loaded together so that their latencies overlap (one round where the
@@ -498,14 +498,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           bal[gi] = __ballot(ok[gi]);
           mine += __popcll(bal[gi]);
         }
-        if (lane == 0) wave_cnt[wave] = mine;
+        // each wave reserves its slice of this round's items (slices in any
+        // order: the integer sums do not depend on it)
+        int before = 0;
+        if (lane == 0) before = atomicAdd(&round_cnt[rpar], mine);
+        before = __builtin_amdgcn_readfirstlane(before);
         __syncthreads();
-        int before = 0, tot = 0;
-        for (int w = 0; w < nwaves; ++w) {
-          const int c = wave_cnt[w];
-          before += (w < wave) ? c : 0;
-          tot += c;
-        }
+        const int tot = round_cnt[rpar];
+        // the other counter was last read before the previous round's
+        // insertion barrier and is next used after this round's
+        if (threadIdx.x == 0) round_cnt[rpar ^ 1] = 0;
+        rpar ^= 1;
         // (2) the list is deposited first if this round's items would not fit
         if (fill + tot > kItemCap) {
           deposit_list(fill);
