@@ -14,7 +14,8 @@
  * oracle (plus 1/2 for the interlaced grid), so the cell choices are the
  * oracle's own.  The two sampling loops split the particles over OpenMP
  * threads; each thread sums its share and the shares are added in thread
- * order.
+ * order.  oracle_deposit_slabs splits the grid's x planes instead, which
+ * keeps the serial loop's order of terms in every cell.
  */
 #include <math.h>
 #include <omp.h>
@@ -78,6 +79,47 @@ void oracle_deposit(const double* u, int64_t n_p, int64_t n, int p, double* rho)
       for (int b = 0; b < p; ++b)
         for (int c = 0; c < p; ++c)
           rho[(cx[a] * n + cy[b]) * n + cz[c]] += wx[a] * wy[b] * wz[c];
+  }
+}
+
+/* first cell of the p-point stencil of u (not reduced mod n), as in stencil() */
+static int64_t first_cell(double u, int p) {
+  const double first = (p % 2 == 0) ? floor(u) - (p / 2 - 1) : floor(u + 0.5) - (p - 1) / 2;
+  return (int64_t)first;
+}
+
+/* The same sum as oracle_deposit with the x planes split among OpenMP
+ * threads: thread t owns planes [n t / T, n (t+1) / T) and walks all
+ * particles in order, adding only the stencil cells that lie in its planes.
+ * Every cell therefore receives its terms in the serial loop's order with the
+ * serial loop's arithmetic, so the grid equals oracle_deposit's bit for bit. */
+void oracle_deposit_slabs(const double* u, int64_t n_p, int64_t n, int p, double* rho) {
+#pragma omp parallel
+  {
+    const int64_t nt = omp_get_num_threads(), t = omp_get_thread_num();
+    const int64_t x0 = n * t / nt, x1 = n * (t + 1) / nt;
+    int64_t cx[MAXP], cy[MAXP], cz[MAXP];
+    double wx[MAXP], wy[MAXP], wz[MAXP];
+    for (int64_t j = 0; j < n_p; ++j) {
+      /* cheap test first: does the x stencil meet this thread's planes? */
+      const int64_t f = first_cell(u[3 * j + 0], p);
+      int hit = 0;
+      for (int a = 0; a < p; ++a) {
+        int64_t c = (f + a) % n;
+        if (c < 0) c += n;
+        hit |= (c >= x0 && c < x1);
+      }
+      if (!hit) continue;
+      stencil(u[3 * j + 0], p, n, cx, wx);
+      stencil(u[3 * j + 1], p, n, cy, wy);
+      stencil(u[3 * j + 2], p, n, cz, wz);
+      for (int a = 0; a < p; ++a) {
+        if (cx[a] < x0 || cx[a] >= x1) continue;
+        for (int b = 0; b < p; ++b)
+          for (int c = 0; c < p; ++c)
+            rho[(cx[a] * n + cy[b]) * n + cz[c]] += wx[a] * wy[b] * wz[c];
+      }
+    }
   }
 }
 

@@ -38,6 +38,8 @@ def _load():
         d, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         lib.oracle_deposit.argtypes = [d, i64, i64, i32, d]
         lib.oracle_deposit.restype = None
+        lib.oracle_deposit_slabs.argtypes = [d, i64, i64, i32, d]
+        lib.oracle_deposit_slabs.restype = None
         lib.oracle_footprint_dft.argtypes = [d, i64, i64, i32, d, i64, d, d]
         lib.oracle_footprint_dft.restype = None
         lib.oracle_cell_values.argtypes = [d, i64, i64, i32, d, i64, d]
@@ -58,6 +60,21 @@ def deposit(pos, box, n, p, shift=0.0):
     rho = np.zeros(n * n * n, dtype=np.float64)
     _load().oracle_deposit(u.ctypes.data, len(u), n, p, rho.ctypes.data)
     return rho.reshape(n, n, n)
+
+
+def deposit_u_slabs(u, n, p):
+    """Grid (N, N, N) float64 of particles at grid coordinates u (n_p, 3),
+    deposited by the x-plane-parallel C loop (equal to ``deposit`` bit for
+    bit)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    rho = np.zeros(n * n * n, dtype=np.float64)
+    _load().oracle_deposit_slabs(u.ctypes.data, len(u), n, p, rho.ctypes.data)
+    return rho.reshape(n, n, n)
+
+
+def deposit_slabs(pos, box, n, p, shift=0.0):
+    """Same as ``deposit`` through the x-plane-parallel C loop."""
+    return deposit_u_slabs(_u(pos, box, n, shift), n, p)
 
 
 def footprint_dft(pos, box, n, p, modes, shift=0.0):
@@ -137,3 +154,51 @@ def power(pos, box, n, p, interlace_on, n_dk=1, n_bins=None):
         n_bins = spectrum.max_bins(n, n_dk)
     delta, _ = delta_half(pos, box, n, p, interlace_on)
     return spectrum.bin_power(delta, box, n, n_dk, n_bins)
+
+
+def power_large(pos, box, n, p, interlace_on, n_dk=1, n_bins=None, planes=16, band=0):
+    """The oracle P(k) (``spectrum.power``: equal masses, raw P) for grids too
+    large for the all-at-once numpy form: both deposits by the x-plane
+    parallel C loop, one grid at a time (F_1 = FFT(rho_1) is kept while
+    rho_2 is deposited and transformed), then delta = C / (N_P W) formed and
+    binned ``planes`` x planes at a time with the same spectrum functions.
+
+    Returns (k_b, P_b, N_b) and, when ``band`` > 0, delta at every mode with
+    all |m_a| <= band as a dense complex array d[m_x + band, m_y + band, m_z]
+    (m_z = 0 .. band) for brute-force checks on the low shells."""
+    from . import spectrum
+    if int(interlace_on) not in (0, 1):
+        raise ValueError("power_large handles one grid or the interlaced pair")
+    if n_bins is None:
+        n_bins = spectrum.max_bins(n, n_dk)
+    pos = np.asarray(pos)
+    n_p = float(len(pos))
+    u = _u(pos, box, n, 0.0)
+    f1 = spectrum.fft_grid(deposit_u_slabs(u, n, p))
+    f2 = None
+    if interlace_on:
+        u += 0.5  # the grid sampled at u + 1/2
+        f2 = spectrum.fft_grid(deposit_u_slabs(u, n, p))
+    del u
+    sums = np.zeros(n_bins)
+    d_band = np.zeros((2 * band + 1, 2 * band + 1, band + 1), dtype=np.complex128) if band else None
+    for x0 in range(0, n, planes):
+        x1 = min(n, x0 + planes)
+        c = spectrum.interlace(f1[x0:x1], f2[x0:x1], n, x0) if interlace_on else f1[x0:x1]
+        delta = c / (n_p * spectrum.window(n, p, x0, x1))
+        sums += spectrum.shell_sums(delta, box, n, n_dk, n_bins, x0)
+        if band:
+            for ix in range(x0, x1):
+                mx = ix if ix <= n // 2 else ix - n
+                if abs(mx) > band:
+                    continue
+                for my in range(-band, band + 1):
+                    d_band[mx + band, my + band, :] = delta[ix - x0, my % n, :band + 1]
+    counts, ksum = mode_table(n, n_dk, n_bins)
+    kf = 2.0 * np.pi / box
+    with np.errstate(invalid="ignore", divide="ignore"):
+        k = kf * ksum / counts
+        pk = sums / counts
+    if band:
+        return k, pk, counts, d_band
+    return k, pk, counts

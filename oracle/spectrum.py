@@ -51,9 +51,10 @@ def signed_index(n):
     return np.where(i <= n // 2, i, i - n)
 
 
-def half_axes(n):
-    """(m_x, m_y, m_z) broadcastable arrays for the rfftn half spectrum."""
-    mx = signed_index(n)[:, None, None]
+def half_axes(n, x0=0, x1=None):
+    """(m_x, m_y, m_z) broadcastable arrays for the rfftn half spectrum
+    (m_x of the x planes x0 .. x1-1 only, all of them by default)."""
+    mx = signed_index(n)[x0:(n if x1 is None else x1), None, None]
     my = signed_index(n)[None, :, None]
     mz = np.arange(n // 2 + 1, dtype=np.int64)[None, None, :]
     return mx, my, mz
@@ -80,9 +81,11 @@ def mask_shift(mask):
     return 0.5 * np.array([(mask >> a) & 1 for a in range(3)], dtype=np.float64)
 
 
-def combine(fs, masks, n):
-    """C = (1/G) sum_j F_j exp(+i pi (sum of m_a over the shifted axes of j) / N)."""
-    mx, my, mz = half_axes(n)
+def combine(fs, masks, n, x0=0):
+    """C = (1/G) sum_j F_j exp(+i pi (sum of m_a over the shifted axes of j) / N).
+
+    The F_j may hold only the x planes x0, x0 + 1, ... of the half spectrum."""
+    mx, my, mz = half_axes(n, x0, x0 + fs[0].shape[0])
     m = (mx, my, mz)
     c = 0.0
     for f, mk in zip(fs, masks):
@@ -91,16 +94,19 @@ def combine(fs, masks, n):
     return c / len(fs)
 
 
-def interlace(f1, f2, n):
-    """C = (F_1 + exp(i pi (m_x+m_y+m_z)/N) F_2) / 2  (eq. intdelta)."""
-    mx, my, mz = half_axes(n)
+def interlace(f1, f2, n, x0=0):
+    """C = (F_1 + exp(i pi (m_x+m_y+m_z)/N) F_2) / 2  (eq. intdelta).
+
+    f1, f2 may hold only the x planes x0, x0 + 1, ... of the half spectrum."""
+    mx, my, mz = half_axes(n, x0, x0 + f1.shape[0])
     phase = np.exp(1j * np.pi * (mx + my + mz).astype(np.float64) / n)
     return 0.5 * (f1 + phase * f2)
 
 
-def window(n, p):
-    """W(m) on the half spectrum (eq. intkerFT, three axes multiplied)."""
-    mx, my, mz = half_axes(n)
+def window(n, p, x0=0, x1=None):
+    """W(m) on the half spectrum (eq. intkerFT, three axes multiplied), on
+    the x planes x0 .. x1-1 (all by default)."""
+    mx, my, mz = half_axes(n, x0, x1)
     return window_1d(p, mx, n) * window_1d(p, my, n) * window_1d(p, mz, n)
 
 
@@ -193,16 +199,24 @@ def delta_half(pos, box, n, p, interlace_on, workers=None, weights=None):
     return c / (n_p * window(n, p)), n_p
 
 
-def bin_power(delta, box, n, n_dk, n_bins):
-    """(k_b, P_b raw, N_b) from a half-spectrum delta (step 4)."""
-    mx, my, mz = half_axes(n)
+def shell_sums(delta, box, n, n_dk, n_bins, x0=0):
+    """Per shell, sum over its modes of w V |delta(m)|^2 (step 4 before the
+    division by N_b), for a half spectrum ``delta`` that holds the x planes
+    x0, x0 + 1, ... (all of them by default).  Shells are disjoint, so the sums
+    of consecutive plane ranges add up to those of the whole half spectrum."""
+    mx, my, mz = half_axes(n, x0, x0 + delta.shape[0])
     m2 = mx * mx + my * my + mz * mz
     b = np.broadcast_to(bin_index(m2, n_dk), m2.shape)
     w = np.broadcast_to(half_weights(n), m2.shape).astype(np.float64)
     sel = (m2 > 0) & (b >= 1) & (b <= n_bins)
     vol = float(box) ** 3
     pk_mode = vol * np.abs(delta) ** 2
-    s = np.bincount(b[sel], weights=(w * pk_mode)[sel], minlength=n_bins + 1)[1:]
+    return np.bincount(b[sel], weights=(w * pk_mode)[sel], minlength=n_bins + 1)[1:]
+
+
+def bin_power(delta, box, n, n_dk, n_bins):
+    """(k_b, P_b raw, N_b) from a half-spectrum delta (step 4)."""
+    s = shell_sums(delta, box, n, n_dk, n_bins)
     counts, ksum = mode_table(n, n_dk, n_bins)
     kf = 2.0 * np.pi / box
     with np.errstate(invalid="ignore", divide="ignore"):

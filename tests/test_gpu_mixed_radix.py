@@ -161,7 +161,8 @@ def test_paper_za_configuration_n480(torch):
     """The paper's Zel'dovich measurement shape: 360^3 particles, L = 2400,
     N_G = 480, PCS + interlacing.  Mode counts and mean k of all 240 shells
     (exact / 1e-10), both grids at sampled cells (tile edges, the periodic
-    wrap), delta(m) at sampled modes (1e-5) and P(k) finite."""
+    wrap), delta(m) at sampled modes (1e-5) and P(k) of all 240 shells
+    against the full-size FP64 oracle (1e-5)."""
     box, n, p = 2400.0, 480, 4
     pos = synth.zeldovich(360, box, 11, dtype=np.float32)
     dpos = to_dev(torch, pos)
@@ -170,7 +171,9 @@ def test_paper_za_configuration_n480(torch):
     counts, ksum = native.mode_table(n, 1, n // 2)
     assert np.array_equal(nm.cpu().numpy()[0], counts)
     assert rel_err(k.cpu().numpy()[0], 2 * np.pi / box * ksum / counts) < 1e-10
-    assert np.all(np.isfinite(pk.cpu().numpy()))
+    _, p0, n0 = native.power_large(pos, box, n, p, True, 1, n // 2)
+    assert np.array_equal(n0, counts)
+    assert rel_err(pk.cpu().numpy()[0], p0) < 1e-5
     cells = np.array([[0, 0, 0], [479, 479, 479], [463, 464, 479], [464, 463, 0], [15, 16, 475],
                       [240, 239, 471], [476, 3, 468], [100, 200, 300]])
     est.deposit(dpos)
@@ -196,8 +199,9 @@ def test_paper_za_configuration_n480(torch):
 def test_largest_mixed_grid_n1000(torch):
     """N = 1000 = 2^3 5^3: the longest run-time FFT plan (radix 8, 5, 5, 5 on
     63 threads per line, 1008-thread column workgroups) and ragged 8-cell last
-    tiles.  All 500 mode counts, sampled cells of both grids and sampled
-    delta(m) against the C oracle loops."""
+    tiles.  P(k) and mode counts of all 500 shells against the full-size
+    FP64 oracle, sampled cells of both grids and sampled delta(m) against the
+    C oracle loops."""
     box, n, p = 1500.0, 1000, 4
     pos = synth.zeldovich(200, box, 13, dtype=np.float32)
     dpos = to_dev(torch, pos)
@@ -206,7 +210,9 @@ def test_largest_mixed_grid_n1000(torch):
     counts, ksum = native.mode_table(n, 1, n // 2)
     assert np.array_equal(nm.cpu().numpy()[0], counts)
     assert rel_err(k.cpu().numpy()[0], 2 * np.pi / box * ksum / counts) < 1e-10
-    assert np.all(np.isfinite(pk.cpu().numpy()))
+    _, p0, n0 = native.power_large(pos, box, n, p, True, 1, n // 2)
+    assert np.array_equal(n0, counts)
+    assert rel_err(pk.cpu().numpy()[0], p0) < 1e-5
     cells = np.array([[0, 0, 0], [999, 999, 999], [992, 991, 999], [991, 992, 0], [7, 8, 995],
                       [500, 499, 996], [996, 3, 992], [123, 456, 789]])
     est.deposit(dpos)

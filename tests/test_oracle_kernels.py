@@ -218,3 +218,80 @@ def test_c_cell_values_and_mode_table_match_numpy_oracle():
         c0, k0 = spectrum.mode_table(nn, dk, nb)
         c1, k1 = native.mode_table(nn, dk, nb)
         assert np.array_equal(c0, c1) and np.allclose(k0, k1, rtol=1e-12)
+
+
+# Every shift a grid of any interlacing code is sampled at (bit a of the
+# mask: half a cell along axis a).
+_ALL_SHIFTS = [spectrum.mask_shift(mk) for mk in range(8)]
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_cell_values_match_deposit_every_order_and_shift(p):
+    """assign.cell_values and the C cell_values loop, which the full-size GPU
+    tests use as the reference grid values, equal the brute-force-pinned
+    numpy deposit at every order and every half-cell shift."""
+    from oracle import native
+    n, box = 12, 60.0
+    pos = synth.zeldovich(10, box, 40 + p, dtype=np.float32)
+    rng = np.random.default_rng(p)
+    cells = np.concatenate([np.array([[0, 0, 0], [11, 11, 11], [0, 11, 5], [6, 0, 11]]),
+                            rng.integers(0, n, (12, 3))])
+    every = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    for sh in _ALL_SHIFTS:
+        u = assign.grid_coords(pos, box, n) + sh
+        ref = assign.deposit_u(u, p, n)
+        assert np.allclose(native.cell_values(pos, box, n, p, every, sh),
+                           ref.reshape(-1), rtol=0, atol=1e-12), sh
+        assert np.allclose(assign.cell_values(pos, box, n, p, cells, sh),
+                           ref[cells[:, 0], cells[:, 1], cells[:, 2]], rtol=0, atol=1e-12), sh
+
+
+@pytest.mark.parametrize("p", ORDERS)
+@pytest.mark.parametrize("code", [0, 1, 2, 3])
+def test_delta_modes_match_delta_half_every_order_and_code(p, code):
+    """native.delta_modes (footprint DFT per mode, combined and deconvolved),
+    the reference of the sampled-mode GPU tests, equals the numpy oracle's
+    delta on the half spectrum for every order and interlacing code."""
+    from oracle import native
+    n, box = 16, 150.0
+    pos = synth.zeldovich(10, box, 50 + p, dtype=np.float32)
+    delta, _ = spectrum.delta_half(pos, box, n, p, code)
+    rng = np.random.default_rng(7 + p)
+    idx = np.concatenate([np.array([[1, 0, 0], [8, 0, 0], [8, 8, 8], [0, 8, 2], [15, 9, 8]]),
+                          np.stack([rng.integers(0, n, 10), rng.integers(0, n, 10),
+                                    rng.integers(0, n // 2 + 1, 10)], axis=1)])
+    modes = np.where(idx <= n // 2, idx, idx - n)
+    got = native.delta_modes(pos, box, n, p, code, modes)
+    ref = delta[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-13 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n,p", [(12, 1), (16, 4), (20, 6), (17, 3)])
+def test_deposit_slabs_equal_serial_loop(n, p):
+    """The x-plane-parallel C deposit equals the serial C loop bit for bit
+    (and so the numpy deposit it is pinned to)."""
+    from oracle import native
+    box = 70.0
+    pos = synth.uniform(4000, box, 60 + p, np.float32)
+    for sh in (0.0, 0.5):
+        a = native.deposit(pos, box, n, p, sh)
+        b = native.deposit_slabs(pos, box, n, p, sh)
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("p,il", [(2, False), (4, True), (3, True)])
+def test_power_large_matches_power(p, il):
+    """The plane-chunked full-size oracle equals the all-at-once oracle, and
+    its band of low modes equals delta on the half spectrum."""
+    from oracle import native
+    n, box, band = 24, 300.0, 5
+    pos = synth.zeldovich(16, box, 70 + p, dtype=np.float32)
+    k0, p0, n0 = spectrum.power(pos, box, n, p, il)
+    k1, p1, n1, db = native.power_large(pos, box, n, p, il, planes=5, band=band)
+    assert np.array_equal(n0, n1)
+    assert np.allclose(p1, p0, rtol=1e-12) and np.allclose(k1, k0, rtol=1e-12)
+    delta, _ = spectrum.delta_half(pos, box, n, p, il)
+    for mx in range(-band, band + 1):
+        for my in range(-band, band + 1):
+            assert np.allclose(db[mx + band, my + band], delta[mx % n, my % n, :band + 1],
+                               rtol=1e-12, atol=1e-15)
