@@ -264,6 +264,22 @@ est_status estimator_direct_delta(est_handle h, const void* pos,
                                   est_dtype dtype, int64_t n, void* dws,
                                   size_t dws_bytes, double* out);
 
+/* estimator_direct_delta without a caller workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as estimator_direct_delta; the workspace is instead a static
+ * device array of 64 MiB that the library holds on every GPU it runs on
+ * until the process ends (its device address is looked up once per device
+ * by estimator_create).  This call allocates nothing.  EST_ENOMEM (nothing
+ * launched) when estimator_direct_workspace_bytes(h, n) exceeds 64 MiB, e.g.
+ * about 4e5 particles on N = 64.  Every call on one GPU shares that array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, handles or threads) race and must be serialised by the caller;
+ * calls on one stream are ordered by it. */
+est_status estimator_direct_delta_noalloc(est_handle h, const void* pos,
+                                          est_dtype dtype, int64_t n,
+                                          double* out);
+
 /* The estimator's delta(m) = C(m) / (N_P W(m)) (eqs. intdelta,
  * windowcorrection; normalised like the direct sum) of set `mock` at every
  * half-spectrum mode, into out (device half spectrum).  Needs

@@ -43,7 +43,8 @@ EXPORTS = [
     "estimator_backward", "estimator_graph_capture", "estimator_graph_launch",
     "estimator_autotune", "estimator_set_launch", "estimator_set_weights", "estimator_copy_grid",
     "estimator_sample_delta",
-    "estimator_direct_workspace_bytes", "estimator_direct_delta", "estimator_export_delta",
+    "estimator_direct_workspace_bytes", "estimator_direct_delta", "estimator_direct_delta_noalloc",
+    "estimator_export_delta",
     "estimator_spectrum_power",
     "estimator_profile", "estimator_profile_read", "estimator_last_error",
 ]
@@ -92,6 +93,7 @@ _SIGS = {
     "estimator_sample_delta": [_P, _I32, _P, _I64, _P],
     "estimator_direct_workspace_bytes": [_P, _I64, ctypes.POINTER(_SZ)],
     "estimator_direct_delta": [_P, _P, _I32, _I64, _P, _SZ, _P],
+    "estimator_direct_delta_noalloc": [_P, _P, _I32, _I64, _P],
     "estimator_export_delta": [_P, _I32, _P],
     "estimator_spectrum_power": [_P, _P, _P, _I32, _I32, ctypes.c_double, _P, _P, _P],
     "estimator_profile": [_P, _I32],
@@ -220,6 +222,10 @@ def estimator_direct_workspace_bytes(h, n):
 def estimator_direct_delta(h, pos, dtype, n, dws, dws_bytes, out):
     _check(_lib.estimator_direct_delta(h, _ptr(pos), int(dtype), int(n), _ptr(dws),
                                        _SZ(int(dws_bytes)), _ptr(out)))
+
+
+def estimator_direct_delta_noalloc(h, pos, dtype, n, out):
+    _check(_lib.estimator_direct_delta_noalloc(h, _ptr(pos), int(dtype), int(n), _ptr(out)))
 
 
 def estimator_export_delta(h, mock, out):

@@ -375,7 +375,10 @@ est_status estimator_create(const est_config* cfg, void* workspace, size_t works
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   clear_stale_error();
-  st = dev_err(launch_tables(h->g, h->b, h->stream), "tables");
+  // device address of the static workspace of estimator_direct_delta_noalloc
+  // (once per device)
+  st = dev_err(direct_static_scratch_init(h->device), "static workspace lookup");
+  if (!st) st = dev_err(launch_tables(h->g, h->b, h->stream), "tables");
   if (st) {
     delete h;
     return st;
@@ -755,6 +758,25 @@ est_status estimator_direct_delta(est_handle h, const void* pos, est_dtype dtype
   if (dws_bytes < need) return fail(EST_ENOMEM, "direct workspace too small: %zu < %zu", dws_bytes, need);
   ProfScope ps(h, kPDirect);
   return dev_err(launch_direct(h->g, pos, dtype, n, h->weights, dws, out, h->stream), "direct sum");
+}
+
+est_status estimator_direct_delta_noalloc(est_handle h, const void* pos, est_dtype dtype, int64_t n,
+                                          double* out) {
+  est_status st = check_handle(h);
+  if (st) return st;
+  if (!pos || !out) return fail(EST_EINVAL, "pos and out are required");
+  if (dtype != EST_F32 && dtype != EST_F64) return fail(EST_EINVAL, "dtype must be EST_F32 or EST_F64");
+  if (n < 1 || n > 2147483647LL) return fail(EST_EINVAL, "n must be 1..2^31-1");
+  const size_t need = direct_workspace(h->g.n, n);
+  if (need > kDirectStaticBytes)
+    return fail(EST_ENOMEM,
+                "direct sum of %lld particles on N = %d needs %zu bytes of workspace, more than the "
+                "%zu-byte static workspace of estimator_direct_delta_noalloc",
+                (long long)n, h->g.n, need, kDirectStaticBytes);
+  void* ws = direct_static_scratch(h->device);
+  if (!ws) return fail(EST_EDEVICE, "static workspace not set up on device %d", h->device);
+  clear_stale_error();
+  return dev_err(launch_direct(h->g, pos, dtype, n, h->weights, ws, out, h->stream), "direct sum");
 }
 
 est_status estimator_export_delta(est_handle h, int32_t mock, double* out) {

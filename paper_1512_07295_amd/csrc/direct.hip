@@ -14,6 +14,8 @@
 //    chunks and summed in FP32 per chunk, then in FP64;
 //  * particles are split into S slices (a grid dimension) for parallelism;
 //    a fixed-order FP64 reduction over the slices gives deterministic output.
+#include <mutex>
+
 #include "fsest_internal.hpp"
 
 namespace fsest {
@@ -152,6 +154,41 @@ int direct_slices(int ngrid, int64_t n) {
 // workspace: fixed-point phases, the mass sums (partials, totals, flags),
 // then the per-slice partial spectra
 constexpr size_t kDirMassBytes = 256 * ((2 * kWSlicesMax * 8 + 2 * 8 + 64 * 4 + 255) / 256);
+
+// Static workspace of the allocation-free entry point.  In host code the
+// name `scratch` only stands for the symbol: its device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current
+// and kept in g_scratch_ptr; only that pointer is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[kDirectStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t direct_static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* direct_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 size_t direct_workspace(int ngrid, int64_t n) {
   const int64_t nmodes = (int64_t)ngrid * ngrid * (ngrid / 2 + 1);

@@ -175,6 +175,12 @@ hipError_t launch_spectrum_power(const Geom& g, const Buffers& b, const double* 
                                  int64_t* nmodes, hipStream_t s);
 // direct summation (eq. deltaDS) over every half-space mode
 size_t direct_workspace(int ngrid, int64_t n);
+// the allocation-free entry point's static workspace (64 MiB per device):
+// looked up once per device (hipGetSymbolAddress with that device current),
+// then its device address; null before a successful init on that device
+constexpr size_t kDirectStaticBytes = (size_t)64 << 20;
+hipError_t direct_static_scratch_init(int device);
+void* direct_static_scratch(int device);
 // w: masses (null: equal masses), normalised by their sum
 hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, const float* w,
                          void* ws,
