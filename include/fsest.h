@@ -145,10 +145,13 @@ est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins,
                            int32_t subtract_shot, double* k, double* p,
                            int64_t* nmodes);
 
-/* Bytes of extra device workspace estimator_bispectrum needs for n_bins
- * shells and n_tri triangles.  Host only. */
-est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_bins,
-                                                int64_t n_tri, size_t* bytes);
+/* Bytes of extra device workspace estimator_bispectrum needs for shells of
+ * width n_dk k_f, n_bins shells and n_tri triangles (e.g. about 11.3 GB for
+ * 128 shells of 2 k_f and all 185,056 closed triangles).  Host only; EINVAL
+ * under the same conditions as estimator_bispectrum. */
+est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_dk,
+                                                int32_t n_bins, int64_t n_tri,
+                                                size_t* bytes);
 
 /* FFT-shell bispectrum (Sec. 4.1, eqs. Best, VBest, Best2, IntI) of set 0
  * (or of `mock`), shells of width n_dk k_f.
@@ -158,6 +161,13 @@ est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_bins,
  *   b          device float64 [n_tri]: V^2 sum III / sum JJJ (NaN if no
  *              closed triplet).
  *   ntri       device float64 [n_tri]: number of closed mode triplets.
+ * The shell fields are evaluated on a grid of M points per axis, the
+ * smallest 2^a 3^b 5^c above 3 R (R the largest |m_a| of the shells; M <= N):
+ * like N under the triangle limit, such an M keeps every triplet sum free of
+ * aliased terms, so the results are those of the N grid up to rounding.
+ * The count sums (sum JJJ) do not depend on the data: the handle keeps them
+ * after a call and reuses them while M, n_dk, n_bins and the triangles' tiles
+ * stay the same.  Host-synchronising.
  * EINVAL if (n_bins + 1/2) n_dk >= N/3 (the triangle limit of Sec. 4.1).
  * ESTATE before estimator_transform. */
 est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk,

@@ -108,3 +108,57 @@ def bispectrum(pos, box, n_grid, order, interlace_on, n_dk=2, n_bins=None,
         bk = bk - sn * (pk[triangles[:, 0] - 1] + pk[triangles[:, 1] - 1]
                         + pk[triangles[:, 2] - 1]) - sn * sn
     return triangles, bk, n_tri
+
+
+def shell_modes_band(band, n_dk, b):
+    """Signed modes (k, 3) of shell b (same integer rule as P(k)) with every
+    |m_a| <= band."""
+    r = np.arange(-band, band + 1, dtype=np.int64)
+    mx, my, mz = np.meshgrid(r, r, r, indexing="ij")
+    q = np.stack([mx, my, mz], -1).reshape(-1, 3)
+    m2 = (q * q).sum(1)
+    sel = (m2 > 0) & (bin_index(m2, n_dk) == b)
+    return q[sel]
+
+
+def band_lookup(d_band, band, q):
+    """delta at signed modes q from d_band[m_x + band, m_y + band, m_z]
+    (m_z = 0 .. band), completed by delta(-m) = conj(delta(m))."""
+    q = np.asarray(q, dtype=np.int64)
+    neg = q[:, 2] < 0
+    qq = np.where(neg[:, None], -q, q)
+    v = d_band[qq[:, 0] + band, qq[:, 1] + band, qq[:, 2]]
+    return np.where(neg, np.conj(v), v)
+
+
+def brute_triplets(d_band, band, n_dk, tri):
+    """For each triangle (b1, b2, b3): the number of closed triplets
+    q1 + q2 + q3 = 0 with q_i in shell b_i, and sum delta(q1) delta(q2)
+    delta(q3) and sum |delta delta delta| over them, by enumeration (eq. Best
+    and the normalisation of eq. VBest by their definitions).  Every shell
+    used must lie inside the band (|m| < (b + 1/2) n_dk <= band)."""
+    counts, sums, abss = [], [], []
+    for b1, b2, b3 in np.asarray(tri).reshape(-1, 3):
+        if 2 * band < (2 * int(b1) + 1) * n_dk - 1:
+            raise ValueError("shell %d reaches outside the band" % b1)
+        q1 = shell_modes_band(band, n_dk, int(b1))
+        q2 = shell_modes_band(band, n_dk, int(b2))
+        d1 = band_lookup(d_band, band, q1)
+        d2 = band_lookup(d_band, band, q2)
+        c, s, a = 0, 0.0 + 0.0j, 0.0
+        for i0 in range(0, len(q1), 512):
+            q3 = -(q1[i0:i0 + 512, None, :] + q2[None, :, :])
+            m2 = (q3 * q3).sum(-1)
+            ok = (m2 > 0) & (bin_index(m2, n_dk) == b3)
+            i1, i2 = np.nonzero(ok)
+            if len(i1) == 0:
+                continue
+            d3 = band_lookup(d_band, band, q3[i1, i2])
+            prod = d1[i0 + i1] * d2[i2] * d3
+            c += len(i1)
+            s += prod.sum()
+            a += np.abs(prod).sum()
+        counts.append(c)
+        sums.append(s)
+        abss.append(a)
+    return np.array(counts), np.array(sums), np.array(abss)

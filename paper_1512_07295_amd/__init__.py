@@ -81,7 +81,7 @@ _SIGS = {
     "estimator_deposit": [_P, _P, _I32, _P, _I64],
     "estimator_transform": [_P],
     "estimator_power": [_P, _I32, _I32, _I32, _P, _P, _P],
-    "estimator_bispectrum_workspace_bytes": [_P, _I32, _I64, ctypes.POINTER(_SZ)],
+    "estimator_bispectrum_workspace_bytes": [_P, _I32, _I32, _I64, ctypes.POINTER(_SZ)],
     "estimator_bispectrum": [_P, _I32, _I32, _I32, _P, _I64, _P, _SZ, _P, _P],
     "estimator_backward": [_P, _P, _I32, _P, _I64, _P, _I32, _I32, _P],
     "estimator_graph_capture": [_P, _P, _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P],
@@ -161,9 +161,10 @@ def estimator_power(h, n_dk, n_bins, subtract_shot, k, p, nmodes):
                                 _ptr(nmodes)))
 
 
-def estimator_bispectrum_workspace_bytes(h, n_bins, n_tri):
+def estimator_bispectrum_workspace_bytes(h, n_dk, n_bins, n_tri):
     out = _SZ(0)
-    _check(_lib.estimator_bispectrum_workspace_bytes(h, int(n_bins), int(n_tri), ctypes.byref(out)))
+    _check(_lib.estimator_bispectrum_workspace_bytes(h, int(n_dk), int(n_bins), int(n_tri),
+                                                     ctypes.byref(out)))
     return int(out.value)
 
 

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsest.so")
-SOURCES = ["api.hip", "deposit.hip", "direct.hip", "fft.hip", "gather.hip", "sort.hip", "spectral.hip"]
+SOURCES = ["api.hip", "bispec.hip", "deposit.hip", "direct.hip", "fft.hip", "gather.hip", "sort.hip", "spectral.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -73,6 +73,11 @@ struct est_ctx {
   bool prof = false;
   bool capturing = false;
   const float* weights = nullptr;  // masses for the particle calls (EST_FLAG_WEIGHTS)
+  // the bispectrum's count sums (sum_x J J J per job entry) of the last
+  // (field grid, shell width, shells, jobs), reused while they match
+  int bs_M = 0, bs_dk = 0, bs_nbins = 0;
+  std::vector<int32_t> bs_jobs;
+  std::vector<double> bs_runj;
   ProfRec rec[kPNumLabels];
   std::vector<hipEvent_t> pool;
 };
@@ -437,33 +442,38 @@ est_status estimator_power(est_handle h, int32_t n_dk, int32_t n_bins, int32_t s
                  "power");
 }
 
-static int bispec_xranges(int64_t n_tri) {
-  const int64_t tb = (n_tri + 255) / 256;
-  int64_t nx = 4096 / tb;
-  if (nx < 1) nx = 1;
-  if (nx > 512) nx = 512;
-  return (int)nx;
+// Host checks shared by the bispectrum's size query and the call: shells
+// below the triangle limit k_max = k_f N / 3 of Sec. 4.1, (n_bins + 1/2)
+// n_dk < N/3.
+static est_status check_bispec_bins(est_handle h, int32_t n_dk, int32_t n_bins, int64_t n_tri) {
+  if (n_dk < 1) return fail(EST_EINVAL, "n_dk must be >= 1");
+  if (n_bins < 1 || n_bins > kMaxBins) return fail(EST_EINVAL, "n_bins out of range");
+  if (3LL * (2 * n_bins + 1) * n_dk >= 2LL * h->g.n)
+    return fail(EST_EINVAL, "(n_bins + 1/2) n_dk must be < N/3 (triangle aliasing limit)");
+  if (n_tri < 1) return fail(EST_EINVAL, "n_tri must be >= 1");
+  return ok();
 }
 
-static size_t bispec_bytes(const Geom& g, int n_bins, int64_t n_tri) {
-  const size_t n3 = (size_t)g.n * g.n * g.n;
-  const size_t npairs = (size_t)(n_bins + 1) / 2;
-  size_t off = 0;
-  off = align_up(off + npairs * n3 * sizeof(float2));  // I pairs
-  off = align_up(off + npairs * n3 * sizeof(float2));  // J pairs
-  off = align_up(off + (size_t)n_tri * 3 * sizeof(int32_t));
-  off = align_up(off + (size_t)bispec_xranges(n_tri) * n_tri * 2 * sizeof(double));
-  return off;
+// the plan the caller's workspace is sized for: as many jobs as triangles,
+// at most every job of n_bins shells
+static est_status bispec_size_plan(est_handle h, int32_t n_dk, int32_t n_bins, int64_t n_tri,
+                                   BsPlan* pl) {
+  int64_t nj = bs_max_jobs(n_bins);
+  if (nj > n_tri) nj = n_tri;
+  if (!bs_plan(h->g.n, n_dk, n_bins, nj, n_tri, pl))
+    return fail(EST_EUNSUPPORTED, "no alias-free field grid for these shells");
+  return ok();
 }
 
-est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_bins, int64_t n_tri,
-                                                size_t* bytes) {
+est_status estimator_bispectrum_workspace_bytes(est_handle h, int32_t n_dk, int32_t n_bins,
+                                                int64_t n_tri, size_t* bytes) {
   est_status st = check_handle(h);
   if (st) return st;
   if (!bytes) return fail(EST_EINVAL, "bytes is NULL");
-  if (n_bins < 1 || n_bins > kMaxBins) return fail(EST_EINVAL, "n_bins out of range");
-  if (n_tri < 1) return fail(EST_EINVAL, "n_tri must be >= 1");
-  *bytes = bispec_bytes(h->g, n_bins, n_tri);
+  if ((st = check_bispec_bins(h, n_dk, n_bins, n_tri))) return st;
+  BsPlan pl;
+  if ((st = bispec_size_plan(h, n_dk, n_bins, n_tri, &pl))) return st;
+  *bytes = pl.bytes;
   return ok();
 }
 
@@ -474,12 +484,8 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
   if (st) return st;
   const Geom& g = h->g;
   if (mock < 0 || mock >= g.batch) return fail(EST_EINVAL, "mock out of range");
-  if (n_dk < 1) return fail(EST_EINVAL, "n_dk must be >= 1");
-  if (n_bins < 1 || n_bins > kMaxBins) return fail(EST_EINVAL, "n_bins out of range");
-  // triangle limit k_max = k_f N / 3 (Sec. 4.1): (n_bins + 1/2) n_dk < N/3
-  if (3LL * (2 * n_bins + 1) * n_dk >= 2LL * g.n)
-    return fail(EST_EINVAL, "(n_bins + 1/2) n_dk must be < N/3 (triangle aliasing limit)");
   if (!tri_host || n_tri < 1) return fail(EST_EINVAL, "triangles missing");
+  if ((st = check_bispec_bins(h, n_dk, n_bins, n_tri))) return st;
   if (!bws || !bk || !ntri) return fail(EST_EINVAL, "NULL device pointer");
   if (((uintptr_t)bws & 255) != 0) return fail(EST_EINVAL, "bispectrum workspace must be 256-byte aligned");
   for (int64_t t = 0; t < n_tri; ++t) {
@@ -487,47 +493,59 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
     if (!(1 <= c && c <= b && b <= a && a <= n_bins))
       return fail(EST_EINVAL, "triangle %lld must satisfy 1 <= b3 <= b2 <= b1 <= n_bins", (long long)t);
   }
-  const size_t need = bispec_bytes(g, n_bins, n_tri);
-  if (bws_bytes < need) return fail(EST_ENOMEM, "bispectrum workspace too small: %zu < %zu", bws_bytes, need);
+  BsPlan sized;
+  if ((st = bispec_size_plan(h, n_dk, n_bins, n_tri, &sized))) return st;
+  if (bws_bytes < sized.bytes)
+    return fail(EST_ENOMEM, "bispectrum workspace too small: %zu < %zu", bws_bytes, sized.bytes);
+  // this call's tile jobs and the entry of every triangle; the plan with the
+  // actual job count fits in the sized workspace
+  std::vector<int32_t> jobs, tmap;
+  bs_jobs(tri_host, n_tri, jobs, tmap);
+  const int64_t njobs = (int64_t)jobs.size() / 4;
+  BsPlan pl;
+  if (!bs_plan(g.n, n_dk, n_bins, njobs, n_tri, &pl))
+    return fail(EST_EUNSUPPORTED, "no alias-free field grid for these shells");
   if ((st = to_spectrum(h))) return st;
-  const size_t n3 = (size_t)g.n * g.n * g.n;
-  const int npairs = (n_bins + 1) / 2;
-  char* base = (char*)bws;
-  size_t off = 0;
-  float2* ip = (float2*)(base + off);
-  off = align_up(off + (size_t)npairs * n3 * sizeof(float2));
-  float2* jp = (float2*)(base + off);
-  off = align_up(off + (size_t)npairs * n3 * sizeof(float2));
-  int32_t* tri_dev = (int32_t*)(base + off);
-  off = align_up(off + (size_t)n_tri * 3 * sizeof(int32_t));
-  double* part = (double*)(base + off);
-  if ((st = dev_err(hipMemcpyAsync(tri_dev, tri_host, (size_t)n_tri * 3 * sizeof(int32_t),
-                                   hipMemcpyHostToDevice, h->stream), "copy triangles")))
-    return st;
-  // full-length complex transforms of the shell fields
-  Geom gf = g;
-  gf.nz = g.n;
-  gf.batch = 1;
-  gf.ps = (int64_t)g.n * g.n;  // the shell fields are unpadded N^3 arrays
-  for (int q = 0; q < npairs; ++q) {
-    const int b1 = 2 * q + 1, b2 = (2 * q + 2 <= n_bins) ? 2 * q + 2 : 0;
-    for (int which = 0; which < 2; ++which) {
-      float2* dst = (which ? jp : ip) + (size_t)q * n3;
-      if ((st = dev_err(launch_shell_pair(g, h->b, mock, n_dk, b1, b2, which == 1, dst, h->stream), "shell fields")))
-        return st;
-      for (int ax = 2; ax >= 0; --ax) {
-        if ((st = dev_err(launch_fft_axis(gf, dst, ax, +1, 1, g.n, h->b.tw_n, h->tu, h->stream), "inverse fft")))
-          return st;
-      }
-    }
-  }
   ProfScope ps(h, kPBispec);
-  const int nx = bispec_xranges(n_tri);
-  if ((st = dev_err(launch_triple_sums((int64_t)n3, ip, jp, n_bins, tri_dev, n_tri, part, nx, h->stream), "triple sums")))
+  char* base = (char*)bws;
+  double* run_i = (double*)(base + pl.off_run);
+  double* run_j = run_i + njobs * 256;
+  if ((st = dev_err(hipMemcpyAsync(base + pl.off_jobs, jobs.data(), jobs.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, h->stream), "copy jobs")) ||
+      (st = dev_err(hipMemcpyAsync(base + pl.off_tmap, tmap.data(), tmap.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, h->stream), "copy triangle map")))
     return st;
-  if ((st = dev_err(launch_bispec_finalize(part, nx, n_tri, g.box * g.box * g.box, (double)n3, bk, ntri, h->stream), "bispectrum")))
+  if ((st = dev_err(launch_bs_setup(g, h->b, mock, n_dk, n_bins, pl, base, h->stream), "delta cube")))
     return st;
-  // the host triangle buffer must outlive the copy
+  if ((st = dev_err(launch_bs_sums(n_dk, n_bins, pl, base, false, run_i, h->stream), "triple sums")))
+    return st;
+  // the counts' sums depend only on the grid M, the shells and the jobs:
+  // computed on the first call and kept by the handle
+  const bool cached = h->bs_M == pl.M && h->bs_dk == n_dk && h->bs_nbins == n_bins &&
+                      h->bs_jobs == jobs && h->bs_runj.size() == (size_t)njobs * 256;
+  if (cached) {
+    if ((st = dev_err(hipMemcpyAsync(run_j, h->bs_runj.data(), h->bs_runj.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, h->stream), "cached counts")))
+      return st;
+  } else {
+    h->bs_M = 0;
+    if ((st = dev_err(launch_bs_sums(n_dk, n_bins, pl, base, true, run_j, h->stream), "count sums")))
+      return st;
+    std::vector<double> runj((size_t)njobs * 256);
+    if ((st = dev_err(hipMemcpyAsync(runj.data(), run_j, runj.size() * sizeof(double),
+                                     hipMemcpyDeviceToHost, h->stream), "keep counts")) ||
+        (st = dev_err(hipStreamSynchronize(h->stream), "synchronize")))
+      return st;
+    h->bs_runj.swap(runj);
+    h->bs_jobs = jobs;
+    h->bs_M = pl.M;
+    h->bs_dk = n_dk;
+    h->bs_nbins = n_bins;
+  }
+  if ((st = dev_err(launch_bs_finalize(pl, base, n_tri, g.box * g.box * g.box, bk, ntri, h->stream),
+                    "bispectrum")))
+    return st;
+  // the host job and triangle buffers must outlive their copies
   return dev_err(hipStreamSynchronize(h->stream), "synchronize");
 }
 

@@ -217,6 +217,18 @@ static hipError_t cols_dir(int L, float2* data, int64_t elem_stride, int64_t inn
   }
 }
 
+hipError_t launch_fft_rows_len(int L, float2* data, int64_t nrows, int rows_per_plane,
+                               int64_t plane_stride, int dir, const float2* tw, hipStream_t s) {
+  return dir < 0 ? rows_dir<-1>(L, data, nrows, rows_per_plane, plane_stride, tw, s)
+                 : rows_dir<+1>(L, data, nrows, rows_per_plane, plane_stride, tw, s);
+}
+
+hipError_t launch_fft_cols_len(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                               int64_t outer_stride, int dir, int c, const float2* tw, hipStream_t s) {
+  return dir < 0 ? cols_dir<-1>(L, data, elem_stride, inner, outer, outer_stride, c, tw, s)
+                 : cols_dir<+1>(L, data, elem_stride, inner, outer, outer_stride, c, tw, s);
+}
+
 hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch, int nz_len,
                            const float2* tw_axis, const Tune& tu, hipStream_t s) {
   const int64_t n = g.n, nz = nz_len, ps = g.ps;

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 #include "../../include/fsest.h"
 
 namespace fsest {
@@ -153,6 +155,14 @@ hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s);
 // direction: -1 forward, +1 inverse.  axis 0 = x (stride N*nz), 1 = y (stride nz), 2 = z (rows).
 hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch,
                            int nz_len, const float2* tw_axis, const Tune& tu, hipStream_t s);
+// one axis of transforms of length L (any 2^a 3^b 5^c up to 1024) on a
+// buffer: contiguous rows (row r at (r / rows_per_plane) plane_stride +
+// (r % rows_per_plane) L), or strided lines (inner adjacent lines per outer
+// block, c of them per workgroup); tw[n] = exp(-2 pi i n / L)
+hipError_t launch_fft_rows_len(int L, float2* data, int64_t nrows, int rows_per_plane,
+                               int64_t plane_stride, int dir, const float2* tw, hipStream_t s);
+hipError_t launch_fft_cols_len(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
+                               int64_t outer_stride, int dir, int c, const float2* tw, hipStream_t s);
 hipError_t launch_mode_table(const Geom& g, const Buffers& b, int n_dk, int n_bins, hipStream_t s);
 // fused last-axis forward FFT (if do_fft) + interlace + deconvolve + shell sums + finalize
 hipError_t launch_power(const Geom& g, const Buffers& b, const Tune& tu, bool do_fft, int n_dk,
@@ -185,13 +195,32 @@ void* direct_static_scratch(int device);
 hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n, const float* w,
                          void* ws,
                          double* out, hipStream_t s);
-// bispectrum
-hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
-                             bool counts_only, float2* out, hipStream_t s);
-hipError_t launch_triple_sums(int64_t npts, const float2* ipairs, const float2* jpairs, int n_bins,
-                              const int32_t* tri, int64_t n_tri, double* part, int n_xr,
-                              hipStream_t s);
-hipError_t launch_bispec_finalize(const double* part, int n_xr, int64_t n_tri, double vol,
-                                  double n3, double* bk, double* ntri, hipStream_t s);
+// ---- FFT-shell bispectrum (bispec.hip)
+// One call's plan: band radius R (every mode of shells 1..n_bins has
+// |m_a| <= R), the alias-free grid M > 3R, Q shell pairs, slabs of S
+// x-planes, points per LDS chunk pc, tile jobs, job groups and point ranges
+// of the triple-sum launch, and the byte offsets of the regions of the
+// caller's bispectrum workspace.
+struct BsPlan {
+  int R, M, Q, S, nslab, pc, ngroups, nranges;
+  int64_t npts, njobs;
+  size_t off_tw, off_band, off_slab, off_jobs, off_tmap, off_part, off_run, bytes;
+};
+// jobs of every ordered triple b1 >= b2 >= b3 of shells 1..n_bins
+int64_t bs_max_jobs(int n_bins);
+// false if no grid of the form 2^a 3^b 5^c between 3R and min(N, 1024) exists
+bool bs_plan(int n, int n_dk, int n_bins, int64_t njobs, int64_t n_tri, BsPlan* pl);
+// the tile jobs (int32 x 4 each: d, r0, c0, 0) of a triangle list and each
+// triangle's (job, entry) pair
+void bs_jobs(const int32_t* tri, int64_t n_tri, std::vector<int32_t>& jobs,
+             std::vector<int32_t>& tmap);
+// twiddles of length M and the cube of delta(m), |m_a| <= R
+hipError_t launch_bs_setup(const Geom& g, const Buffers& b, int mock, int n_dk, int n_bins,
+                           const BsPlan& pl, char* bws, hipStream_t s);
+// per-entry sums over every slab (delta fields, or the counts when `counts`)
+hipError_t launch_bs_sums(int n_dk, int n_bins, const BsPlan& pl, char* bws, bool counts,
+                          double* run, hipStream_t s);
+hipError_t launch_bs_finalize(const BsPlan& pl, char* bws, int64_t n_tri, double vol, double* bk,
+                              double* ntri, hipStream_t s);
 
 }  // namespace fsest

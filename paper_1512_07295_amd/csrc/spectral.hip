@@ -1,7 +1,7 @@
 // Fourier-space stages: interlacing (eq. intdelta), window deconvolution
 // (eqs. windowcorrection, intkerFT), |k|-shell sums for P(k) (eq. ps and the
-// estimator of Sec. 2.2), the adjoint spectrum, and the FFT-shell bispectrum
-// (Sec. 4.1, eqs. Best2, IntI).
+// estimator of Sec. 2.2) and the adjoint spectrum.  The bispectrum is in
+// bispec.hip.
 //
 // The grid holds Z = FFT(rho1 + i rho2) (interlaced) or Z = FFT of the real
 // grid packed pairwise along z (h = N/2 complex columns).  Either way the
@@ -10,7 +10,7 @@
 // the z FFT of both rows, keeps them in LDS and finishes every half-space mode
 // of the pair without writing the spectrum back.
 #include "fft_line.hpp"
-#include "fsest_internal.hpp"
+#include "modes.hpp"
 
 namespace fsest {
 
@@ -51,103 +51,6 @@ hipError_t launch_tables(const Geom& g, const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, g, b.tw_n, b.tw_nz,
                      b.inv_w2, b.win1, b.phase);
   return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ int signed_freq(int i, int n) { return (i <= n / 2) ? i : i - n; }
-
-// -i mod n for 0 <= i < n (a mask when n is a compile-time power of two)
-template <bool P2>
-__device__ __forceinline__ int neg_mod(int i, int n) {
-  if constexpr (P2) return (n - i) & (n - 1);
-  else return i ? n - i : 0;
-}
-// s mod 2n for -2n <= s < 4n: index into the table exp(+i pi s / N)
-template <bool P2>
-__device__ __forceinline__ int mod_2n(int s, int n) {
-  if constexpr (P2) return s & (2 * n - 1);
-  else return s < 0 ? s + 2 * n : (s >= 2 * n ? s - 2 * n : s);
-}
-// FFT index of signed frequency m, |m| < n
-__device__ __forceinline__ int fft_index(int m, int n) { return m < 0 ? m + n : m; }
-
-// shell b with (2b-1)^2 n^2 <= 4 m2 < (2b+1)^2 n^2 (b = 0 below the first shell)
-__device__ __forceinline__ int shell_of(int m2, int n_dk) {
-  const int x = 4 * m2;
-  int r = (int)sqrtf((float)x);
-  while (r * r > x) --r;
-  while ((r + 1) * (r + 1) <= x) ++r;
-  return ((r / n_dk) + 1) >> 1;
-}
-
-// Row pair q of one set: rows (x, y) and (-x, -y); q < N^2/2 + 2.
-__device__ __forceinline__ void pair_rows(int64_t q, int n, int& x, int& y) {
-  const int h1 = n / 2 + 1;
-  if (q < h1) { x = 0; y = (int)q; return; }
-  q -= h1;
-  const int64_t mid = (int64_t)(n / 2 - 1) * n;
-  if (q < mid) { x = 1 + (int)(q / n); y = (int)(q % n); return; }
-  q -= mid;
-  x = n / 2;
-  y = (int)q;
-}
-
-// Transforms of the real grids at half-space mode (row, mz) from the pair
-// (Za, Zb) = (Z(k), Z(-k)), combined per eq. intdelta: returns C(m).
-template <bool IL, bool P2 = true>
-__device__ __forceinline__ float2 combined_mode(float2 za, float2 zb, int mx, int my, int mz,
-                                                const float2* __restrict__ phase, int n) {
-  // first and second real transforms: (za + conj zb)/2 and (za - conj zb)/(2i)
-  const float2 f1 = make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y));
-  const float2 f2 = make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x));
-  if constexpr (IL) {
-    const float2 ph = phase[mod_2n<P2>(mx + my + mz, n)];  // exp(+i pi (mx+my+mz)/N)
-    return cscale(cadd(f1, cmul(ph, f2)), 0.5f);
-  } else {
-    // even/odd z samples: F = E + exp(-2 pi i mz/N) O
-    const float2 ph = cconj(phase[mod_2n<P2>(2 * mz, n)]);
-    return cadd(f1, cmul(ph, f2));
-  }
-}
-
-// |K C(m)|^2 from the pair (Za, Zb) = (Z(k), Z(-k)) and the phase ph of
-// combined_mode: with a = Za, b = conj(Zb), 2 F1 = a + b and 2 F2 = (a - b)/i,
-// so (cx, cy) = 2 (F1 + ph F2).  The interlaced combination is
-// C = (F1 + ph F2)/2 (K = 4); the packed real grid's is C = F1 + ph F2 (K = 2).
-__device__ __forceinline__ float pair_power(float2 za, float2 zb, float2 ph) {
-  const float sx = za.x + zb.x, sy = za.y - zb.y;
-  const float dx = za.x - zb.x, dy = za.y + zb.y;
-  const float cx = sx + (ph.x * dy + ph.y * dx);
-  const float cy = sy + (ph.y * dy - ph.x * dx);
-  return cx * cx + cy * cy;
-}
-
-// C(m) of interlacing codes 2 and 3 (more than two grids): C = (1/G) sum_j
-// F_j(m) exp(+i pi s_j / N), s_j the sum of the components of m along the
-// axes grid j is shifted on, with F_2q and F_2q+1 unpacked from slab q's
-// Z(k) and Z(-k) as in combined_mode.  Signed m, |m_a| <= N/2.
-__device__ __forceinline__ float2 multi_mode(const float2* __restrict__ data, const Geom& g,
-                                             int mock, int mx, int my, int mz,
-                                             const float2* __restrict__ phase) {
-  const int n = g.n;
-  const int x = fft_index(mx, n), y = fft_index(my, n), z = fft_index(mz, n);
-  const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n), zm = neg_mod<false>(z, n);
-  const int m[3] = {mx, my, mz};
-  float2 c = make_float2(0.f, 0.f);
-  for (int q = 0; q < g.npair; ++q) {
-    const int slab = mock * g.npair + q;
-    const float2 za = data[complex_index(g, slab, x, y, z)];
-    const float2 zb = data[complex_index(g, slab, xm, ym, zm)];
-    const float2 f[2] = {make_float2(0.5f * (za.x + zb.x), 0.5f * (za.y - zb.y)),
-                         make_float2(0.5f * (za.y + zb.y), 0.5f * (zb.x - za.x))};
-    for (int h = 0; h < 2; ++h) {
-      const int mk = grid_mask(g.code, 2 * q + h);
-      int sj = 0;
-      for (int a = 0; a < 3; ++a) sj += ((mk >> a) & 1) ? m[a] : 0;
-      c = cadd(c, cmul(phase[mod_2n<false>(sj, n)], f[h]));
-    }
-  }
-  return cscale(c, 1.0f / (float)g.ng);
 }
 
 template <int L>
@@ -1044,158 +947,6 @@ hipError_t launch_sample_delta(const Geom& g, const Buffers& b, int mock, const 
                                int64_t n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sample_delta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.grid, g,
                      mock, modes, n, b.norm, out);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ bispectrum
-// Y(m) = S_b1(m) d(m) + i S_b2(m) d(m) on the full N^3 grid, d = delta (or 1
-// for the counts), so that one inverse complex FFT gives I_b1 + i I_b2 (eq. IntI).
-__global__ __launch_bounds__(256) void k_shell_pair(const float2* __restrict__ data, Geom g, int mock,
-                                                    int n_dk, int b1, int b2, int counts_only,
-                                                    const float2* __restrict__ phase,
-                                                    const float* __restrict__ win1,
-                                                    const double* __restrict__ norm,
-                                                    float2* __restrict__ out) {
-  const int n = g.n;
-  const int64_t n3 = (int64_t)n * n * n;
-  const int L = g.nz;
-  const float inv_np = 1.0f / (float)norm[2 * mock];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i / ((int64_t)n * n)), y = (int)((i / n) % n), z = (int)(i % n);
-    const int mx = signed_freq(x, n), my = signed_freq(y, n), mz = signed_freq(z, n);
-    const int m2 = mx * mx + my * my + mz * mz;
-    const int b = m2 ? shell_of(m2, n_dk) : 0;
-    float2 res = make_float2(0.f, 0.f);
-    if (b != 0 && (b == b1 || b == b2)) {
-      float2 d;
-      if (counts_only) {
-        d = make_float2(1.f, 0.f);
-      } else {
-        const int xm = neg_mod<false>(x, n), ym = neg_mod<false>(y, n);
-        const int zz = ((mz % L) + L) % L, zm = neg_mod<false>(zz, L);
-        float2 c;
-        if (g.npair > 1) {
-          c = multi_mode(data, g, mock, mx, my, mz, phase);
-        } else {
-          const float2 za = data[complex_index(g, mock, x, y, zz)];
-          const float2 zb = data[complex_index(g, mock, xm, ym, zm)];
-          if (g.il) c = combined_mode<true, false>(za, zb, mx, my, mz, phase, n);
-          else c = combined_mode<false, false>(za, zb, mx, my, mz, phase, n);
-        }
-        const float w = win1[x] * win1[y] * win1[z];
-        d = cscale(c, inv_np / w);
-      }
-      if (b == b1) res = cadd(res, d);
-      if (b == b2) res = cadd(res, make_float2(-d.y, d.x));
-    }
-    out[i] = res;
-  }
-}
-
-hipError_t launch_shell_pair(const Geom& g, const Buffers& b, int mock, int n_dk, int b1, int b2,
-                             bool counts_only, float2* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_shell_pair, dim3(8192), dim3(256), 0, s, b.grid, g, mock, n_dk, b1, b2,
-                     counts_only ? 1 : 0, b.phase, b.win1, b.norm, out);
-  return hipGetLastError();
-}
-
-// sum_x F_b1 F_b2 F_b3 for blocks of 256 triangles over x-ranges; fields b
-// live in pair buffers (b-1)/2 as the real (b odd) or imaginary part.
-constexpr int kTriXC = 64;
-
-__global__ __launch_bounds__(256) void k_triple(int64_t npts, const float2* __restrict__ ip,
-                                                const float2* __restrict__ jp, int n_bins,
-                                                const int32_t* __restrict__ tri, int64_t n_tri,
-                                                double* __restrict__ part, int n_xr) {
-  extern __shared__ float sh[];
-  float* fi = sh;
-  float* fj = sh + n_bins * (kTriXC + 1);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int b1 = 0, b2 = 0, b3 = 0;
-  const bool valid = t < n_tri;
-  if (valid) {
-    b1 = tri[3 * t] - 1;
-    b2 = tri[3 * t + 1] - 1;
-    b3 = tri[3 * t + 2] - 1;
-  }
-  const int npairs = (n_bins + 1) / 2;
-  const int64_t per = (npts + n_xr - 1) / n_xr;
-  const int64_t x0 = (int64_t)blockIdx.y * per;
-  const int64_t x1 = min(npts, x0 + per);
-  double ai = 0.0, aj = 0.0;
-  for (int64_t c0 = x0; c0 < x1; c0 += kTriXC) {
-    const int cl = (int)min((int64_t)kTriXC, x1 - c0);
-    for (int idx = threadIdx.x; idx < npairs * kTriXC; idx += blockDim.x) {
-      const int pr = idx / kTriXC, xo = idx % kTriXC;
-      float2 vi = make_float2(0.f, 0.f), vj = make_float2(0.f, 0.f);
-      if (xo < cl) {
-        vi = ip[(int64_t)pr * npts + c0 + xo];
-        vj = jp[(int64_t)pr * npts + c0 + xo];
-      }
-      fi[(2 * pr) * (kTriXC + 1) + xo] = vi.x;
-      fj[(2 * pr) * (kTriXC + 1) + xo] = vj.x;
-      if (2 * pr + 1 < n_bins) {
-        fi[(2 * pr + 1) * (kTriXC + 1) + xo] = vi.y;
-        fj[(2 * pr + 1) * (kTriXC + 1) + xo] = vj.y;
-      }
-    }
-    __syncthreads();
-    if (valid) {
-      const float* i1 = fi + b1 * (kTriXC + 1);
-      const float* i2 = fi + b2 * (kTriXC + 1);
-      const float* i3 = fi + b3 * (kTriXC + 1);
-      const float* j1 = fj + b1 * (kTriXC + 1);
-      const float* j2 = fj + b2 * (kTriXC + 1);
-      const float* j3 = fj + b3 * (kTriXC + 1);
-      float si = 0.f, sj = 0.f;
-      for (int xo = 0; xo < cl; ++xo) {
-        si += i1[xo] * i2[xo] * i3[xo];
-        sj += j1[xo] * j2[xo] * j3[xo];
-      }
-      ai += si;
-      aj += sj;
-    }
-    __syncthreads();
-  }
-  if (valid) {
-    part[((int64_t)blockIdx.y * n_tri + t) * 2] = ai;
-    part[((int64_t)blockIdx.y * n_tri + t) * 2 + 1] = aj;
-  }
-}
-
-hipError_t launch_triple_sums(int64_t npts, const float2* ipairs, const float2* jpairs, int n_bins,
-                              const int32_t* tri, int64_t n_tri, double* part, int n_xr,
-                              hipStream_t s) {
-  const unsigned tb = (unsigned)((n_tri + 255) / 256);
-  const size_t lds = sizeof(float) * 2 * (size_t)n_bins * (kTriXC + 1);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_triple, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL(k_triple, dim3(tb, n_xr), dim3(256), lds, s, npts, ipairs, jpairs, n_bins, tri,
-                     n_tri, part, n_xr);
-  return hipGetLastError();
-}
-
-__global__ void k_bispec_finalize(const double* __restrict__ part, int n_xr, int64_t n_tri, double vol,
-                                  double n3, double* bk, double* ntri) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tri) return;
-  double si = 0.0, sj = 0.0;
-  for (int i = 0; i < n_xr; ++i) {
-    si += part[((int64_t)i * n_tri + t) * 2];
-    sj += part[((int64_t)i * n_tri + t) * 2 + 1];
-  }
-  bk[t] = (sj > 0.5) ? vol * vol * si / sj : __builtin_nan("");
-  ntri[t] = sj / n3;
-}
-
-hipError_t launch_bispec_finalize(const double* part, int n_xr, int64_t n_tri, double vol, double n3,
-                                  double* bk, double* ntri, hipStream_t s) {
-  hipLaunchKernelGGL(k_bispec_finalize, dim3((unsigned)((n_tri + 255) / 256)), dim3(256), 0, s, part,
-                     n_xr, n_tri, vol, n3, bk, ntri);
   return hipGetLastError();
 }
 

@@ -124,7 +124,7 @@ class Estimator:
         tri = np.ascontiguousarray(np.asarray(triangles, dtype=np.int32).reshape(-1, 3))
         if n_bins is None:
             n_bins = int(tri.max())
-        nbytes = estimator_bispectrum_workspace_bytes(self.h, n_bins, len(tri))
+        nbytes = estimator_bispectrum_workspace_bytes(self.h, n_dk, n_bins, len(tri))
         buf, ptr = _aligned_workspace(nbytes, self.device)
         bk = torch.empty(len(tri), dtype=torch.float64, device=self.device)
         nt = torch.empty_like(bk)

@@ -118,3 +118,25 @@ def test_adjoint_matches_finite_differences(p, il):
             fd = (loss(xp)[0] - loss(xm)[0]) / (2 * h)
             scale = np.abs(grad).max()
             assert abs(fd - grad[j, ax]) < 1e-5 * scale + 1e-6 * abs(fd), (j, ax, fd, grad[j, ax])
+
+
+def test_band_brute_triplets_match_fft_shell_sums():
+    """oracle.bispectrum.brute_triplets (enumeration over a band of delta,
+    the reference of the full-size bispectrum spot checks) equals the
+    FFT-shell triple sums / N^3 and the counts of the J fields."""
+    n, box, n_dk, band = 24, 300.0, 2, 7
+    pos = synth.zeldovich(16, box, 9, dtype=np.float32)
+    delta, _ = spectrum.delta_half(pos, box, n, 4, True)
+    d_band = np.zeros((2 * band + 1, 2 * band + 1, band + 1), dtype=np.complex128)
+    for mx in range(-band, band + 1):
+        for my in range(-band, band + 1):
+            d_band[mx + band, my + band] = delta[mx % n, my % n, :band + 1]
+    tri = np.array([[1, 1, 1], [2, 1, 1], [2, 2, 1], [3, 2, 1], [3, 3, 2], [3, 3, 3]], dtype=np.int32)
+    cnt, s, a = bispectrum.brute_triplets(d_band, band, n_dk, tri)
+    masks = bispectrum.shell_masks(n, n_dk, 3)
+    fi = bispectrum.shell_fields(delta, masks, n)
+    fj = bispectrum.shell_fields(np.ones_like(delta), masks, n)
+    assert np.allclose(cnt, bispectrum.triple_sums(fj, tri) / n ** 3, rtol=0, atol=1e-6)
+    s_fft = bispectrum.triple_sums(fi, tri) / n ** 3
+    assert np.all(np.abs(s.imag) <= 1e-12 * a)
+    assert np.allclose(s.real, s_fft, rtol=1e-10, atol=1e-12 * np.max(a))
