@@ -64,9 +64,10 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(label, n_particles, n, nz, n_grids, nkeys):
-    """Bytes a kernel group must move per launch (float32 positions)."""
-    cells = n * n * nz
+def algorithmic_bytes(label, n_particles, n, nz, n_grids, nkeys, sets=1):
+    """Bytes a kernel group must move per launch (float32 positions, `sets`
+    particle sets of n^3 cells each)."""
+    cells = sets * n * n * nz
     return {
         # positions read twice (histogram, super-bucket pass); positions and
         # 8-byte cell records written and read once in super-bucket order and
@@ -74,16 +75,157 @@ def algorithmic_bytes(label, n_particles, n, nz, n_grids, nkeys):
         # offsets and counts written
         "bucket_sort": 84 * n_particles + 8 * nkeys,
         # positions read once, every grid written once
-        "deposit": 12 * n_particles + 4 * n_grids * n * n * n,
+        "deposit": 12 * n_particles + 4 * n_grids * sets * n * n * n,
         # complex grid read and written once per pass
         "fft_x": 16 * cells,
         "fft_y": 16 * cells,
         # complex grid read once (last-axis FFT, interlace, deconvolve, bin)
         "power_fused_z": 8 * cells,
+        # adjoint: forward z FFT, gradient spectrum and inverse z FFT of the
+        # grid read and written once; inverse y and x passes likewise
+        "adjoint_fused_z": 16 * cells,
+        "ifft_y": 16 * cells,
+        "ifft_x": 16 * cells,
+        # positions read, gradients written, every gradient grid read once
+        "gather_grad": 24 * n_particles + 4 * n_grids * sets * n * n * n,
     }.get(label)
 
 
-def headline(args, torch, F, est_mod, synth):
+def stage_rooflines(prof, bytes_of, copy_gbs):
+    """Per kernel group: ms per launch, fraction of the 8 TB/s HBM peak and
+    of the measured copy bandwidth for its algorithmic bytes; and the
+    dominant group's roofline entry."""
+    stages, frac, frac_copy = {}, {}, {}
+    dom = None
+    for name, (ms, cnt) in prof.items():
+        per = ms / cnt
+        stages[name] = round(per, 4)
+        b = bytes_of(name)
+        if b:
+            gbs = b / (per * 1e-3) / 1e9
+            frac[name] = round(gbs / PEAK_HBM_GBS, 4)
+            if copy_gbs:
+                frac_copy[name] = round(gbs / copy_gbs, 4)
+            if dom is None or per > dom[1]:
+                dom = (name, per, b, gbs)
+    roof = None
+    if dom:
+        name, per, b, gbs = dom
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                "frac_of_measured_copy": round(gbs / copy_gbs, 4) if copy_gbs else None,
+                "traffic": None, "algorithmic_bytes_per_launch": b, "ms_per_launch": round(per, 4)}
+    return stages, frac, frac_copy, roof
+
+
+def copy_bandwidth(torch, gib=2, reps=10):
+    """Device-to-device copy of `gib` GiB (read + write counted), HIP events on
+    the current stream, best of `reps`: the bandwidth a plain streaming
+    kernel reaches on this GPU."""
+    a = torch.ones(gib * 256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * a.numel() * 4 / (best * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("device copy: %.1f GB/s (%d GiB, best of %d)" % (gbs, gib, reps))
+    return gbs
+
+
+PEAK_FP32_MATRIX_TFLOPS = 157.3
+
+
+def closed_triangles(n_bins):
+    """Every (b1, b2, b3) with b1 >= b2 >= b3 >= 1 and b1 <= b2 + b3."""
+    out = []
+    for b1 in range(1, n_bins + 1):
+        for b2 in range(1, b1 + 1):
+            for b3 in range(max(1, b1 - b2), b2 + 1):
+                out.append((b1, b2, b3))
+    return np.array(out, dtype=np.int32)
+
+
+def bispectrum_mfma_work(tri, n_dk, n_bins):
+    """(M, jobs) of the library's bispectrum for these triangles: the
+    alias-free field grid (smallest 2^a 3^b 5^c above 3R, R the largest |m_a|
+    of the shells) and the 16x16 MFMA tiles (fixed b1 - b2; 16 consecutive
+    b2 by 16 consecutive b3) that cover the triangles."""
+    r = ((2 * n_bins + 1) * n_dk - 1) // 2
+    m = 3 * r + 1
+
+    def smooth(v):
+        for p in (2, 3, 5):
+            while v % p == 0:
+                v //= p
+        return v == 1
+
+    while not smooth(m):
+        m += 1
+    d = tri[:, 0] - tri[:, 1]
+    bs = np.maximum(d, 1)
+    keys = (d.astype(np.int64) * 64 + (tri[:, 1] - bs) // 16) * 64 + (tri[:, 2] - bs) // 16
+    return m, len(np.unique(keys))
+
+
+def bispectrum_leg(args, torch, F, est, n_dk=2, n_bins=128, copy_gbs=None):
+    """FFT-shell bispectrum of the headline workload (the handle has just
+    transformed it): 128 shells of 2 k_f up to k_N/2, every closed triangle.
+    The first call also sums the counts (sum JJJ), later calls reuse them.
+    Roofline: the MFMA triple sums (f32 16x16x4 tiles, flops the tiles
+    execute) against the FP32 matrix peak."""
+    tri = closed_triangles(n_bins)
+    m, njobs = bispectrum_mfma_work(tri, n_dk, n_bins)
+    nbytes = F.estimator_bispectrum_workspace_bytes(est.h, n_dk, n_bins, len(tri))
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (buf.data_ptr() + 255) // 256 * 256
+    bk = torch.empty(len(tri), dtype=torch.float64, device="cuda")
+    nt = torch.empty_like(bk)
+    times, profs = [], []
+    for it in range(3):
+        F.estimator_profile(est.h, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.estimator_bispectrum(est.h, 0, n_dk, n_bins, tri, len(tri), ptr, nbytes, bk, nt)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        F.estimator_profile(est.h, 0)
+        profs.append(F.profile_table(est.h))
+        log("bispectrum call %d: %.3f s" % (it, times[-1]))
+    del buf
+    torch.cuda.empty_cache()
+    cached = profs[-1]
+    tri_ms = cached["bispec_triple"][0]
+    passes = 1  # the cached calls sum the delta fields only
+    mfma_flops = 2.0 * njobs * 256 * float(m) ** 3 * passes
+    useful_flops = 2.0 * len(tri) * float(m) ** 3 * passes
+    achieved = mfma_flops / (tri_ms * 1e-3) / 1e12
+    return {"value": round(times[-1], 3), "unit": "s per call (count sums reused)",
+            "first_call_s": round(times[0], 3), "calls_s": [round(t, 3) for t in times],
+            "stage_ms_cached_call": {k: round(v[0], 2) for k, v in cached.items()},
+            "stage_ms_first_call": {k: round(v[0], 2) for k, v in profs[0].items()},
+            "field_grid": m, "mfma_tiles": njobs, "n_triangles": len(tri),
+            "useful_gflops": round(useful_flops / times[-1] / 1e9, 1),
+            "roofline": {"bound": "mfma", "kernel": "k_bs_triple (f32 16x16x4)",
+                         "achieved": round(achieved, 2), "peak": PEAK_FP32_MATRIX_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MATRIX_TFLOPS, 4),
+                         "traffic": None,
+                         "flops_per_call": mfma_flops, "ms_per_call": round(tri_ms, 2)},
+            "config": {"workload": "FFT-shell bispectrum of the headline particles on the 1024^3 "
+                                   "grid: 128 shells of 2 k_f (to k_N/2), all %d closed triangles; "
+                                   "fields on the alias-free %d^3 grid" % (len(tri), m),
+                       "n_dk": n_dk, "n_bins": n_bins}}
+
+
+def headline(args, torch, F, est_mod, synth, copy_gbs=None):
     n_side, box, n = 512, 2000.0, 1024
     t0 = time.time()
     pos_h = synth.zeldovich(n_side, box, 3, dtype=np.float32)
@@ -135,11 +277,13 @@ def headline(args, torch, F, est_mod, synth):
     bytes_per = algorithmic_bytes(name, npart, n, n, 2, nkeys)
     achieved = bytes_per / (per_launch_ms * 1e-3) / 1e9
     stages = {kname: round(v[0] / v[1], 4) for kname, v in prof.items()}
-    roof_all = {}
+    roof_all, roof_copy = {}, {}
     for kname, (kms, kcnt) in prof.items():
         b = algorithmic_bytes(kname, npart, n, n, 2, nkeys)
         if b:
             roof_all[kname] = round(b / (kms / kcnt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+            if copy_gbs:
+                roof_copy[kname] = round(b / (kms / kcnt * 1e-3) / 1e9 / copy_gbs, 4)
     result = {
         "value": npart * args.steps / dt / 1e6,
         "ms_per_step": 1e3 * dt / args.steps,
@@ -148,19 +292,24 @@ def headline(args, torch, F, est_mod, synth):
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(name, "pcs_il_n1024_za512"),
                      "algorithmic_bytes_per_launch": bytes_per,
-                     "ms_per_launch": round(per_launch_ms, 4)},
+                     "ms_per_launch": round(per_launch_ms, 4),
+                     "measured_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs else None},
         "stage_ms": stages,
         "stage_hbm_frac": roof_all,
+        "stage_copy_frac": roof_copy,
         "launch_choice": choice,
         "p_first_bins": [float(x) for x in pk[0, :4].cpu().numpy()],
     }
+    if not args.no_bispectrum:
+        result["bispectrum"] = bispectrum_leg(args, torch, F, est, copy_gbs=copy_gbs)
     est.close()
     del pos
     torch.cuda.empty_cache()
     return result
 
 
-def batched(args, torch, F, est_mod, synth):
+def batched(args, torch, F, est_mod, synth, copy_gbs=None):
     box, n, n_mocks = 500.0, 128, 64
     t0 = time.time()
     pos_h, offs_h = synth.mocks(n_mocks, box, 100)
@@ -181,16 +330,39 @@ def batched(args, torch, F, est_mod, synth):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log("batched: %.3f ms per graph replay" % (1e3 * dt / args.steps))
+    # stage breakdown: the same three calls made directly (events are not
+    # recorded inside a captured graph)
+    k = torch.empty((n_mocks, n // 2), dtype=torch.float64, device="cuda")
+    pk = torch.empty_like(k)
+    nm = torch.empty((n_mocks, n // 2), dtype=torch.int64, device="cuda")
+    F.estimator_profile(est.h, 1)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        F.estimator_deposit(est.h, pos, F.EST_F32, offs, npart)
+        F.estimator_transform(est.h)
+        F.estimator_power(est.h, 1, n // 2, 0, k, pk, nm)
+    torch.cuda.synchronize()
+    dt_direct = time.perf_counter() - t1
+    F.estimator_profile(est.h, 0)
+    prof = F.profile_table(est.h)
+    nkeys = n_mocks * (n // 4) ** 3 + 1
+    stages, frac, frac_copy, roof = stage_rooflines(
+        prof, lambda name: algorithmic_bytes(name, npart, n, n, 2, nkeys, sets=n_mocks), copy_gbs)
+    for name, ms in sorted(stages.items(), key=lambda kv: -kv[1]):
+        log("  batched %-14s %8.3f ms" % (name, ms))
     est.close()
     return {"value": npart * args.steps / dt / 1e6, "unit": "Mparticles/s",
             "ms_per_step": 1e3 * dt / args.steps, "autotune_choice": choice,
+            "ms_per_step_direct_calls": round(1e3 * dt_direct / args.steps, 4),
+            "stage_ms": stages, "stage_hbm_frac": frac, "stage_copy_frac": frac_copy,
+            "roofline": roof,
             "config": {"workload": "64 mocks, Poisson counts around log-uniform means in [1e5, 4e6] "
                                    "(even uniform, odd Zel'dovich), L=500, 128^3 grids, PCS + "
                                    "interlacing, one HIP graph replay per step",
                        "n_particles": npart}}
 
 
-def fwd_bwd(args, torch, F, est_mod, synth):
+def fwd_bwd(args, torch, F, est_mod, synth, copy_gbs=None):
     box, n, n_bins = 1000.0, 256, 128
     pos = torch.as_tensor(synth.zeldovich(128, box, 5, dtype=np.float32), device="cuda")
     tgt = torch.as_tensor(synth.zeldovich(128, box, 6, dtype=np.float32), device="cuda")
@@ -215,9 +387,28 @@ def fwd_bwd(args, torch, F, est_mod, synth):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log("fwd+bwd: %.3f ms per step" % (1e3 * dt / args.steps))
+    # stage breakdown (forward and adjoint kernel groups) over as many steps
+    F.estimator_profile(est.h, 1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    F.estimator_profile(est.h, 0)
+    prof = F.profile_table(est.h)
+    nkeys = (n // 4) ** 3 + 1
+    # per launch (groups such as the sort and deposit run twice per step:
+    # forward and the adjoint's recomputation)
+    per_launch = {name: (ms / cnt, 1) for name, (ms, cnt) in prof.items()}
+    _, frac, frac_copy, roof = stage_rooflines(
+        per_launch, lambda name: algorithmic_bytes(name, npart, n, n, 2, nkeys), copy_gbs)
+    stages = {name: round(ms / args.steps, 4) for name, (ms, cnt) in prof.items()}
+    launches = {name: int(cnt) // args.steps for name, (ms, cnt) in prof.items()}
+    for name, ms in sorted(stages.items(), key=lambda kv: -kv[1]):
+        log("  fwd+bwd %-16s %8.3f ms per step (%d launches)" % (name, ms, launches[name]))
     est.close()
     return {"value": npart * args.steps / dt / 1e6, "unit": "Mparticles/s",
             "ms_per_step": 1e3 * dt / args.steps,
+            "stage_ms_per_step": stages, "stage_launches_per_step": launches,
+            "stage_hbm_frac": frac, "stage_copy_frac": frac_copy, "roofline": roof,
             "config": {"workload": "128^3 Zel'dovich particles, L=1000, 256^3 grid, PCS + interlacing, "
                                    "chi^2 loss of 128 P(k) bins vs a second seed, forward + adjoint",
                        "n_particles": npart}}
@@ -424,23 +615,27 @@ def bias_experiment(torch, est_mod, synth, n_side=192, n=128, box=1000.0):
 
 
 def cpu_baseline():
-    """The FP64 oracle on a bounded sample: the same kind of workload at 1/64 size."""
+    """The FP64 oracle on the 256^3 configuration: 256^3 Zel'dovich particles
+    (L = 1000), 256^3 grid, PCS + interlacing, P(k) in k_f shells to Nyquist;
+    one run (about 20-30 s of CPU work)."""
     import oracle
     import synth
     workers = len(os.sched_getaffinity(0))
-    pos = synth.zeldovich(128, 500.0, 3, dtype=np.float32)
-    reps = 3
+    try:
+        ram_gb = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 1e9
+    except (ValueError, OSError):
+        ram_gb = None
+    pos = synth.zeldovich(256, 1000.0, 2, dtype=np.float32)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.power(pos, 500.0, 256, 4, True, 1, 128, workers=workers)
-    dt = (time.perf_counter() - t0) / reps
-    log("cpu oracle sample: %.1f s" % dt)
+    oracle.power(pos, 1000.0, 256, 4, True, 1, 128, workers=workers)
+    dt = time.perf_counter() - t0
+    log("cpu oracle, 256^3 particles on 256^3: %.1f s" % dt)
     return {"value": round(len(pos) / dt / 1e6, 4), "unit": "Mparticles/s", "cores": workers,
-            "kind": "oracle",
-            "sample": "128^3 Zel'dovich particles (L=500) on a 256^3 grid, PCS + interlacing, "
-                      "P(k) to Nyquist: 1/64 of the headline particles and cells at the same "
-                      "cell size; FP64 numpy deposit on one core, scipy FFT on %d threads; "
-                      "mean of %d runs, %.1f s each" % (workers, reps, dt)}
+            "kind": "oracle", "host_ram_gb": round(ram_gb, 1) if ram_gb else None,
+            "sample": "the 256^3 configuration: 256^3 Zel'dovich particles (L=1000) on a 256^3 "
+                      "grid, PCS + interlacing, P(k) in k_f shells to Nyquist (1/8 of the "
+                      "headline particles, 1/64 of its cells); FP64 numpy deposit on one core, "
+                      "scipy FFT on %d threads; one run of %.1f s" % (workers, dt)}
 
 
 def main():
@@ -450,6 +645,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bispectrum", action="store_true", help="skip the bispectrum leg")
     ap.add_argument("--launch-choice", type=int, default=None,
                     help="headline launch shapes (0..47) instead of autotuning them")
     ap.add_argument("--bias", action="store_true",
@@ -485,8 +681,8 @@ def main():
         bias_experiment(torch, est_mod, synth)
         return
     if args.leg:
-        legs = {"batched": lambda: batched(args, torch, F, est_mod, synth),
-                "fwd_bwd": lambda: fwd_bwd(args, torch, F, est_mod, synth),
+        legs = {"batched": lambda: batched(args, torch, F, est_mod, synth, copy_bandwidth(torch)),
+                "fwd_bwd": lambda: fwd_bwd(args, torch, F, est_mod, synth, copy_bandwidth(torch)),
                 "direct_sum": lambda: direct_leg(args, torch, est_mod, synth),
                 "paper_za_480": lambda: paper_za_leg(args, torch, F, est_mod, synth),
                 "variants": lambda: variants_leg(args, torch, F, est_mod, synth),
@@ -494,11 +690,14 @@ def main():
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
         return
 
-    head = headline(args, torch, F, est_mod, synth)
+    copy_gbs = copy_bandwidth(torch)
+    head = headline(args, torch, F, est_mod, synth, copy_gbs)
     extra = {}
+    if "bispectrum" in head:
+        extra["bispectrum"] = head.pop("bispectrum")
     if not args.no_extra:
-        extra["batched"] = batched(args, torch, F, est_mod, synth)
-        extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth)
+        extra["batched"] = batched(args, torch, F, est_mod, synth, copy_gbs)
+        extra["fwd_bwd"] = fwd_bwd(args, torch, F, est_mod, synth, copy_gbs)
         extra["direct_sum"] = direct_leg(args, torch, est_mod, synth)
         extra["paper_za_480"] = paper_za_leg(args, torch, F, est_mod, synth)
         extra["variants"] = variants_leg(args, torch, F, est_mod, synth)
@@ -524,6 +723,8 @@ def main():
         "roofline": head["roofline"],
         "stage_ms": head["stage_ms"],
         "stage_hbm_frac": head["stage_hbm_frac"],
+        "stage_copy_frac": head["stage_copy_frac"],
+        "measured_copy_gbs": round(copy_gbs, 1),
         "launch_choice": head["launch_choice"],
     }
     out.update(extra)

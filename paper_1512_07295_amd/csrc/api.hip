@@ -46,11 +46,12 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 enum ProfLabel {
   kPSort = 0, kPDeposit, kPFftX, kPFftY, kPFftZ, kPPower, kPAdjoint, kPIfftY, kPIfftX, kPGather,
-  kPModes, kPBispec, kPDirect, kPNumLabels
+  kPModes, kPBispec, kPDirect, kPBsFields, kPBsTriple, kPNumLabels
 };
 static const char* kProfNames[kPNumLabels] = {
     "bucket_sort", "deposit", "fft_x", "fft_y", "fft_z", "power_fused_z", "adjoint_fused_z",
-    "ifft_y", "ifft_x", "gather_grad", "mode_table", "bispectrum", "direct_sum"};
+    "ifft_y", "ifft_x", "gather_grad", "mode_table", "bispectrum", "direct_sum",
+    "bispec_fields", "bispec_triple"};
 
 struct ProfRec {
   double total_ms = 0.0;
@@ -506,7 +507,6 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
   if (!bs_plan(g.n, n_dk, n_bins, njobs, n_tri, &pl))
     return fail(EST_EUNSUPPORTED, "no alias-free field grid for these shells");
   if ((st = to_spectrum(h))) return st;
-  ProfScope ps(h, kPBispec);
   char* base = (char*)bws;
   double* run_i = (double*)(base + pl.off_run);
   double* run_j = run_i + njobs * 256;
@@ -515,10 +515,27 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
       (st = dev_err(hipMemcpyAsync(base + pl.off_tmap, tmap.data(), tmap.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, h->stream), "copy triangle map")))
     return st;
-  if ((st = dev_err(launch_bs_setup(g, h->b, mock, n_dk, n_bins, pl, base, h->stream), "delta cube")))
-    return st;
-  if ((st = dev_err(launch_bs_sums(n_dk, n_bins, pl, base, false, run_i, h->stream), "triple sums")))
-    return st;
+  {
+    ProfScope ps(h, kPBispec);
+    if ((st = dev_err(launch_bs_setup(g, h->b, mock, n_dk, n_bins, pl, base, h->stream), "delta cube")))
+      return st;
+  }
+  // slab by slab: the fields, then their triple sums
+  auto sums = [&](bool counts, double* run) -> est_status {
+    for (int sl = 0; sl < pl.nslab; ++sl) {
+      est_status e;
+      {
+        ProfScope ps(h, kPBsFields);
+        if ((e = dev_err(launch_bs_fields(n_dk, n_bins, pl, base, counts, sl, h->stream), "shell fields")))
+          return e;
+      }
+      ProfScope ps(h, kPBsTriple);
+      if ((e = dev_err(launch_bs_triple(n_bins, pl, base, sl == 0, run, h->stream), "triple sums")))
+        return e;
+    }
+    return EST_OK;
+  };
+  if ((st = sums(false, run_i))) return st;
   // the counts' sums depend only on the grid M, the shells and the jobs:
   // computed on the first call and kept by the handle
   const bool cached = h->bs_M == pl.M && h->bs_dk == n_dk && h->bs_nbins == n_bins &&
@@ -529,8 +546,7 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
       return st;
   } else {
     h->bs_M = 0;
-    if ((st = dev_err(launch_bs_sums(n_dk, n_bins, pl, base, true, run_j, h->stream), "count sums")))
-      return st;
+    if ((st = sums(true, run_j))) return st;
     std::vector<double> runj((size_t)njobs * 256);
     if ((st = dev_err(hipMemcpyAsync(runj.data(), run_j, runj.size() * sizeof(double),
                                      hipMemcpyDeviceToHost, h->stream), "keep counts")) ||
@@ -542,9 +558,12 @@ est_status estimator_bispectrum(est_handle h, int32_t mock, int32_t n_dk, int32_
     h->bs_dk = n_dk;
     h->bs_nbins = n_bins;
   }
-  if ((st = dev_err(launch_bs_finalize(pl, base, n_tri, g.box * g.box * g.box, bk, ntri, h->stream),
-                    "bispectrum")))
-    return st;
+  {
+    ProfScope ps(h, kPBispec);
+    if ((st = dev_err(launch_bs_finalize(pl, base, n_tri, g.box * g.box * g.box, bk, ntri, h->stream),
+                      "bispectrum")))
+      return st;
+  }
   // the host job and triangle buffers must outlive their copies
   return dev_err(hipStreamSynchronize(h->stream), "synchronize");
 }

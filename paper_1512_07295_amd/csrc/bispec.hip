@@ -429,38 +429,42 @@ static hipError_t triple_t(const BsPlan& pl, const float2* slab, int n_bins, con
   return hipGetLastError();
 }
 
-hipError_t launch_bs_sums(int n_dk, int n_bins, const BsPlan& pl, char* bws, bool counts,
-                          double* run, hipStream_t s) {
+hipError_t launch_bs_fields(int n_dk, int n_bins, const BsPlan& pl, char* bws, bool counts, int slab_index,
+                            hipStream_t s) {
   const float2* tw = (const float2*)(bws + pl.off_tw);
   const float2* band = (const float2*)(bws + pl.off_band);
   float2* slab = (float2*)(bws + pl.off_slab);
+  const int M = pl.M, R = pl.R;
+  const int64_t plane = (int64_t)M * M;
+  const int64_t xthreads = (int64_t)pl.Q * plane;
+  hipLaunchKernelGGL(k_bs_xdft, dim3((unsigned)((xthreads + 255) / 256)), dim3(256), 0, s, band, R, M,
+                     pl.S, slab_index * pl.S, pl.Q, n_dk, n_bins, counts ? 1 : 0, tw, slab);
+  // inverse z transforms of the rows that carry data (|m_y| <= R), then y
+  const int64_t planes = (int64_t)pl.Q * pl.S;
+  hipError_t e = launch_fft_rows_len(M, slab, planes * (R + 1), R + 1, plane, +1, tw, s);
+  if (e != hipSuccess) return e;
+  if (R > 0 &&
+      (e = launch_fft_rows_len(M, slab + (int64_t)(M - R) * M, planes * R, R, plane, +1, tw, s)) !=
+          hipSuccess)
+    return e;
+  return launch_fft_cols_len(M, slab, M, M, planes, plane, +1, 16, tw, s);
+}
+
+hipError_t launch_bs_triple(int n_bins, const BsPlan& pl, char* bws, bool first_slab, double* run,
+                            hipStream_t s) {
+  const float2* slab = (const float2*)(bws + pl.off_slab);
   const int32_t* jobs = (const int32_t*)(bws + pl.off_jobs);
   double* part = (double*)(bws + pl.off_part);
   const int64_t entries = pl.njobs * 256;
-  hipError_t e = launch_fill_u32((uint32_t*)run, (size_t)entries * 2, 0u, s);
+  hipError_t e = hipSuccess;
+  if (first_slab && (e = launch_fill_u32((uint32_t*)run, (size_t)entries * 2, 0u, s)) != hipSuccess)
+    return e;
+  if (pl.pc == 64) e = triple_t<64>(pl, slab, n_bins, jobs, part, s);
+  else if (pl.pc == 32) e = triple_t<32>(pl, slab, n_bins, jobs, part, s);
+  else e = triple_t<16>(pl, slab, n_bins, jobs, part, s);
   if (e != hipSuccess) return e;
-  const int M = pl.M, R = pl.R;
-  const int64_t plane = (int64_t)M * M;
-  for (int sl = 0; sl < pl.nslab; ++sl) {
-    const int64_t xthreads = (int64_t)pl.Q * plane;
-    hipLaunchKernelGGL(k_bs_xdft, dim3((unsigned)((xthreads + 255) / 256)), dim3(256), 0, s, band, R,
-                       M, pl.S, sl * pl.S, pl.Q, n_dk, n_bins, counts ? 1 : 0, tw, slab);
-    // inverse z transforms of the rows that carry data (|m_y| <= R), then y
-    const int64_t planes = (int64_t)pl.Q * pl.S;
-    if ((e = launch_fft_rows_len(M, slab, planes * (R + 1), R + 1, plane, +1, tw, s)) != hipSuccess)
-      return e;
-    if (R > 0 &&
-        (e = launch_fft_rows_len(M, slab + (int64_t)(M - R) * M, planes * R, R, plane, +1, tw, s)) !=
-            hipSuccess)
-      return e;
-    if ((e = launch_fft_cols_len(M, slab, M, M, planes, plane, +1, 16, tw, s)) != hipSuccess) return e;
-    if (pl.pc == 64) e = triple_t<64>(pl, slab, n_bins, jobs, part, s);
-    else if (pl.pc == 32) e = triple_t<32>(pl, slab, n_bins, jobs, part, s);
-    else e = triple_t<16>(pl, slab, n_bins, jobs, part, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bs_reduce, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, part,
-                       entries, pl.nranges, run);
-  }
+  hipLaunchKernelGGL(k_bs_reduce, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, part,
+                     entries, pl.nranges, run);
   return hipGetLastError();
 }
 

@@ -217,9 +217,12 @@ void bs_jobs(const int32_t* tri, int64_t n_tri, std::vector<int32_t>& jobs,
 // twiddles of length M and the cube of delta(m), |m_a| <= R
 hipError_t launch_bs_setup(const Geom& g, const Buffers& b, int mock, int n_dk, int n_bins,
                            const BsPlan& pl, char* bws, hipStream_t s);
-// per-entry sums over every slab (delta fields, or the counts when `counts`)
-hipError_t launch_bs_sums(int n_dk, int n_bins, const BsPlan& pl, char* bws, bool counts,
-                          double* run, hipStream_t s);
+// the fields of slab `slab_index` (delta, or the counts when `counts`)
+hipError_t launch_bs_fields(int n_dk, int n_bins, const BsPlan& pl, char* bws, bool counts,
+                            int slab_index, hipStream_t s);
+// the slab's triple sums added to run (run cleared first for the first slab)
+hipError_t launch_bs_triple(int n_bins, const BsPlan& pl, char* bws, bool first_slab, double* run,
+                            hipStream_t s);
 hipError_t launch_bs_finalize(const BsPlan& pl, char* bws, int64_t n_tri, double vol, double* bk,
                               double* ntri, hipStream_t s);
 
