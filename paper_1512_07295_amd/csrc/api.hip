@@ -199,14 +199,12 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   const size_t nkeys = batch * (size_t)g.nb * g.nb * g.nb + 1;
   Buffers bb;
   bb.grid = (float2*)take(batch * g.npair * n * (size_t)g.ps * sizeof(float2));
-  bb.sorted = take((size_t)c.max_particles * 3 * sizeof(double));
-  bb.cells = (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t));
+  bb.recs = (uint4*)take((size_t)c.max_particles * sizeof(uint4));
   bb.rank = (uint32_t*)take((size_t)c.max_particles * sizeof(uint32_t));
   bb.boff = (uint32_t*)take(nkeys * sizeof(uint32_t));
   bb.bcnt = (uint32_t*)take(nkeys * sizeof(uint32_t));
   const bool two_level = g.nsup <= kMaxSuper;
-  bb.tpos = two_level ? take((size_t)c.max_particles * 3 * sizeof(double)) : nullptr;
-  bb.trec = two_level ? (uint64_t*)take((size_t)c.max_particles * sizeof(uint64_t)) : nullptr;
+  bb.trecs = two_level ? (uint4*)take((size_t)c.max_particles * sizeof(uint4)) : nullptr;
   const size_t nh = two_level ? (size_t)g.nsup * kMaxSortBlocks + 1 : 0;
   bb.hsup = two_level ? (uint32_t*)take(nh * sizeof(uint32_t)) : nullptr;
   const size_t nscan = nkeys > nh ? nkeys : nh;
@@ -301,7 +299,7 @@ est_status run_deposit(est_handle h, const void* pos, est_dtype dt, const int64_
     if (st) return st;
   }
   ProfScope ps(h, kPDeposit);
-  return dev_err(launch_deposit(h->g, dt, h->b, h->tu, h->weights != nullptr, h->stream), "deposit");
+  return dev_err(launch_deposit(h->g, h->b, h->tu, h->weights != nullptr, h->stream), "deposit");
 }
 
 est_status run_xy(est_handle h, int dir) {

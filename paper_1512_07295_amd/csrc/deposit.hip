@@ -105,25 +105,6 @@ struct DepRanges {
   int count;
 };
 
-// First cell of the p-point stencil along one axis (not wrapped) and its
-// weights times `scale`, for grid coordinate u (the cell choice of
-// stencil_1d, whose weights these are).
-template <int P>
-__device__ __forceinline__ int stencil_first(double u, float scale, float (&w)[P]) {
-  int cell[P];
-  stencil_1d<P>(u, 1 << 30, cell, w);
-  const double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
-#pragma unroll
-  for (int i = 0; i < P; ++i) w[i] *= scale;
-  return (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
-}
-
-template <int P>
-__device__ __forceinline__ int first_cell(double u) {
-  const double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
-  return (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
-}
-
 // Position of a stencil's first cell relative to the tile origin t0, mod N.
 // For a tile smaller than the grid the result lies in [-(P-1), n - P + 1)
 // and the stencil reaches the tile's LDS block iff it is < kTileMax (which
@@ -160,17 +141,25 @@ __device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
   return (rx * kPlane + ry * kRow + rz + zhalo<P>()) & 63;
 }
 
-// Adds one grid's footprint of one particle to the tile.
+// Adds one grid's footprint of one particle (its record, particles.hpp) to
+// the tile.  Grid gi is sampled at u + 1/2 on the axes whose bit is set in
+// its mask mk: there the first cell moves by the record's step and the
+// offset by -/+ 1/2.
 template <int P, typename AT, int WRAP>
-__device__ __forceinline__ void deposit_item(double x, double y, double z, int gi, const Geom& g,
-                                             int t0x, int t0y, int t0z, AT* sm, float scale,
-                                             int mk) {
+__device__ __forceinline__ void deposit_item(uint4 rec, int gi, const Geom& g, int t0x, int t0y,
+                                             int t0z, AT* sm, float scale, int mk) {
   const int n = g.n;
-  // grid gi is sampled at u + 1/2 on the axes whose bit is set in its mask mk
+  constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
+  const int sx = (int)((rec.x >> 30) & 1u), sy = (int)(rec.x >> 31), sz = (int)((rec.y >> 24) & 1u);
   float wx[P], wy[P], wz[P];
-  const int fx = stencil_first<P>(grid_coord(x, g.box, g.inv) + ((mk & 1) ? 0.5 : 0.0), scale, wx);
-  const int fy = stencil_first<P>(grid_coord(y, g.box, g.inv) + ((mk & 2) ? 0.5 : 0.0), 1.0f, wy);
-  const int fz = stencil_first<P>(grid_coord(z, g.box, g.inv) + ((mk & 4) ? 0.5 : 0.0), 1.0f, wz);
+  weights_from_offset<P>(record_offset<P>(rec.y, sx, (mk & 1) != 0), wx);
+  weights_from_offset<P>(record_offset<P>(rec.z, sy, (mk & 2) != 0), wy);
+  weights_from_offset<P>(record_offset<P>(rec.w, sz, (mk & 4) != 0), wz);
+#pragma unroll
+  for (int i = 0; i < P; ++i) wx[i] *= scale;
+  const int fx = (int)(rec.x & 1023u) - off + ((mk & 1) ? sx : 0);
+  const int fy = (int)((rec.x >> 10) & 1023u) - off + ((mk & 2) ? sy : 0);
+  const int fz = (int)((rec.x >> 20) & 1023u) - off + ((mk & 4) ? sz : 0);
   constexpr bool PERIODIC = WRAP == kPeriodic;
   const int rx = rel_first<P, WRAP>(fx, t0x, n);
   const int ry = rel_first<P, WRAP>(fy, t0y, n);
@@ -248,9 +237,8 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // with run-time masks (mask_a, mask_b) written to slab q of each set
 // CAP: registers capped at 64 (8 waves per SIMD) so that two 1024-thread
 // workgroups share a CU (two_groups_per_cu)
-template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT, bool CAP>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 1))) void k_deposit(const TP* __restrict__ sorted,
-                                                  const uint64_t* __restrict__ cells,
+template <int P, int IL, bool WIDE, int WRAP, bool WT, bool CAP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 1))) void k_deposit(const uint4* __restrict__ recs,
                                                   const uint32_t* __restrict__ boff,
                                                   const uint32_t* __restrict__ bcnt, float* grid,
                                                   Geom g, uint32_t* __restrict__ stats,
@@ -385,47 +373,38 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
       for (int e = threadIdx.x; e < m; e += nthreads)
         item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
       __syncthreads();
-      // lane l of virtual wave r takes item r + l W; each item's position
-      // is loaded one iteration ahead
+      // lane l of virtual wave r takes item r + l W; each item's record is
+      // loaded one iteration ahead
       const int W = (m + 63) >> 6;
       const int vend = 64 * W;
       int e_cur = -1;
-      TP px = 0, py = 0, pz = 0;
+      uint4 rc = make_uint4(0u, 0u, 0u, 0u);
       {
         const int v = threadIdx.x;
         const int p = (v >> 6) + (v & 63) * W;
         if (v < vend && p < m) {
           e_cur = item_order[p];
-          const int64_t jq = item_j[e_cur];
-          px = sorted[3 * jq + 0];
-          py = sorted[3 * jq + 1];
-          pz = sorted[3 * jq + 2];
+          rc = recs[item_j[e_cur]];
         }
       }
       for (int v = threadIdx.x; v < vend; v += nthreads) {
         const int vn = v + nthreads;
         const int pn = (vn >> 6) + (vn & 63) * W;
         int e_nxt = -1;
-        TP nx = 0, ny = 0, nz = 0;
+        uint4 rn = make_uint4(0u, 0u, 0u, 0u);
         if (vn < vend && pn < m) {
           e_nxt = item_order[pn];
-          const int64_t jq = item_j[e_nxt];
-          nx = sorted[3 * jq + 0];
-          ny = sorted[3 * jq + 1];
-          nz = sorted[3 * jq + 2];
+          rn = recs[item_j[e_nxt]];
         }
         if (e_cur >= 0) {
           float sc = scale;
           if constexpr (WT) sc *= sw[item_j[e_cur]];
           const int gi = item_meta[e_cur] >> 6;
           const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-          deposit_item<P, AT, WRAP>((double)px, (double)py, (double)pz, gi, g, t0x, t0y, t0z, sm,
-                                    sc, mk);
+          deposit_item<P, AT, WRAP>(rc, gi, g, t0x, t0y, t0z, sm, sc, mk);
         }
         e_cur = e_nxt;
-        px = nx;
-        py = ny;
-        pz = nz;
+        rc = rn;
       }
       __syncthreads();
     };
@@ -439,18 +418,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
     for (uint32_t rb = 0; rb < total; rb += kPre * nthreads) {
       uint32_t jj[kPre];
-      uint64_t rec[kPre];
+      uint2 rec[kPre];
 #pragma unroll
       for (int q = 0; q < kPre; ++q) {
         const uint32_t r0 = rb + q * nthreads;
         const uint32_t item = r0 + threadIdx.x;
         jj[q] = 0;
-        rec[q] = 0;
+        rec[q] = make_uint2(0u, 0u);
         if (r0 < total) {
           const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item);
           if (item < total) {
             jj[q] = rg.start[seg] + (item - rg.pref[seg]);
-            rec[q] = cells[jj[q]];
+            // cells and steps: the record's x word and the y word's step bit
+            rec[q] = *reinterpret_cast<const uint2*>(recs + jj[q]);
           }
         }
       }
@@ -469,16 +449,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           cls[gi] = 0;
         }
         if (item < total) {
-          const uint64_t r = rec[0];
-          const int cx = (int)(r & 0xFFFF) - off;
-          const int cy = (int)((r >> 16) & 0xFFFF) - off;
-          const int cz = (int)((r >> 32) & 0xFFFF) - off;
+          const uint2 r = rec[0];
+          const int cx = (int)(r.x & 1023u) - off;
+          const int cy = (int)((r.x >> 10) & 1023u) - off;
+          const int cz = (int)((r.x >> 20) & 1023u) - off;
 #pragma unroll
           for (int gi = 0; gi < NG; ++gi) {
             const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-            const int sx = (mk & 1) ? (int)((r >> 48) & 1) : 0;
-            const int sy = (mk & 2) ? (int)((r >> 49) & 1) : 0;
-            const int sz = (mk & 4) ? (int)((r >> 50) & 1) : 0;
+            const int sx = (mk & 1) ? (int)((r.x >> 30) & 1u) : 0;
+            const int sy = (mk & 2) ? (int)(r.x >> 31) : 0;
+            const int sz = (mk & 4) ? (int)((r.y >> 24) & 1u) : 0;
             const int rx = rel_first<P, WRAP>(cx + sx, t0x, n);
             const int ry = rel_first<P, WRAP>(cy + sy, t0y, n);
             const int rz = rel_first<P, WRAP>(cz + sz, t0z, n);
@@ -604,101 +584,93 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
 // order 4 with a tile smaller than the grid.  Measured at 1024^3 with 2^27
 // particles (PCS): 11.8 ms with two 512-thread workgroups per CU, 10.8 ms
 // with two of 1024.
-template <int P, int IL, typename TP, bool WIDE, int WRAP, bool WT>
+template <int P, int IL, bool WIDE, int WRAP, bool WT>
 __host__ __device__ constexpr bool two_groups_per_cu() {
-  return std::is_same<TP, float>::value && !WIDE && IL == 1 && !WT &&
-         (P <= 2 || (P == 4 && WRAP != kPeriodic));
+  return !WIDE && IL == 1 && !WT && (P <= 2 || (P == 4 && WRAP != kPeriodic));
 }
 
 // threads: 256, 512 or 1024 per deposit workgroup, or 0 for the kernel's
 // own choice (1024 where two_groups_per_cu, else 512)
-template <int P, int IL, typename TP, int WRAP, bool WT>
+template <int P, int IL, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
                            const float* sw, int q, int ma, int mb, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
-  constexpr bool kTwo = two_groups_per_cu<P, IL, TP, false, WRAP, WT>();
+  constexpr bool kTwo = two_groups_per_cu<P, IL, false, WRAP, WT>();
   if (narrow) {
     const int tn = threads ? threads : (kTwo ? 1024 : 512);
     bool capped = false;
     if constexpr (kTwo) {
       if (tn == 1024) {
-        hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT, true>), dim3((unsigned)ntiles),
-                           dim3(tn), 0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt,
-                           (float*)b.grid, g, b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+        hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, true>), dim3((unsigned)ntiles),
+                           dim3(tn), 0, s, (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g,
+                           b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
         capped = true;
       }
     }
     if (!capped)
-      hipLaunchKernelGGL((k_deposit<P, IL, TP, false, WRAP, WT, false>), dim3((unsigned)ntiles),
-                         dim3(tn), 0, s, (const TP*)b.sorted, b.cells, b.boff, b.bcnt,
-                         (float*)b.grid, g, b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+      hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, false>), dim3((unsigned)ntiles),
+                         dim3(tn), 0, s, (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g,
+                         b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
   }
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
   const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
-  hipLaunchKernelGGL((k_deposit<P, IL, TP, true, WRAP, WT, false>), dim3(wblocks),
-                     dim3(threads ? threads : 512), 0, s,
-                     (const TP*)b.sorted, b.cells, b.boff, b.bcnt, (float*)b.grid, g, b.stats,
-                     narrow ? 0 : 1, 1, 0, sw, q, ma, mb);
+  hipLaunchKernelGGL((k_deposit<P, IL, true, WRAP, WT, false>), dim3(wblocks),
+                     dim3(threads ? threads : 512), 0, s, (const uint4*)b.recs, b.boff, b.bcnt,
+                     (float*)b.grid, g, b.stats, narrow ? 0 : 1, 1, 0, sw, q, ma, mb);
 }
 
 template <int P, int IL, int WRAP>
-static void dispatch_deposit_w(const Geom& g, est_dtype dt, const Buffers& b, int threads,
-                               bool narrow, bool xcd, const float* sw, int q, int ma, int mb,
-                               hipStream_t s) {
-  if (sw) {
-    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
-    else deposit_launch<P, IL, double, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
-  } else {
-    if (dt == EST_F32) deposit_launch<P, IL, float, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
-    else deposit_launch<P, IL, double, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
-  }
+static void dispatch_deposit_w(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
+                               const float* sw, int q, int ma, int mb, hipStream_t s) {
+  if (sw) deposit_launch<P, IL, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
+  else deposit_launch<P, IL, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
 }
 
 template <int P, int IL>
-static void dispatch_deposit_t(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                               int threads, const float* sw, int q, int ma, int mb, hipStream_t s) {
+static void dispatch_deposit_t(const Geom& g, const Buffers& b, const Tune& tu, int threads,
+                               const float* sw, int q, int ma, int mb, hipStream_t s) {
   const bool narrow = tu.dep_narrow != 0;
   const bool xcd = tu.dep_xcd != 0;
   if (g.tile == g.n)
-    dispatch_deposit_w<P, IL, kPeriodic>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kPeriodic>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
   else if ((g.n & (g.n - 1)) == 0)
-    dispatch_deposit_w<P, IL, kMasked>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kMasked>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
   else
-    dispatch_deposit_w<P, IL, kGeneral>(g, dt, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kGeneral>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
 }
 
 template <int P>
-static void dispatch_deposit_p(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                               int threads, const float* sw, hipStream_t s) {
+static void dispatch_deposit_p(const Geom& g, const Buffers& b, const Tune& tu, int threads,
+                               const float* sw, hipStream_t s) {
   if (g.code == 0) {
-    dispatch_deposit_t<P, 0>(g, dt, b, tu, threads, sw, 0, 0, 0, s);
+    dispatch_deposit_t<P, 0>(g, b, tu, threads, sw, 0, 0, 0, s);
   } else if (g.code == 1) {
-    dispatch_deposit_t<P, 1>(g, dt, b, tu, threads, sw, 0, 0, 7, s);
+    dispatch_deposit_t<P, 1>(g, b, tu, threads, sw, 0, 0, 7, s);
   } else {
     // one pass per slab; the 64-bit kernel's tile counter restarts each time
     for (int q = 0; q < g.npair; ++q) {
       if (q > 0) launch_fill_u32(b.stats + 1, 1, 0u, s);
-      dispatch_deposit_t<P, 2>(g, dt, b, tu, threads, sw, q, grid_mask(g.code, 2 * q),
+      dispatch_deposit_t<P, 2>(g, b, tu, threads, sw, q, grid_mask(g.code, 2 * q),
                                grid_mask(g.code, 2 * q + 1), s);
     }
   }
 }
 
-hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                          bool weighted, hipStream_t s) {
+hipError_t launch_deposit(const Geom& g, const Buffers& b, const Tune& tu, bool weighted,
+                          hipStream_t s) {
   int threads = tu.dep_threads;
   if (threads != 256 && threads != 512 && threads != 1024) threads = 0;  // per kernel
   const float* sw = weighted ? b.sw : nullptr;
   switch (g.order) {
-    case 1: dispatch_deposit_p<1>(g, dt, b, tu, threads, sw, s); break;
-    case 2: dispatch_deposit_p<2>(g, dt, b, tu, threads, sw, s); break;
-    case 3: dispatch_deposit_p<3>(g, dt, b, tu, threads, sw, s); break;
-    case 4: dispatch_deposit_p<4>(g, dt, b, tu, threads, sw, s); break;
-    case 5: dispatch_deposit_p<5>(g, dt, b, tu, threads, sw, s); break;
-    default: dispatch_deposit_p<6>(g, dt, b, tu, threads, sw, s); break;
+    case 1: dispatch_deposit_p<1>(g, b, tu, threads, sw, s); break;
+    case 2: dispatch_deposit_p<2>(g, b, tu, threads, sw, s); break;
+    case 3: dispatch_deposit_p<3>(g, b, tu, threads, sw, s); break;
+    case 4: dispatch_deposit_p<4>(g, b, tu, threads, sw, s); break;
+    case 5: dispatch_deposit_p<5>(g, b, tu, threads, sw, s); break;
+    default: dispatch_deposit_p<6>(g, b, tu, threads, sw, s); break;
   }
   return hipGetLastError();
 }

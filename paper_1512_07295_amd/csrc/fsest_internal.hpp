@@ -69,13 +69,11 @@ __device__ __forceinline__ int64_t complex_index(const Geom& g, int mock, int x,
 // Work buffers carved out of the caller's workspace.
 struct Buffers {
   float2* grid;            // batch * N * N * nz complex (rho1 + i rho2, or packed reals)
-  void* sorted;            // max_particles * 3 * 8 bytes
-  uint64_t* cells;         // max_particles cell records (sorted order)
+  uint4* recs;             // max_particles 16-byte particle records, bucket order
   uint32_t* rank;          // max_particles
   uint32_t* boff;          // batch * nb^3 + 1 bucket start offsets (key order)
   uint32_t* bcnt;          // batch * nb^3 bucket counts
-  void* tpos;              // max_particles * 3 * 8 bytes: positions in super-bucket order
-  uint64_t* trec;          // max_particles cell records in super-bucket order
+  uint4* trecs;            // max_particles records in super-bucket order (two-level sort)
   uint32_t* hsup;          // kMaxSuper * kMaxSortBlocks + 1 histogram / offsets
   uint32_t* scan_tmp;      // scan block sums
   uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter,
@@ -142,9 +140,10 @@ hipError_t launch_weight_stats(const float* w, const int64_t* offsets, int64_t n
 // copy, divided by the largest mass, goes to b.sw
 hipError_t launch_sort(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,
                        int64_t n_total, const float* w, const Buffers& b, hipStream_t s);
-// weighted: read b.sw and scale the grids by the largest mass
-hipError_t launch_deposit(const Geom& g, est_dtype dt, const Buffers& b, const Tune& tu,
-                          bool weighted, hipStream_t s);
+// from the sort's records (any position type); weighted: read b.sw and
+// scale the grids by the largest mass
+hipError_t launch_deposit(const Geom& g, const Buffers& b, const Tune& tu, bool weighted,
+                          hipStream_t s);
 hipError_t launch_copy_grid(const Geom& g, const Buffers& b, int which, int mock, float* dst,
                             hipStream_t s);
 hipError_t launch_gather_grad(const Geom& g, const void* pos, est_dtype dt, const int64_t* offsets,

@@ -72,15 +72,12 @@ __device__ __forceinline__ void bspline_weights(float t, float (&w)[P], float (&
   for (int j = 0; j < P; ++j) w[j] = v[j];
 }
 
-// Cells (mod N) and weights of the p-point stencil of one axis, for grid
-// coordinate u (float64).  Even p: first cell floor(u) - (p/2 - 1); odd p:
-// first cell floor(u + 1/2) - (p-1)/2.  Weights are W^(p)(cell - u) of
-// Sec. 2.3 written per offset with f = u - floor(...).
+// Weights W^(p)(cell - u) of Sec. 2.3 of the p stencil cells along one axis,
+// written per offset f = u - floor(u) in [0, 1) for even p and
+// f = u - floor(u + 1/2) in [-1/2, 1/2) for odd p (the stencil's first cell
+// is floor(...) - (p/2 - 1), resp. - (p-1)/2).
 template <int P>
-__device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], float (&w)[P]) {
-  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
-  const int first = (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
-  const float f = (float)(u - fl);
+__device__ __forceinline__ void weights_from_offset(float f, float (&w)[P]) {
   if constexpr (P == 1) {
     w[0] = 1.0f;
   } else if constexpr (P == 2) {
@@ -102,12 +99,69 @@ __device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], floa
     float wd[P];
     bspline_weights<P>((P % 2 == 0) ? 1.0f - f : 0.5f - f, w, wd);
   }
+}
+
+// Cells (mod N) and weights of the p-point stencil of one axis, for grid
+// coordinate u (float64).  Even p: first cell floor(u) - (p/2 - 1); odd p:
+// first cell floor(u + 1/2) - (p-1)/2.
+template <int P>
+__device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], float (&w)[P]) {
+  double fl = (P % 2 == 0) ? floor(u) : floor(u + 0.5);
+  const int first = (int)fl - ((P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2);
+  weights_from_offset<P>((float)(u - fl), w);
   // first + i lies in [-(p-1), N + p - 1]
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int c = first + i;
     cell[i] = c < 0 ? c + n : (c >= n ? c - n : c);
   }
+}
+
+// ---- particle records
+// The sort writes one 16-byte record per particle, in bucket order, and the
+// deposit reads only these.  Per axis a: the first grid's floor cell c_a
+// (floor(u) for even p, floor(u + 1/2) for odd p; mod N), the step s_a from
+// it to the same floor on the grid sampled at u + 1/2 (0 or 1), and the
+// offset t_a = u - floor(...) (+ 1/2 for odd p), in [0, 1), as a 24-bit
+// fraction rounded to nearest: an error of at most 2^-25, that of a float32
+// offset in [1/2, 1).  Every cell choice is made on the float64 u.  Words:
+//   x: c_x | c_y << 10 | c_z << 20 | s_x << 30 | s_y << 31
+//   y: t_x | s_z << 24
+//   z: t_y | bits 24..31 free (the two-level sort keeps a bucket index there)
+//   w: t_z | bits 24..31 free
+constexpr int kFracBits = 24;
+constexpr uint32_t kFracMask = (1u << kFracBits) - 1u;
+
+__device__ __forceinline__ uint4 particle_record(double ux, double uy, double uz, const Geom& g) {
+  const bool even = (g.order % 2) == 0;
+  const double u[3] = {ux, uy, uz};
+  uint32_t cell[3], step[3], frac[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
+    const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
+    const double f2 = even ? floor(u2) : floor(u2 + 0.5);
+    const int c1 = (int)f1;  // in [0, N]
+    cell[a] = (uint32_t)(c1 >= g.n ? c1 - g.n : c1);
+    step[a] = (uint32_t)((int)(f2 - f1) & 1);
+    const double t = u[a] - f1 + (even ? 0.0 : 0.5);  // exact, in [0, 1)
+    const double q = floor(t * 16777216.0 + 0.5);
+    frac[a] = q > 16777215.0 ? kFracMask : (uint32_t)q;
+  }
+  return make_uint4(cell[0] | (cell[1] << 10) | (cell[2] << 20) | (step[0] << 30) | (step[1] << 31),
+                    frac[0] | (step[2] << 24), frac[1], frac[2]);
+}
+
+// the offset f (as in weights_from_offset) of one axis from its 24-bit
+// fraction t, on the grid sampled at u + 1/2 along this axis when `shifted`:
+// there t moves by -1/2 if the floor cell steps, by +1/2 if not (exact)
+template <int P>
+__device__ __forceinline__ float record_offset(uint32_t t, int step, bool shifted) {
+  int q = (int)(t & kFracMask);
+  if (shifted) q += step ? -(1 << (kFracBits - 1)) : (1 << (kFracBits - 1));
+  float f = (float)q * (1.0f / 16777216.0f);
+  if constexpr (P % 2 == 1) f -= 0.5f;
+  return f;
 }
 
 // derivative dW/ds of the same weights (s = cell - u)

@@ -5,8 +5,9 @@
 // (per-workgroup LDS histograms over super-buckets, a scan, a super-bucket
 // scatter, then one workgroup per super-bucket sorting its buckets in LDS);
 // a single-level counting sort with device-scope atomics is the fallback.
-// Every particle carries an 8-byte cell record (its floor cells and the
-// interlacing steps) so the deposit decides tile membership in integers.
+// The positions are read only here: the sorted output is one 16-byte record
+// per particle (particles.hpp: floor cells, interlacing steps and 24-bit
+// offsets), so the deposit does all its work in integers and float32.
 #include "particles.hpp"
 
 namespace fsest {
@@ -180,29 +181,19 @@ __global__ __launch_bounds__(kCountThreads) void k_bucket_count(
   if (key != kEmptyKey) rank[j] = hval[slot] + local;
 }
 
-// Cell record of one particle, used by the deposit to decide which tiles a
-// particle's stencils reach without redoing the float64 cell arithmetic:
-// bits 16a .. 16a+15 hold the first-grid floor cell along axis a (floor(u)
-// for even p, floor(u + 1/2) for odd p; mod N), bit 48 + a holds the step
-// from it to the same floor on the grid shifted by H/2 (0 or 1).
-// bits kRecFineShift.. carry a particle's bucket inside its super-bucket
-// between the two passes of the two-level sort
-constexpr int kRecFineShift = 52;
-
-__device__ __forceinline__ uint64_t cell_record(double ux, double uy, double uz, const Geom& g) {
-  const bool even = (g.order % 2) == 0;
-  const double u[3] = {ux, uy, uz};
-  uint64_t rec = 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
-    const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
-    const double f2 = even ? floor(u2) : floor(u2 + 0.5);
-    const int c1 = (int)f1;  // in [0, N]
-    rec |= (uint64_t)(c1 >= g.n ? c1 - g.n : c1) << (16 * a);
-    rec |= (uint64_t)((int)(f2 - f1) & 1) << (48 + a);
-  }
-  return rec;
+// The two-level sort carries a particle's bucket inside its super-bucket
+// (12 bits) between its two passes in the free upper bytes of the record's
+// z and w words.
+__device__ __forceinline__ uint4 with_fine(uint4 r, uint32_t fine) {
+  r.z |= (fine & 255u) << 24;
+  r.w |= (fine >> 8) << 24;
+  return r;
+}
+__device__ __forceinline__ uint32_t fine_of(uint4 r) { return (r.z >> 24) | ((r.w >> 24) << 8); }
+__device__ __forceinline__ uint4 without_fine(uint4 r) {
+  r.z &= kFracMask;
+  r.w &= kFracMask;
+  return r;
 }
 
 template <typename TP>
@@ -210,8 +201,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ p
                                                         const int64_t* __restrict__ offsets, Geom g,
                                                         const uint32_t* __restrict__ boff,
                                                         const uint32_t* __restrict__ rank,
-                                                        TP* __restrict__ sorted,
-                                                        uint64_t* __restrict__ cells,
+                                                        uint4* __restrict__ recs,
                                                         const float* __restrict__ w,
                                                         float* __restrict__ sw,
                                                         const uint32_t* __restrict__ stats) {
@@ -227,10 +217,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ p
   const int bz = base_cell(uz, g.n) / kBucket;
   const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
   const int64_t dst = (int64_t)boff[key] + rank[j];
-  sorted[3 * dst + 0] = px;
-  sorted[3 * dst + 1] = py;
-  sorted[3 * dst + 2] = pz;
-  cells[dst] = cell_record(ux, uy, uz, g);
+  recs[dst] = particle_record(ux, uy, uz, g);
   if (w) sw[dst] = scaled_mass(w, j, stats);
 }
 
@@ -337,12 +324,11 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
   if ((e = scan_in_place(b.boff, nkeys + 1, b.scan_tmp, b.stats, s)) != hipSuccess) return e;
   if (dt == EST_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3(pblocks), dim3(256), 0, s, (const float*)pos,
-                       n_total, offsets, g, b.boff, b.rank, (float*)b.sorted, b.cells, w, b.sw,
-                       b.stats);
+                       n_total, offsets, g, b.boff, b.rank, b.recs, w, b.sw, b.stats);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3(pblocks), dim3(256), 0, s,
-                       (const double*)pos, n_total, offsets, g, b.boff, b.rank,
-                       (double*)b.sorted, b.cells, w, b.sw, b.stats);
+                       (const double*)pos, n_total, offsets, g, b.boff, b.rank, b.recs, w, b.sw,
+                       b.stats);
   return hipGetLastError();
 }
 
@@ -354,8 +340,8 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
 // (C) each workgroup re-reads its chunk and moves every particle (position
 // and cell record) into its super-bucket segment, ranking with LDS
 // counters; (D) one workgroup per super-bucket counts its particles per
-// bucket, writes the bucket offsets and counts, and moves the particles into
-// bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
+// bucket, writes the bucket offsets and counts, and moves the records into
+// bucket order.  Pass (C) already writes records, not positions.  Buckets are therefore contiguous in z inside a super-bucket;
 // the deposit splits its bucket runs at super-bucket boundaries.
 constexpr int kSortThreads = 1024;
 constexpr int kSortBatch = 4;  // particles per thread whose loads are in flight together
@@ -409,8 +395,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict
 template <typename TP>
 __global__ __launch_bounds__(kSortThreads) void k_sort_super(
     const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
-    int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ tpos,
-    uint64_t* __restrict__ trec, const float* __restrict__ w, float* __restrict__ tw) {
+    int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, uint4* __restrict__ trec,
+    const float* __restrict__ w, float* __restrict__ tw) {
   __shared__ uint32_t cur[kMaxSuper];
   for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
     cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
@@ -440,22 +426,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
         const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
         const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
         const uint32_t p = atomicAdd(&cur[sup], 1u);
-        tpos[3 * (int64_t)p + 0] = px[q];
-        tpos[3 * (int64_t)p + 1] = py[q];
-        tpos[3 * (int64_t)p + 2] = pz[q];
-        trec[p] = cell_record(ux, uy, uz, g) | ((uint64_t)fine << kRecFineShift);
+        trec[p] = with_fine(particle_record(ux, uy, uz, g), fine);
         if (w) tw[p] = w[j];
       }
     }
   }
 }
 
-template <typename TP>
 __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
-    const TP* __restrict__ tpos, const uint64_t* __restrict__ trec, int64_t n_total, Geom g,
-    int nblk, const uint32_t* __restrict__ hoff, TP* __restrict__ sorted,
-    uint64_t* __restrict__ cells, uint32_t* __restrict__ boff, uint32_t* __restrict__ bcnt,
-    uint32_t* __restrict__ stats, const float* __restrict__ tw, float* __restrict__ sw) {
+    const uint4* __restrict__ trec, int64_t n_total, Geom g, int nblk,
+    const uint32_t* __restrict__ hoff, uint4* __restrict__ recs, uint32_t* __restrict__ boff,
+    uint32_t* __restrict__ bcnt, uint32_t* __restrict__ stats, const float* __restrict__ tw,
+    float* __restrict__ sw) {
   constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
   __shared__ uint32_t hist[kFineMax * kFineMax * kFineMax];
   __shared__ uint32_t wtot[kSortThreads / 64];
@@ -466,15 +448,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
   __syncthreads();
   for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
-    uint64_t r[kSortBatch];
+    uint32_t f[kSortBatch];
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q) {
       const uint32_t i = ib + q * kSortThreads;
-      r[q] = (i < seg1) ? trec[i] : 0ull;
+      // the bucket index sits in the top bytes of the z and w words
+      f[q] = (i < seg1) ? ((trec[i].z >> 24) | ((trec[i].w >> 24) << 8)) : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q)
-      if (ib + q * kSortThreads < seg1) atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
+      if (ib + q * kSortThreads < seg1) atomicAdd(&hist[f[q]], 1u);
   }
   __syncthreads();
   // exclusive scan of hist[0, nf): kPer consecutive buckets per thread
@@ -519,26 +502,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   }
   __syncthreads();
   for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
-    uint64_t r[kSortBatch];
-    TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
+    uint4 r[kSortBatch];
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q) {
       const uint32_t i = ib + q * kSortThreads;
-      if (i < seg1) {
-        r[q] = trec[i];
-        px[q] = tpos[3 * (int64_t)i + 0];
-        py[q] = tpos[3 * (int64_t)i + 1];
-        pz[q] = tpos[3 * (int64_t)i + 2];
-      }
+      if (i < seg1) r[q] = trec[i];
     }
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q) {
       if (ib + q * kSortThreads < seg1) {
-        const uint32_t p = seg0 + atomicAdd(&hist[(uint32_t)(r[q] >> kRecFineShift)], 1u);
-        sorted[3 * (int64_t)p + 0] = px[q];
-        sorted[3 * (int64_t)p + 1] = py[q];
-        sorted[3 * (int64_t)p + 2] = pz[q];
-        cells[p] = r[q] & ((1ull << kRecFineShift) - 1ull);
+        const uint32_t p = seg0 + atomicAdd(&hist[fine_of(r[q])], 1u);
+        recs[p] = without_fine(r[q]);
         if (tw) sw[p] = scaled_mass(tw, ib + q * kSortThreads, stats);
       }
     }
@@ -559,10 +533,10 @@ static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* of
   if ((e = scan_in_place(b.hsup, (size_t)g.nsup * nblk, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
-                     offsets, g, chunk, nblk, b.hsup, (TP*)b.tpos, b.trec, w, b.tw);
-  hipLaunchKernelGGL(k_sort_fine<TP>, dim3(g.nsup), dim3(kSortThreads), 0, s, (const TP*)b.tpos,
-                     b.trec, n_total, g, nblk, b.hsup, (TP*)b.sorted, b.cells, b.boff, b.bcnt,
-                     b.stats, w ? b.tw : nullptr, b.sw);
+                     offsets, g, chunk, nblk, b.hsup, b.trecs, w, b.tw);
+  hipLaunchKernelGGL(k_sort_fine, dim3(g.nsup), dim3(kSortThreads), 0, s, (const uint4*)b.trecs,
+                     n_total, g, nblk, b.hsup, b.recs, b.boff, b.bcnt, b.stats,
+                     w ? b.tw : nullptr, b.sw);
   return hipGetLastError();
 }
 
