@@ -378,6 +378,12 @@ est_status estimator_create(const est_config* cfg, void* workspace, size_t works
   layout(*cfg, (char*)workspace, &h->b, &h->tune_out);
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+        cus > 0)
+      h->tu.cus = cus;
+  }
   clear_stale_error();
   // device address of the static workspace of estimator_direct_delta_noalloc
   // (once per device)

@@ -48,6 +48,12 @@ __device__ __forceinline__ int narrow_bits(uint32_t maxcount) {
   return f;
 }
 
+// The 32-bit format's fraction bits for this deposit, once per deposit.
+template <int P>
+__global__ void k_narrow(uint32_t* stats) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) stats[6] = (uint32_t)narrow_bits<P>(stats[0]);
+}
+
 // LDS layout of a deposit workgroup, in 32-bit words:
 //   [0, kItemCap)            particle index of each work item
 //   [.., + kItemCap/4)       item meta bytes: bank class (6 bits) | grid << 6
@@ -227,10 +233,12 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // deposited with LDS integer atomics, lane l of
 // virtual wave r taking sorted item r + l * W (W = virtual waves in the
 // flush); (3) the finished tile is scaled back to float and written once.
-// `dynamic`: tiles are taken from a global counter (stats[1], zeroed with
-// the sort) instead of one tile per workgroup.  `xcd`: consecutive tiles go
-// to the same XCD (workgroup b runs on XCD b mod 8), so the buckets that
-// neighbouring tiles share are read through one L2.
+// Workgroups loop over tiles b, b + gridDim, ... (a persistent grid of a few
+// workgroups per CU, so the per-workgroup set-up is paid once per many
+// tiles); `dynamic`: tiles are taken from a global counter (stats[1], zeroed
+// with the sort) instead.  `xcd`: consecutive tiles go to the same XCD
+// (workgroup b runs on XCD b mod 8), so the buckets that neighbouring tiles
+// share are read through one L2.
 // WT: per-particle masses (sw, bucket order, divided by the largest mass);
 // a separate instantiation so that the equal-mass kernel keeps its registers
 // IL: 0 one grid; 1 the interlaced pair (masks 0 and 7); 2 a pair of grids
@@ -260,8 +268,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   AT* sm = reinterpret_cast<AT*>(smem);
   const int acc0 = acc_first_word<AT>() * 4 / (int)sizeof(AT);
 
-  // fixed-point format for this deposit (uniform over the grid)
-  const int nbits = narrow_bits<P>(stats[0]);
+  // fixed-point format for this deposit (uniform over the grid; k_narrow
+  // computed it from the sort's largest bucket count)
+  const int nbits = (int)stats[6];
   if (!WIDE && nbits < kNarrowMinBits) return;                // the wide kernel does it
   if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
   const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
@@ -277,7 +286,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   const int64_t ntiles = (int64_t)g.batch * tiles_per_set;
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool remap = xcd && !dynamic && (int64_t)gridDim.x == ntiles && (ntiles & 7) == 0;
+  // workgroup b runs on XCD b mod 8: with xcd, the tiles of XCD x are the
+  // x-th eighth, taken in order by its workgroups (gridDim a multiple of 8)
+  const bool remap = xcd && !dynamic && (gridDim.x & 7) == 0 && (ntiles & 7) == 0;
 
   int64_t b = blockIdx.x;
   if (dynamic) {
@@ -593,25 +604,29 @@ __host__ __device__ constexpr bool two_groups_per_cu() {
 // own choice (1024 where two_groups_per_cu, else 512)
 template <int P, int IL, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
-                           const float* sw, int q, int ma, int mb, hipStream_t s) {
+                           int cus, const float* sw, int q, int ma, int mb, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
   const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
   constexpr bool kTwo = two_groups_per_cu<P, IL, false, WRAP, WT>();
   if (narrow) {
     const int tn = threads ? threads : (kTwo ? 1024 : 512);
+    // a persistent grid: 8 workgroups per CU (a multiple of 8 for the XCD
+    // grouping), each looping over tiles
+    const int64_t cap = (int64_t)cus * 8;
+    const unsigned nwg = (unsigned)(ntiles < cap ? ntiles : cap);
     bool capped = false;
     if constexpr (kTwo) {
       if (tn == 1024) {
-        hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, true>), dim3((unsigned)ntiles),
-                           dim3(tn), 0, s, (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g,
-                           b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+        hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, true>), dim3(nwg), dim3(tn), 0, s,
+                           (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0, 0,
+                           xcd ? 1 : 0, sw, q, ma, mb);
         capped = true;
       }
     }
     if (!capped)
-      hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, false>), dim3((unsigned)ntiles),
-                         dim3(tn), 0, s, (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g,
-                         b.stats, 0, 0, xcd ? 1 : 0, sw, q, ma, mb);
+      hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, false>), dim3(nwg), dim3(tn), 0, s,
+                         (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0, 0,
+                         xcd ? 1 : 0, sw, q, ma, mb);
   }
   // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
@@ -624,9 +639,9 @@ static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool na
 
 template <int P, int IL, int WRAP>
 static void dispatch_deposit_w(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
-                               const float* sw, int q, int ma, int mb, hipStream_t s) {
-  if (sw) deposit_launch<P, IL, WRAP, true>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
-  else deposit_launch<P, IL, WRAP, false>(g, b, threads, narrow, xcd, nullptr, q, ma, mb, s);
+                               int cus, const float* sw, int q, int ma, int mb, hipStream_t s) {
+  if (sw) deposit_launch<P, IL, WRAP, true>(g, b, threads, narrow, xcd, cus, sw, q, ma, mb, s);
+  else deposit_launch<P, IL, WRAP, false>(g, b, threads, narrow, xcd, cus, nullptr, q, ma, mb, s);
 }
 
 template <int P, int IL>
@@ -635,16 +650,17 @@ static void dispatch_deposit_t(const Geom& g, const Buffers& b, const Tune& tu, 
   const bool narrow = tu.dep_narrow != 0;
   const bool xcd = tu.dep_xcd != 0;
   if (g.tile == g.n)
-    dispatch_deposit_w<P, IL, kPeriodic>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kPeriodic>(g, b, threads, narrow, xcd, tu.cus, sw, q, ma, mb, s);
   else if ((g.n & (g.n - 1)) == 0)
-    dispatch_deposit_w<P, IL, kMasked>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kMasked>(g, b, threads, narrow, xcd, tu.cus, sw, q, ma, mb, s);
   else
-    dispatch_deposit_w<P, IL, kGeneral>(g, b, threads, narrow, xcd, sw, q, ma, mb, s);
+    dispatch_deposit_w<P, IL, kGeneral>(g, b, threads, narrow, xcd, tu.cus, sw, q, ma, mb, s);
 }
 
 template <int P>
 static void dispatch_deposit_p(const Geom& g, const Buffers& b, const Tune& tu, int threads,
                                const float* sw, hipStream_t s) {
+  hipLaunchKernelGGL(k_narrow<P>, dim3(1), dim3(64), 0, s, b.stats);
   if (g.code == 0) {
     dispatch_deposit_t<P, 0>(g, b, tu, threads, sw, 0, 0, 0, s);
   } else if (g.code == 1) {

@@ -78,7 +78,8 @@ struct Buffers {
   uint32_t* scan_tmp;      // scan block sums
   uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter,
                            // [4] largest mass (float bits), [5] nonzero if a mass is
-                           // negative or not finite
+                           // negative or not finite, [6] fraction bits of the
+                           // deposit's 32-bit fixed point
   float2* tw_n;            // exp(-2 pi i n / N)
   float2* tw_nz;           // exp(-2 pi i n / nz)
   float* inv_w2;           // 1 / W_1D(m(i))^2 for FFT index i (N entries)
@@ -106,6 +107,7 @@ struct Tune {
   int dep_threads = 0;    // threads per deposit workgroup (0: chosen per kernel)
   int dep_narrow = 1;     // 32-bit fixed point when provably safe (else 64-bit)
   int dep_xcd = 1;        // consecutive deposit tiles on one XCD (shared L2)
+  int cus = 256;          // compute units of the handle's device (set at create)
 };
 
 // Device helper: wrap one float64 coordinate into [0, L) with the fixed

@@ -24,6 +24,18 @@ __device__ __forceinline__ int mock_of(const int64_t* offsets, int batch, int64_
   return lo;
 }
 
+// the same for j known to lie in sets lo .. hi (offsets[lo] <= j < offsets[hi + 1]):
+// a workgroup's contiguous chunk of particles spans few sets, so the search
+// is usually empty
+__device__ __forceinline__ int mock_in(const int64_t* offsets, int lo, int hi, int64_t j) {
+  int h = hi + 1;  // offsets[lo] <= j < offsets[h]
+  while (h - lo > 1) {
+    const int mid = (lo + h) >> 1;
+    if (offsets[mid] <= j) lo = mid; else h = mid;
+  }
+  return lo;
+}
+
 template <typename TP>
 __device__ __forceinline__ void load_pos(const TP* pos, int64_t j, double& x, double& y, double& z) {
   x = (double)pos[3 * j + 0];

@@ -368,6 +368,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
+  // the sets this chunk spans
+  const int mlo = j0 < j1 ? mock_of(offsets, g.batch, j0) : 0;
+  const int mhi = j0 < j1 ? mock_of(offsets, g.batch, j1 - 1) : 0;
   // kSortBatch particles per thread at a time, their loads issued together
   for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
     double x[kSortBatch], y[kSortBatch], z[kSortBatch];
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict
         int bx, by, bz;
         particle_buckets(grid_coord(x[q], g.box, g.inv), grid_coord(y[q], g.box, g.inv),
                          grid_coord(z[q], g.box, g.inv), g, bx, by, bz);
-        atomicAdd(&hist[super_of(mock_of(offsets, g.batch, j), bx, by, bz, g)], 1u);
+        atomicAdd(&hist[super_of(mlo == mhi ? mlo : mock_in(offsets, mlo, mhi, j), bx, by, bz, g)], 1u);
       }
     }
   }
@@ -403,6 +406,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
+  const int mlo = j0 < j1 ? mock_of(offsets, g.batch, j0) : 0;
+  const int mhi = j0 < j1 ? mock_of(offsets, g.batch, j1 - 1) : 0;
   for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += kSortBatch * kSortThreads) {
     TP px[kSortBatch], py[kSortBatch], pz[kSortBatch];
 #pragma unroll
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
         const double uz = grid_coord((double)pz[q], g.box, g.inv);
         int bx, by, bz;
         particle_buckets(ux, uy, uz, g, bx, by, bz);
-        const int sup = super_of(mock_of(offsets, g.batch, j), bx, by, bz, g);
+        const int sup = super_of(mlo == mhi ? mlo : mock_in(offsets, mlo, mhi, j), bx, by, bz, g);
         const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
         const uint32_t p = atomicAdd(&cur[sup], 1u);
         trec[p] = with_fine(particle_record(ux, uy, uz, g), fine);
