@@ -308,12 +308,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
     if (threadIdx.x < 2) round_cnt[threadIdx.x] = 0;
 
-    // bucket neighbourhood: buckets of cells t0-3 .. t0+T, or every bucket
-    int cnt = T / kBucket + 2;
+    // bucket neighbourhood: particles are bucketed by their first grid's
+    // first stencil cell f, and a stencil of either grid reaches the tile
+    // iff f lies in [t0 - (P - 1) - S, t0 + T - 1] (S = 1 with a shifted
+    // grid), i.e. in the T/4 + kLow buckets from t0/4 - kLow; or every bucket
+    constexpr int kLow = (P - 1 + (IL ? 1 : 0) + kBucket - 1) / kBucket;
+    int cnt = T / kBucket + kLow;
     if (cnt > nb) cnt = nb;
-    const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - 1 + nb) % nb;
-    const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - 1 + nb) % nb;
-    const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - 1 + nb) % nb;
+    const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - kLow + nb) % nb;
+    const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - kLow + nb) % nb;
+    const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - kLow + nb) % nb;
     const int ncomb = cnt * cnt;  // <= 36
     const int64_t mbase = (int64_t)mock * nb * nb * nb;
     if (wave == 0) {
@@ -668,7 +672,7 @@ static void dispatch_deposit_p(const Geom& g, const Buffers& b, const Tune& tu, 
   } else {
     // one pass per slab; the 64-bit kernel's tile counter restarts each time
     for (int q = 0; q < g.npair; ++q) {
-      if (q > 0) launch_fill_u32(b.stats + 1, 1, 0u, s);
+      if (q > 0) (void)launch_fill_u32(b.stats + 1, 1, 0u, s);  // reported by launch_deposit
       dispatch_deposit_t<P, 2>(g, b, tu, threads, sw, q, grid_mask(g.code, 2 * q),
                                grid_mask(g.code, 2 * q + 1), s);
     }

@@ -43,12 +43,6 @@ __device__ __forceinline__ void load_pos(const TP* pos, int64_t j, double& x, do
   z = (double)pos[3 * j + 2];
 }
 
-// floor(u) mod N for u in [0, N] (u = N can come out of the rounding of x N / L)
-__device__ __forceinline__ int base_cell(double u, int n) {
-  const int c = (int)floor(u);
-  return c >= n ? c - n : c;
-}
-
 // ------------------------------------------------------------------ stencils
 // Orders above 4 (the higher-order B-splines of Sec. 2.3): the weights of
 // the p stencil cells are N_p(t + i), i = 0..p-1, of the cardinal B-spline
@@ -144,6 +138,26 @@ __device__ __forceinline__ void stencil_1d(double u, int n, int (&cell)[P], floa
 constexpr int kFracBits = 24;
 constexpr uint32_t kFracMask = (1u << kFracBits) - 1u;
 
+// floor(u) for even p, floor(u + 1/2) for odd p (the record's floor, before
+// the reduction mod N)
+__device__ __forceinline__ double record_floor(double u, bool even) {
+  return even ? floor(u) : floor(u + 0.5);
+}
+
+// Bucket of one axis: the bucket of the first grid's first stencil cell
+// (record floor minus the stencil offset, mod N).  Keyed this way, the
+// particles whose stencil on either grid can reach cells [t0, t0 + T) have
+// first cells in [t0 - (p - 1) - 1, t0 + T - 1]: T/4 + ceil(p/4) buckets
+// when t0 is a multiple of 4 (keyed by floor(u) it would be T/4 + 2 up to
+// p = 4).
+__device__ __forceinline__ int bucket_of(double u, const Geom& g) {
+  const bool even = (g.order % 2) == 0;
+  const int off = even ? g.order / 2 - 1 : (g.order - 1) / 2;
+  int f = (int)record_floor(u, even) - off;  // in [-off, N - off]
+  f = f < 0 ? f + g.n : (f >= g.n ? f - g.n : f);
+  return f / kBucket;
+}
+
 __device__ __forceinline__ uint4 particle_record(double ux, double uy, double uz, const Geom& g) {
   const bool even = (g.order % 2) == 0;
   const double u[3] = {ux, uy, uz};
@@ -151,8 +165,8 @@ __device__ __forceinline__ uint4 particle_record(double ux, double uy, double uz
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double u2 = u[a] + 0.5;  // the interlaced grid's coordinate
-    const double f1 = even ? floor(u[a]) : floor(u[a] + 0.5);
-    const double f2 = even ? floor(u2) : floor(u2 + 0.5);
+    const double f1 = record_floor(u[a], even);
+    const double f2 = record_floor(u2, even);
     const int c1 = (int)f1;  // in [0, N]
     cell[a] = (uint32_t)(c1 >= g.n ? c1 - g.n : c1);
     step[a] = (uint32_t)((int)(f2 - f1) & 1);

@@ -1,5 +1,5 @@
-// Bucket sort of the particles by 4^3-cell bucket (the deposit's input
-// order), the per-set counts and mass sums, and small fill/scan utilities.
+// Bucket sort of the particles by 4^3-cell bucket of their first stencil
+// cell (the deposit's input order), the per-set counts and mass sums, and small fill/scan utilities.
 //
 // Design (gfx950): by default two levels without device-scope atomics
 // (per-workgroup LDS histograms over super-buckets, a scan, a super-bucket
@@ -155,9 +155,9 @@ __global__ __launch_bounds__(kCountThreads) void k_bucket_count(
     double x, y, z;
     load_pos(pos, j, x, y, z);
     const int mock = mock_of(offsets, g.batch, j);
-    const int bx = base_cell(grid_coord(x, g.box, g.inv), g.n) / kBucket;
-    const int by = base_cell(grid_coord(y, g.box, g.inv), g.n) / kBucket;
-    const int bz = base_cell(grid_coord(z, g.box, g.inv), g.n) / kBucket;
+    const int bx = bucket_of(grid_coord(x, g.box, g.inv), g);
+    const int by = bucket_of(grid_coord(y, g.box, g.inv), g);
+    const int bz = bucket_of(grid_coord(z, g.box, g.inv), g);
     key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
   }
   __syncthreads();
@@ -212,9 +212,9 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const TP* __restrict__ p
   const double ux = grid_coord((double)px, g.box, g.inv);
   const double uy = grid_coord((double)py, g.box, g.inv);
   const double uz = grid_coord((double)pz, g.box, g.inv);
-  const int bx = base_cell(ux, g.n) / kBucket;
-  const int by = base_cell(uy, g.n) / kBucket;
-  const int bz = base_cell(uz, g.n) / kBucket;
+  const int bx = bucket_of(ux, g);
+  const int by = bucket_of(uy, g);
+  const int bz = bucket_of(uz, g);
   const uint32_t key = (uint32_t)(((int64_t)mock * g.nb + bx) * g.nb + by) * g.nb + bz;
   const int64_t dst = (int64_t)boff[key] + rank[j];
   recs[dst] = particle_record(ux, uy, uz, g);
@@ -348,9 +348,9 @@ constexpr int kSortBatch = 4;  // particles per thread whose loads are in flight
 
 __device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
                                                  int& bx, int& by, int& bz) {
-  bx = base_cell(ux, g.n) / kBucket;
-  by = base_cell(uy, g.n) / kBucket;
-  bz = base_cell(uz, g.n) / kBucket;
+  bx = bucket_of(ux, g);
+  by = bucket_of(uy, g);
+  bz = bucket_of(uz, g);
 }
 
 __device__ __forceinline__ int super_of(int mock, int bx, int by, int bz, const Geom& g) {
