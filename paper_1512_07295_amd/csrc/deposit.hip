@@ -233,12 +233,26 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // deposited with LDS integer atomics, lane l of
 // virtual wave r taking sorted item r + l * W (W = virtual waves in the
 // flush); (3) the finished tile is scaled back to float and written once.
-// Workgroups loop over tiles b, b + gridDim, ... (a persistent grid of a few
+//
+// Work units.  `walk` (tiles smaller than the grid, N >= T + 4 kLow): a unit
+// is a segment of up to seg_len consecutive tiles of one z column, taken in
+// order.  A particle's items go to the tile that holds its first z cell
+// f_z, whole in z: the cells they give above the tile (at most P) stay in
+// the LDS rows' upper halo and move down to the next tile's first cells
+// (the carry).  The segment's first tile also takes the kLow buckets below
+// it, whose stencils reach into it from below (their cells below the tile
+// fall into the rows' lower margin and are dropped), and the carry of its
+// last tile is dropped: the next segment takes those particles again.  So a
+// particle is scanned by the tiles of one z position (plus a first tile's
+// look-back) and its z stencil is never split.  Otherwise a unit is one
+// tile, which scans T/4 + kLow buckets per axis and keeps the items whose
+// stencil reaches it.
+// Workgroups loop over units b, b + gridDim, ... (a persistent grid of a few
 // workgroups per CU, so the per-workgroup set-up is paid once per many
-// tiles); `dynamic`: tiles are taken from a global counter (stats[1], zeroed
-// with the sort) instead.  `xcd`: consecutive tiles go to the same XCD
-// (workgroup b runs on XCD b mod 8), so the buckets that neighbouring tiles
-// share are read through one L2.
+// units); `dynamic`: units are taken from a global counter (stats[1],
+// zeroed with the sort) instead.  `xcd`: consecutive units go to the same
+// XCD (workgroup b runs on XCD b mod 8), so the buckets that neighbouring
+// columns share are read through one L2.
 // WT: per-particle masses (sw, bucket order, divided by the largest mass);
 // a separate instantiation so that the equal-mass kernel keeps its registers
 // IL: 0 one grid; 1 the interlaced pair (masks 0 and 7); 2 a pair of grids
@@ -252,7 +266,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
                                                   Geom g, uint32_t* __restrict__ stats,
                                                   int exclusive, int dynamic, int xcd,
                                                   const float* __restrict__ sw, int q, int mask_a,
-                                                  int mask_b) {
+                                                  int mask_b, int walk, int seg_len) {
   using AT = typename std::conditional<WIDE, unsigned long long, unsigned>::type;
   constexpr int NG = IL ? 2 : 1;
   constexpr int kWords = acc_first_word<AT>() + NG * kGridWords * (int)(sizeof(AT) / 4);
@@ -282,310 +296,352 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
 
   const int n = g.n, T = g.tile, nb = g.nb;
   const int tpa = (n + T - 1) / T;  // tiles per axis; the last one is ragged when T does not divide N
-  const int64_t tiles_per_set = (int64_t)tpa * tpa * tpa;
-  const int64_t ntiles = (int64_t)g.batch * tiles_per_set;
+  const int slen = walk ? seg_len : 1;
+  const int upc = (tpa + slen - 1) / slen;  // units per z column
+  // (the host keeps the unit count below 2^31)
+  const uint32_t units_per_set = (uint32_t)(tpa * tpa * upc);
+  const uint32_t nunits = (uint32_t)g.batch * units_per_set;
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // workgroup b runs on XCD b mod 8: with xcd, the tiles of XCD x are the
+  // workgroup b runs on XCD b mod 8: with xcd, the units of XCD x are the
   // x-th eighth, taken in order by its workgroups (gridDim a multiple of 8)
-  const bool remap = xcd && !dynamic && (gridDim.x & 7) == 0 && (ntiles & 7) == 0;
+  const bool remap = xcd && !dynamic && (gridDim.x & 7) == 0 && (nunits & 7) == 0;
+  // buckets below a tile whose particles can reach it (see the ranges below)
+  constexpr int kLow = (P - 1 + (IL ? 1 : 0) + kBucket - 1) / kBucket;
 
-  int64_t b = blockIdx.x;
+  uint32_t b = blockIdx.x;
   if (dynamic) {
     if (threadIdx.x == 0) next_tile = (int)atomicAdd(&stats[1], 1u);
     __syncthreads();
-    b = next_tile;
+    b = (uint32_t)next_tile;
   }
-  while (b < ntiles) {
-    const int64_t tid_all = remap ? ((b & 7) * (ntiles >> 3) + (b >> 3)) : b;
-    const int mock = (int)(tid_all / tiles_per_set);
-    const int trem = (int)(tid_all % tiles_per_set);
-    const int tx = trem / (tpa * tpa), ty = (trem / tpa) % tpa, tz = trem % tpa;
-    const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
-    // cells of this tile per axis (a multiple of kBucket)
-    const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
+  while (b < nunits) {
+    const uint32_t uid = remap ? ((b & 7) * (nunits >> 3) + (b >> 3)) : b;
+    const int mock = (int)(uid / units_per_set);
+    const int urem = (int)(uid % units_per_set);
+    const int tx = urem / (tpa * upc), ty = (urem / upc) % tpa, sg = urem % upc;
+    const int tz1 = min(tpa, (sg + 1) * slen);
+    for (int tz = sg * slen; tz < tz1; ++tz) {
+      const bool first = tz == sg * slen;
+      const int t0x = tx * T, t0y = ty * T, t0z = tz * T;
+      // cells of this tile per axis (a multiple of kBucket)
+      const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
 
-    if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
-    if (threadIdx.x < 2) round_cnt[threadIdx.x] = 0;
+      if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
+      if (threadIdx.x < 2) round_cnt[threadIdx.x] = 0;
 
-    // bucket neighbourhood: particles are bucketed by their first grid's
-    // first stencil cell f, and a stencil of either grid reaches the tile
-    // iff f lies in [t0 - (P - 1) - S, t0 + T - 1] (S = 1 with a shifted
-    // grid), i.e. in the T/4 + kLow buckets from t0/4 - kLow; or every bucket
-    constexpr int kLow = (P - 1 + (IL ? 1 : 0) + kBucket - 1) / kBucket;
-    int cnt = T / kBucket + kLow;
-    if (cnt > nb) cnt = nb;
-    const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - kLow + nb) % nb;
-    const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - kLow + nb) % nb;
-    const int b0z = (cnt == nb) ? 0 : (t0z / kBucket - kLow + nb) % nb;
-    const int ncomb = cnt * cnt;  // <= 36
-    const int64_t mbase = (int64_t)mock * nb * nb * nb;
-    if (wave == 0) {
-      // a column's run of cnt buckets in z is contiguous in memory except
-      // where it crosses a super-bucket edge (every g.fb buckets, which
-      // includes the periodic wrap): at most two pieces
-      uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
-      if (lane < ncomb) {
-        const int ix = lane / cnt, iy = lane % cnt;
-        const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
-        const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
-        const int z1 = b0z + cnt;                       // exclusive end, may pass nb
-        const int zs = (b0z / g.fb + 1) * g.fb;         // next super-bucket edge
-        const int za = z1 < zs ? z1 : zs;               // end of the first piece
-        s0 = boff[row + b0z];
-        e0 = boff[row + za - 1] + bcnt[row + za - 1];
-        if (z1 > zs) {
-          const int zb = zs % nb, ze = zb + (z1 - zs);
-          s1 = boff[row + zb];
-          e1 = boff[row + ze - 1] + bcnt[row + ze - 1];
-        }
-      }
-      // exclusive prefix of the per-lane lengths across the wave
-      const uint32_t la = e0 - s0, lb = e1 - s1;
-      uint32_t incl = la + lb;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
-        if (lane >= off) incl += o;
-      }
-      const uint32_t excl = incl - la - lb;
-      if (lane < ncomb) {
-        rg.start[2 * lane] = s0;
-        rg.start[2 * lane + 1] = s1;
-        rg.pref[2 * lane + 1] = excl + la;
-        rg.pref[2 * lane + 2] = excl + la + lb;
-      }
-      if (lane == 0) {
-        rg.pref[0] = 0;
-        rg.count = 2 * ncomb;
-      }
-    }
-    // the other waves clear the tile while wave 0 waits for the offsets
-    {
-      uint4* z4 = reinterpret_cast<uint4*>(smem + acc_first_word<AT>());
-      constexpr int kZero4 = (kWords - acc_first_word<AT>()) / 4;
-      for (int i = threadIdx.x; i < kZero4; i += nthreads) z4[i] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    __syncthreads();
-    const uint32_t total = rg.pref[rg.count];
-    const int nr = rg.count;
-
-    // Sorts the m listed items by bank class and deposits them; every
-    // thread calls it with the same m, and it ends with a barrier.
-    auto deposit_list = [&](int m) __attribute__((always_inline)) {
+      // bucket neighbourhood: particles are bucketed by their first grid's
+      // first stencil cell f, and a stencil of either grid reaches the tile
+      // iff f lies in [t0 - (P - 1) - S, t0 + T - 1] (S = 1 with a shifted
+      // grid), i.e. in the T/4 + kLow buckets from t0/4 - kLow; or every
+      // bucket.  Walking in z: the tile's own ez/4 buckets, and the kLow below
+      // them for a segment's first tile.
+      int cnt = T / kBucket + kLow;
+      if (cnt > nb) cnt = nb;
+      const int b0x = (cnt == nb) ? 0 : (t0x / kBucket - kLow + nb) % nb;
+      const int b0y = (cnt == nb) ? 0 : (t0y / kBucket - kLow + nb) % nb;
+      const int zlow = walk ? (first ? kLow : 0) : kLow;
+      int cntz = walk ? ez / kBucket + zlow : cnt;
+      if (cntz > nb) cntz = nb;
+      const int b0z = (!walk && cntz == nb) ? 0 : (t0z / kBucket - zlow + nb) % nb;
+      const int ncomb = cnt * cnt;  // <= 36
+      const int64_t mbase = (int64_t)mock * nb * nb * nb;
       if (wave == 0) {
-        const int c = cls_cnt[lane];
-        int incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int t = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += t;
-        }
-        cls_cur[lane] = incl - c;
-        cls_cnt[lane] = 0;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < m; e += nthreads)
-        item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
-      __syncthreads();
-      // lane l of virtual wave r takes item r + l W; each item's record is
-      // loaded one iteration ahead
-      const int W = (m + 63) >> 6;
-      const int vend = 64 * W;
-      int e_cur = -1;
-      uint4 rc = make_uint4(0u, 0u, 0u, 0u);
-      {
-        const int v = threadIdx.x;
-        const int p = (v >> 6) + (v & 63) * W;
-        if (v < vend && p < m) {
-          e_cur = item_order[p];
-          rc = recs[item_j[e_cur]];
-        }
-      }
-      for (int v = threadIdx.x; v < vend; v += nthreads) {
-        const int vn = v + nthreads;
-        const int pn = (vn >> 6) + (vn & 63) * W;
-        int e_nxt = -1;
-        uint4 rn = make_uint4(0u, 0u, 0u, 0u);
-        if (vn < vend && pn < m) {
-          e_nxt = item_order[pn];
-          rn = recs[item_j[e_nxt]];
-        }
-        if (e_cur >= 0) {
-          float sc = scale;
-          if constexpr (WT) sc *= sw[item_j[e_cur]];
-          const int gi = item_meta[e_cur] >> 6;
-          const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-          deposit_item<P, AT, WRAP>(rc, gi, g, t0x, t0y, t0z, sm, sc, mk);
-        }
-        e_cur = e_nxt;
-        rc = rn;
-      }
-      __syncthreads();
-    };
-    int fill = 0;  // items in the list (the same value in every thread)
-    int rpar = 0;  // which of the two round counters this round uses
-
-    // rounds of blockDim candidates; the cell records of kPre rounds are
-    // loaded together so that their latencies overlap (one round where the
-    // registers are capped: the other workgroup on the CU covers the wait)
-    constexpr int kPre = CAP ? 1 : 4;
-    constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
-    for (uint32_t rb = 0; rb < total; rb += kPre * nthreads) {
-      uint32_t jj[kPre];
-      uint2 rec[kPre];
-#pragma unroll
-      for (int q = 0; q < kPre; ++q) {
-        const uint32_t r0 = rb + q * nthreads;
-        const uint32_t item = r0 + threadIdx.x;
-        jj[q] = 0;
-        rec[q] = make_uint2(0u, 0u);
-        if (r0 < total) {
-          const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item);
-          if (item < total) {
-            jj[q] = rg.start[seg] + (item - rg.pref[seg]);
-            // cells and steps: the record's x word and the y word's step bit
-            rec[q] = *reinterpret_cast<const uint2*>(recs + jj[q]);
+        // a column's run of cnt buckets in z is contiguous in memory except
+        // where it crosses a super-bucket edge (every g.fb buckets, which
+        // includes the periodic wrap): at most two pieces
+        uint32_t s0 = 0, e0 = 0, s1 = 0, e1 = 0;
+        if (lane < ncomb) {
+          const int ix = lane / cnt, iy = lane % cnt;
+          const int bx = (b0x + ix) % nb, by = (b0y + iy) % nb;
+          const int64_t row = mbase + ((int64_t)bx * nb + by) * nb;
+          const int z1 = b0z + cntz;                      // exclusive end, may pass nb
+          const int zs = (b0z / g.fb + 1) * g.fb;         // next super-bucket edge
+          const int za = z1 < zs ? z1 : zs;               // end of the first piece
+          s0 = boff[row + b0z];
+          e0 = boff[row + za - 1] + bcnt[row + za - 1];
+          if (z1 > zs) {
+            const int zb = zs % nb, ze = zb + (z1 - zs);
+            s1 = boff[row + zb];
+            e1 = boff[row + ze - 1] + bcnt[row + ze - 1];
           }
         }
-      }
-#pragma unroll 1
-      for (int q = 0; q < kPre; ++q) {
-        const uint32_t r0 = rb + q * nthreads;
-        if (r0 >= total) break;
-        // (1) candidates of this round -> work items
-        const uint32_t item = r0 + threadIdx.x;
-        const uint32_t j = jj[0];
-        bool ok[NG];
-        int cls[NG];
+        // exclusive prefix of the per-lane lengths across the wave
+        const uint32_t la = e0 - s0, lb = e1 - s1;
+        uint32_t incl = la + lb;
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-          ok[gi] = false;
-          cls[gi] = 0;
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t o = (uint32_t)__shfl_up((int)incl, off, 64);
+          if (lane >= off) incl += o;
         }
-        if (item < total) {
-          const uint2 r = rec[0];
-          const int cx = (int)(r.x & 1023u) - off;
-          const int cy = (int)((r.x >> 10) & 1023u) - off;
-          const int cz = (int)((r.x >> 20) & 1023u) - off;
+        const uint32_t excl = incl - la - lb;
+        if (lane < ncomb) {
+          rg.start[2 * lane] = s0;
+          rg.start[2 * lane + 1] = s1;
+          rg.pref[2 * lane + 1] = excl + la;
+          rg.pref[2 * lane + 2] = excl + la + lb;
+        }
+        if (lane == 0) {
+          rg.pref[0] = 0;
+          rg.count = 2 * ncomb;
+        }
+      }
+      // the other waves clear the tile, or move the carry down, while wave 0
+      // waits for the offsets
+      if (first) {
+        uint4* z4 = reinterpret_cast<uint4*>(smem + acc_first_word<AT>());
+        constexpr int kZero4 = (kWords - acc_first_word<AT>()) / 4;
+        for (int i = threadIdx.x; i < kZero4; i += nthreads) z4[i] = make_uint4(0u, 0u, 0u, 0u);
+      } else {
+        // every row moves down by T elements (the previous tile was whole):
+        // the upper halo becomes the first cells, the rest is cleared (the
+        // lower margin receives old owned cells, which are never read)
+        constexpr int kRow4 = kRow * (int)sizeof(AT) / 16;
+        constexpr int kShift4 = kTileMax * (int)sizeof(AT) / 16;
+        static_assert(kRow * sizeof(AT) % 16 == 0 && kPlane * sizeof(AT) % 16 == 0,
+                      "rows of uint4");
+        for (int r = threadIdx.x; r < NG * kTileMax * kTileMax; r += nthreads) {
+          const int gi = r / (kTileMax * kTileMax);
+          const int lx = (r / kTileMax) % kTileMax, ly = r % kTileMax;
+          uint4* row =
+              reinterpret_cast<uint4*>(sm + acc0 + gi * kGridWords + lx * kPlane + ly * kRow);
+          uint4 v[kRow4 - kShift4];
+#pragma unroll
+          for (int c = 0; c < kRow4 - kShift4; ++c) v[c] = row[kShift4 + c];
+#pragma unroll
+          for (int c = 0; c < kRow4; ++c)
+            row[c] = c < kRow4 - kShift4 ? v[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+      __syncthreads();
+      const uint32_t total = rg.pref[rg.count];
+      const int nr = rg.count;
+
+      // Sorts the m listed items by bank class and deposits them; every
+      // thread calls it with the same m, and it ends with a barrier.
+      auto deposit_list = [&](int m) __attribute__((always_inline)) {
+        if (wave == 0) {
+          const int c = cls_cnt[lane];
+          int incl = c;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+          }
+          cls_cur[lane] = incl - c;
+          cls_cnt[lane] = 0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < m; e += nthreads)
+          item_order[atomicAdd(&cls_cur[item_meta[e] & 63], 1)] = (uint16_t)e;
+        __syncthreads();
+        // lane l of virtual wave r takes item r + l W; each item's record is
+        // loaded one iteration ahead
+        const int W = (m + 63) >> 6;
+        const int vend = 64 * W;
+        int e_cur = -1;
+        uint4 rc = make_uint4(0u, 0u, 0u, 0u);
+        {
+          const int v = threadIdx.x;
+          const int p = (v >> 6) + (v & 63) * W;
+          if (v < vend && p < m) {
+            e_cur = item_order[p];
+            rc = recs[item_j[e_cur]];
+          }
+        }
+        for (int v = threadIdx.x; v < vend; v += nthreads) {
+          const int vn = v + nthreads;
+          const int pn = (vn >> 6) + (vn & 63) * W;
+          int e_nxt = -1;
+          uint4 rn = make_uint4(0u, 0u, 0u, 0u);
+          if (vn < vend && pn < m) {
+            e_nxt = item_order[pn];
+            rn = recs[item_j[e_nxt]];
+          }
+          if (e_cur >= 0) {
+            float sc = scale;
+            if constexpr (WT) sc *= sw[item_j[e_cur]];
+            const int gi = item_meta[e_cur] >> 6;
+            const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
+            deposit_item<P, AT, WRAP>(rc, gi, g, t0x, t0y, t0z, sm, sc, mk);
+          }
+          e_cur = e_nxt;
+          rc = rn;
+        }
+        __syncthreads();
+      };
+      int fill = 0;  // items in the list (the same value in every thread)
+      int rpar = 0;  // which of the two round counters this round uses
+
+      // rounds of blockDim candidates; the cell records of kPre rounds are
+      // loaded together so that their latencies overlap (one round where the
+      // registers are capped: the other workgroup on the CU covers the wait)
+      constexpr int kPre = CAP ? 1 : 4;
+      constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
+      for (uint32_t rb = 0; rb < total; rb += kPre * nthreads) {
+        uint32_t jj[kPre];
+        uint2 rec[kPre];
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+          const uint32_t r0 = rb + q * nthreads;
+          const uint32_t item = r0 + threadIdx.x;
+          jj[q] = 0;
+          rec[q] = make_uint2(0u, 0u);
+          if (r0 < total) {
+            const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item);
+            if (item < total) {
+              jj[q] = rg.start[seg] + (item - rg.pref[seg]);
+              // cells and steps: the record's x word and the y word's step bit
+              rec[q] = *reinterpret_cast<const uint2*>(recs + jj[q]);
+            }
+          }
+        }
+#pragma unroll 1
+        for (int q = 0; q < kPre; ++q) {
+          const uint32_t r0 = rb + q * nthreads;
+          if (r0 >= total) break;
+          // (1) candidates of this round -> work items
+          const uint32_t item = r0 + threadIdx.x;
+          const uint32_t j = jj[0];
+          bool ok[NG];
+          int cls[NG];
 #pragma unroll
           for (int gi = 0; gi < NG; ++gi) {
-            const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-            const int sx = (mk & 1) ? (int)((r.x >> 30) & 1u) : 0;
-            const int sy = (mk & 2) ? (int)(r.x >> 31) : 0;
-            const int sz = (mk & 4) ? (int)((r.y >> 24) & 1u) : 0;
-            const int rx = rel_first<P, WRAP>(cx + sx, t0x, n);
-            const int ry = rel_first<P, WRAP>(cy + sy, t0y, n);
-            const int rz = rel_first<P, WRAP>(cz + sz, t0z, n);
-            ok[gi] = reaches_tile<P, WRAP>(rx, ry, rz);
-            cls[gi] = bank_class<P>(rx, ry, rz);
+            ok[gi] = false;
+            cls[gi] = 0;
+          }
+          if (item < total) {
+            const uint2 r = rec[0];
+            const int cx = (int)(r.x & 1023u) - off;
+            const int cy = (int)((r.x >> 10) & 1023u) - off;
+            const int cz = (int)((r.x >> 20) & 1023u) - off;
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+              const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
+              const int sx = (mk & 1) ? (int)((r.x >> 30) & 1u) : 0;
+              const int sy = (mk & 2) ? (int)(r.x >> 31) : 0;
+              const int sz = (mk & 4) ? (int)((r.y >> 24) & 1u) : 0;
+              const int rx = rel_first<P, WRAP>(cx + sx, t0x, n);
+              const int ry = rel_first<P, WRAP>(cy + sy, t0y, n);
+              const int rz = rel_first<P, WRAP>(cz + sz, t0z, n);
+              if (walk) {
+                // own buckets: always (the cells above the tile are carried);
+                // the look-back buckets: if the stencil reaches the tile, i.e.
+                // starts in [-(P - 1), 0] (rel_first maps the others above T)
+                int dz = cz - t0z;
+                dz = dz < 0 ? dz + n : dz;
+                ok[gi] = rx < kTileMax && ry < kTileMax && (dz < ez || rz <= 0);
+              } else {
+                ok[gi] = reaches_tile<P, WRAP>(rx, ry, rz);
+              }
+              cls[gi] = bank_class<P>(rx, ry, rz);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t + 1 < kPre; ++t) {
+            jj[t] = jj[t + 1];
+            rec[t] = rec[t + 1];
+          }
+          unsigned long long bal[NG];
+          int mine = 0;
+#pragma unroll
+          for (int gi = 0; gi < NG; ++gi) {
+            bal[gi] = __ballot(ok[gi]);
+            mine += __popcll(bal[gi]);
+          }
+          // each wave reserves its slice of this round's items (slices in any
+          // order: the integer sums do not depend on it)
+          int before = 0;
+          if (lane == 0) before = atomicAdd(&round_cnt[rpar], mine);
+          before = __builtin_amdgcn_readfirstlane(before);
+          __syncthreads();
+          const int tot = round_cnt[rpar];
+          // the other counter was last read before the previous round's
+          // insertion barrier and is next used after this round's
+          if (threadIdx.x == 0) round_cnt[rpar ^ 1] = 0;
+          rpar ^= 1;
+          // (2) the list is deposited first if this round's items would not fit
+          if (fill + tot > kItemCap) {
+            deposit_list(fill);
+            fill = 0;
+          }
+          const unsigned long long below = (1ull << lane) - 1ull;
+          int pos = fill + before;
+#pragma unroll
+          for (int gi = 0; gi < NG; ++gi) {
+            if (ok[gi]) {
+              const int p = pos + __popcll(bal[gi] & below);
+              item_j[p] = j;
+              item_meta[p] = (uint8_t)(cls[gi] | (gi << 6));
+              atomicAdd(&cls_cnt[cls[gi]], 1);
+            }
+            pos += __popcll(bal[gi]);
+          }
+          __syncthreads();
+          fill += tot;
+          if (r0 + nthreads >= total) {  // the last round: deposit what is left
+            deposit_list(fill);
+            fill = 0;
           }
         }
-#pragma unroll
-        for (int t = 0; t + 1 < kPre; ++t) {
-          jj[t] = jj[t + 1];
-          rec[t] = rec[t + 1];
-        }
-        unsigned long long bal[NG];
-        int mine = 0;
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-          bal[gi] = __ballot(ok[gi]);
-          mine += __popcll(bal[gi]);
-        }
-        // each wave reserves its slice of this round's items (slices in any
-        // order: the integer sums do not depend on it)
-        int before = 0;
-        if (lane == 0) before = atomicAdd(&round_cnt[rpar], mine);
-        before = __builtin_amdgcn_readfirstlane(before);
-        __syncthreads();
-        const int tot = round_cnt[rpar];
-        // the other counter was last read before the previous round's
-        // insertion barrier and is next used after this round's
-        if (threadIdx.x == 0) round_cnt[rpar ^ 1] = 0;
-        rpar ^= 1;
-        // (2) the list is deposited first if this round's items would not fit
-        if (fill + tot > kItemCap) {
-          deposit_list(fill);
-          fill = 0;
-        }
-        const unsigned long long below = (1ull << lane) - 1ull;
-        int pos = fill + before;
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-          if (ok[gi]) {
-            const int p = pos + __popcll(bal[gi] & below);
-            item_j[p] = j;
-            item_meta[p] = (uint8_t)(cls[gi] | (gi << 6));
-            atomicAdd(&cls_cnt[cls[gi]], 1);
-          }
-          pos += __popcll(bal[gi]);
-        }
-        __syncthreads();
-        fill += tot;
-        if (r0 + nthreads >= total) {  // the last round: deposit what is left
-          deposit_list(fill);
-          fill = 0;
-        }
       }
-    }
-    // (3) write the tile (halo cells dropped, or folded back when periodic)
-    const int slab = (IL == 2) ? mock * g.npair + q : mock;
-    if constexpr (WRAP != kPeriodic) {
-      // four consecutive z cells per thread; the narrow scale is a power of
-      // two, so float(sum) * 2^-F rounds exactly like the double product
-      constexpr int TT = kTileMax;
-      const float inv_f = (float)inv_scale;
-      for (int i = threadIdx.x; i < TT * TT * TT / 4; i += nthreads) {
-        const int lx = i / (TT * TT / 4), ly = (i / (TT / 4)) % TT, lz = (i % (TT / 4)) * 4;
-        if (lx >= ex || ly >= ey || lz >= ez) continue;  // outside a ragged tile
-        float v[NG][4];
+      // (3) write the tile (halo cells dropped, or folded back when periodic)
+      const int slab = (IL == 2) ? mock * g.npair + q : mock;
+      if constexpr (WRAP != kPeriodic) {
+        // four consecutive z cells per thread; the narrow scale is a power of
+        // two, so float(sum) * 2^-F rounds exactly like the double product
+        constexpr int TT = kTileMax;
+        const float inv_f = (float)inv_scale;
+        for (int i = threadIdx.x; i < TT * TT * TT / 4; i += nthreads) {
+          const int lx = i / (TT * TT / 4), ly = (i / (TT / 4)) % TT, lz = (i % (TT / 4)) * 4;
+          if (lx >= ex || ly >= ey || lz >= ez) continue;  // outside a ragged tile
+          float v[NG][4];
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
+          for (int gi = 0; gi < NG; ++gi) {
+            const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const AT s = sm[a + q];
-            v[gi][q] = (WIDE ? (float)((double)s * inv_scale) : (float)s * inv_f) * wmul;
+            for (int q = 0; q < 4; ++q) {
+              const AT s = sm[a + q];
+              v[gi][q] = (WIDE ? (float)((double)s * inv_scale) : (float)s * inv_f) * wmul;
+            }
+          }
+          if constexpr (IL) {
+            float4* dst = reinterpret_cast<float4*>(
+                reinterpret_cast<float2*>(grid) + complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz));
+            dst[0] = make_float4(v[0][0], v[NG - 1][0], v[0][1], v[NG - 1][1]);
+            dst[1] = make_float4(v[0][2], v[NG - 1][2], v[0][3], v[NG - 1][3]);
+          } else {
+            *reinterpret_cast<float4*>(grid + real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)) =
+                make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
           }
         }
-        if constexpr (IL) {
-          float4* dst = reinterpret_cast<float4*>(
-              reinterpret_cast<float2*>(grid) + complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz));
-          dst[0] = make_float4(v[0][0], v[NG - 1][0], v[0][1], v[NG - 1][1]);
-          dst[1] = make_float4(v[0][2], v[NG - 1][2], v[0][3], v[NG - 1][3]);
-        } else {
-          *reinterpret_cast<float4*>(grid + real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)) =
-              make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
-        }
-      }
-    } else {
-      for (int i = threadIdx.x; i < T * T * T; i += nthreads) {
-        const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-        float v[NG];
+      } else {
+        for (int i = threadIdx.x; i < T * T * T; i += nthreads) {
+          const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
+          float v[NG];
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-          const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
-          AT s = sm[a];
-          if (lz < zhalo<P>()) s += sm[a + T];
-          v[gi] = (float)((double)s * inv_scale) * wmul;
-        }
-        if constexpr (IL) {
-          reinterpret_cast<float2*>(grid)[complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] =
-              make_float2(v[0], v[NG - 1]);
-        } else {
-          grid[real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] = v[0];
+          for (int gi = 0; gi < NG; ++gi) {
+            const int a = acc0 + gi * kGridWords + lx * kPlane + ly * kRow + lz + zhalo<P>();
+            AT s = sm[a];
+            if (lz < zhalo<P>()) s += sm[a + T];
+            v[gi] = (float)((double)s * inv_scale) * wmul;
+          }
+          if constexpr (IL) {
+            reinterpret_cast<float2*>(grid)[complex_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] =
+                make_float2(v[0], v[NG - 1]);
+          } else {
+            grid[real_cell_index(g, slab, t0x + lx, t0y + ly, t0z + lz)] = v[0];
+          }
         }
       }
+      __syncthreads();  // the tile is written before it is cleared or moved
     }
     if (dynamic) {
-      __syncthreads();  // every thread has read next_tile and finished the tile
       if (threadIdx.x == 0) next_tile = (int)atomicAdd(&stats[1], 1u);
       __syncthreads();
-      b = next_tile;
+      b = (uint32_t)next_tile;
     } else {
       b += gridDim.x;
-      __syncthreads();
     }
   }
 }
@@ -606,39 +662,56 @@ __host__ __device__ constexpr bool two_groups_per_cu() {
 
 // threads: 256, 512 or 1024 per deposit workgroup, or 0 for the kernel's
 // own choice (1024 where two_groups_per_cu, else 512)
+// Segment length of the z walk: the longest of 8, 4, 2 tiles that still
+// gives every workgroup of the persistent grid about 8 units (the units of a
+// batch of uneven sets differ in cost).
+static int walk_segment(const Geom& g, int cus) {
+  const int tpa = (g.n + g.tile - 1) / g.tile;
+  const int64_t cols = (int64_t)g.batch * tpa * tpa;
+  int len = 8;
+  while (len > 2 && cols * ((tpa + len - 1) / len) < (int64_t)cus * 64) len /= 2;
+  return len;
+}
+
 template <int P, int IL, int WRAP, bool WT>
 static void deposit_launch(const Geom& g, const Buffers& b, int threads, bool narrow, bool xcd,
                            int cus, const float* sw, int q, int ma, int mb, hipStream_t s) {
   const int tpa = (g.n + g.tile - 1) / g.tile;
-  const int64_t ntiles = (int64_t)g.batch * tpa * tpa * tpa;
+  // the z walk needs a tile smaller than the grid and the look-back buckets
+  // of a segment's first tile distinct from its own
+  constexpr int kLow = (P - 1 + (IL ? 1 : 0) + kBucket - 1) / kBucket;
+  const bool walk = WRAP != kPeriodic && g.n >= g.tile + kBucket * kLow;
+  const int seg = walk ? walk_segment(g, cus) : 1;
+  const int64_t nunits = (int64_t)g.batch * tpa * tpa * ((tpa + seg - 1) / seg);
   constexpr bool kTwo = two_groups_per_cu<P, IL, false, WRAP, WT>();
   if (narrow) {
     const int tn = threads ? threads : (kTwo ? 1024 : 512);
     // a persistent grid: 8 workgroups per CU (a multiple of 8 for the XCD
-    // grouping), each looping over tiles
+    // grouping), each looping over units
     const int64_t cap = (int64_t)cus * 8;
-    const unsigned nwg = (unsigned)(ntiles < cap ? ntiles : cap);
+    const unsigned nwg = (unsigned)(nunits < cap ? nunits : cap);
     bool capped = false;
     if constexpr (kTwo) {
       if (tn == 1024) {
         hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, true>), dim3(nwg), dim3(tn), 0, s,
                            (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0, 0,
-                           xcd ? 1 : 0, sw, q, ma, mb);
+                           xcd ? 1 : 0, sw, q, ma, mb, walk ? 1 : 0, seg);
         capped = true;
       }
     }
     if (!capped)
       hipLaunchKernelGGL((k_deposit<P, IL, false, WRAP, WT, false>), dim3(nwg), dim3(tn), 0, s,
                          (const uint4*)b.recs, b.boff, b.bcnt, (float*)b.grid, g, b.stats, 0, 0,
-                         xcd ? 1 : 0, sw, q, ma, mb);
+                         xcd ? 1 : 0, sw, q, ma, mb, walk ? 1 : 0, seg);
   }
-  // the 64-bit kernel holds one workgroup per CU; it takes tiles from a
+  // the 64-bit kernel holds one workgroup per CU; it takes units from a
   // counter, so when the 32-bit kernel does the work it costs one short wave
   // per workgroup
-  const unsigned wblocks = (unsigned)(ntiles < 1024 ? ntiles : 1024);
+  const unsigned wblocks = (unsigned)(nunits < 1024 ? nunits : 1024);
   hipLaunchKernelGGL((k_deposit<P, IL, true, WRAP, WT, false>), dim3(wblocks),
                      dim3(threads ? threads : 512), 0, s, (const uint4*)b.recs, b.boff, b.bcnt,
-                     (float*)b.grid, g, b.stats, narrow ? 0 : 1, 1, 0, sw, q, ma, mb);
+                     (float*)b.grid, g, b.stats, narrow ? 0 : 1, 1, 0, sw, q, ma, mb,
+                     walk ? 1 : 0, seg);
 }
 
 template <int P, int IL, int WRAP>
