@@ -175,6 +175,7 @@ Geom make_geom(const est_config& c) {
   for (int d = 1; d <= kFineMax && d <= g.nb; ++d)
     if (g.nb % d == 0) g.fb = d;
   g.sa = g.nb / g.fb;
+  g.fb_mul = g.fb >= 2 ? (uint32_t)(4294967296ull / (uint64_t)g.fb + 1) : 0u;
   const int64_t nsup = (int64_t)c.batch * g.sa * g.sa * g.sa;
   // the two-level sort runs when nsup <= kMaxSuper; a larger value selects the atomic sort
   g.nsup = ((c.flags & EST_FLAG_ATOMIC_SORT) || nsup > kMaxSuper) ? kMaxSuper + 1 : (int)nsup;
@@ -205,7 +206,8 @@ size_t layout(const est_config& c, char* base, Buffers* b, void** tune_out) {
   bb.bcnt = (uint32_t*)take(nkeys * sizeof(uint32_t));
   const bool two_level = g.nsup <= kMaxSuper;
   bb.trecs = two_level ? (uint4*)take((size_t)c.max_particles * sizeof(uint4)) : nullptr;
-  const size_t nh = two_level ? (size_t)g.nsup * kMaxSortBlocks + 1 : 0;
+  // block-major histograms (kMaxSortBlocks rows of nsup) and the nsup + 1 super-bucket starts
+  const size_t nh = two_level ? (size_t)g.nsup * kMaxSortBlocks + g.nsup + 1 : 0;
   bb.hsup = two_level ? (uint32_t*)take(nh * sizeof(uint32_t)) : nullptr;
   const size_t nscan = nkeys > nh ? nkeys : nh;
   bb.scan_tmp = (uint32_t*)take(((nscan + 2047) / 2048 + 1) * sizeof(uint32_t));

@@ -39,6 +39,7 @@ struct Geom {
   int nb;         // buckets per axis = N / kBucket
   int tile;       // deposit tile edge
   int fb;         // buckets per super-bucket edge: min(kFineMax, nb)
+  uint32_t fb_mul;  // floor(2^32 / fb) + 1 (fb >= 2): x / fb = umulhi(x, fb_mul) for x < 2^16
   int sa;         // super-buckets per axis: nb / fb
   int nsup;       // batch * sa^3 (two-level sort when <= kMaxSuper)
   double box;     // L
@@ -74,7 +75,8 @@ struct Buffers {
   uint32_t* boff;          // batch * nb^3 + 1 bucket start offsets (key order)
   uint32_t* bcnt;          // batch * nb^3 bucket counts
   uint4* trecs;            // max_particles records in super-bucket order (two-level sort)
-  uint32_t* hsup;          // kMaxSuper * kMaxSortBlocks + 1 histogram / offsets
+  uint32_t* hsup;          // kMaxSortBlocks x nsup block-major histograms / offsets,
+                           // then the nsup + 1 super-bucket starts
   uint32_t* scan_tmp;      // scan block sums
   uint32_t* stats;         // [0] largest bucket count of the last sort, [1] tile counter,
                            // [4] largest mass (float bits), [5] nonzero if a mass is

@@ -337,11 +337,12 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
 // nblk workgroups histograms a contiguous chunk of particles over the
 // super-buckets in LDS; (B) the histograms, laid out super-major, are
 // scanned, giving every (super-bucket, workgroup) pair its output offset;
-// (C) each workgroup re-reads its chunk and moves every particle (position
-// and cell record) into its super-bucket segment, ranking with LDS
-// counters; (D) one workgroup per super-bucket counts its particles per
-// bucket, writes the bucket offsets and counts, and moves the records into
-// bucket order.  Pass (C) already writes records, not positions.  Buckets are therefore contiguous in z inside a super-bucket;
+// (C) each workgroup re-reads its chunk and moves every particle's record
+// into its super-bucket segment, ranking with LDS counters, and writes the
+// particle's bucket inside the super-bucket beside it (2 bytes); (D) one
+// workgroup per super-bucket counts its particles per bucket from those
+// 2-byte indices, writes the bucket offsets and counts, and moves the
+// records into bucket order.  Buckets are therefore contiguous in z inside a super-bucket;
 // the deposit splits its bucket runs at super-bucket boundaries.
 constexpr int kSortThreads = 1024;
 constexpr int kSortBatch = 4;  // particles per thread whose loads are in flight together
@@ -353,8 +354,14 @@ __device__ __forceinline__ void particle_buckets(double ux, double uy, double uz
   bz = bucket_of(uz, g);
 }
 
+// x / fb for a bucket index x (< 2^16): floor(x m / 2^32) with m = floor(2^32 / fb) + 1
+// is exact there, since the error x (m fb - 2^32) / (fb 2^32) < 2^-16 < 1/fb
+__device__ __forceinline__ int div_fb(int x, const Geom& g) {
+  return g.fb == 1 ? x : (int)__umulhi((uint32_t)x, g.fb_mul);
+}
+
 __device__ __forceinline__ int super_of(int mock, int bx, int by, int bz, const Geom& g) {
-  return ((mock * g.sa + bx / g.fb) * g.sa + by / g.fb) * g.sa + bz / g.fb;
+  return ((mock * g.sa + div_fb(bx, g)) * g.sa + div_fb(by, g)) * g.sa + div_fb(bz, g);
 }
 
 template <typename TP>
@@ -392,17 +399,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const TP* __restrict
   }
   __syncthreads();
   for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
-    hsup[(int64_t)i * nblk + blockIdx.x] = hist[i];
+    hsup[(int64_t)blockIdx.x * g.nsup + i] = hist[i];
 }
 
 template <typename TP>
 __global__ __launch_bounds__(kSortThreads) void k_sort_super(
     const TP* __restrict__ pos, int64_t n_total, const int64_t* __restrict__ offsets, Geom g,
-    int64_t chunk, int nblk, const uint32_t* __restrict__ hoff, uint4* __restrict__ trec,
-    const float* __restrict__ w, float* __restrict__ tw) {
+    int64_t chunk, const uint32_t* __restrict__ hoff, const uint32_t* __restrict__ base,
+    uint4* __restrict__ trec,
+    uint16_t* __restrict__ tfine, const float* __restrict__ w, float* __restrict__ tw) {
   __shared__ uint32_t cur[kMaxSuper];
   for (int i = threadIdx.x; i < g.nsup; i += kSortThreads)
-    cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
+    cur[i] = base[i] + hoff[(int64_t)blockIdx.x * g.nsup + i];
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = (j0 + chunk < n_total) ? j0 + chunk : n_total;
@@ -429,9 +437,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
         int bx, by, bz;
         particle_buckets(ux, uy, uz, g, bx, by, bz);
         const int sup = super_of(mlo == mhi ? mlo : mock_in(offsets, mlo, mhi, j), bx, by, bz, g);
-        const uint32_t fine = ((bx % g.fb) * g.fb + by % g.fb) * g.fb + bz % g.fb;
+        const int fx = bx - div_fb(bx, g) * g.fb, fy = by - div_fb(by, g) * g.fb;
+        const int fz = bz - div_fb(bz, g) * g.fb;
+        const uint32_t fine = (uint32_t)((fx * g.fb + fy) * g.fb + fz);
         const uint32_t p = atomicAdd(&cur[sup], 1u);
         trec[p] = with_fine(particle_record(ux, uy, uz, g), fine);
+        tfine[p] = (uint16_t)fine;
         if (w) tw[p] = w[j];
       }
     }
@@ -439,8 +450,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_super(
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
-    const uint4* __restrict__ trec, int64_t n_total, Geom g, int nblk,
-    const uint32_t* __restrict__ hoff, uint4* __restrict__ recs, uint32_t* __restrict__ boff,
+    const uint4* __restrict__ trec, const uint16_t* __restrict__ tfine, Geom g,
+    const uint32_t* __restrict__ base, uint4* __restrict__ recs, uint32_t* __restrict__ boff,
     uint32_t* __restrict__ bcnt, uint32_t* __restrict__ stats, const float* __restrict__ tw,
     float* __restrict__ sw) {
   constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
@@ -448,17 +459,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   __shared__ uint32_t wtot[kSortThreads / 64];
   const int sup = blockIdx.x;
   const int nf = g.fb * g.fb * g.fb;
-  const uint32_t seg0 = hoff[(int64_t)sup * nblk];
-  const uint32_t seg1 = (sup + 1 < g.nsup) ? hoff[(int64_t)(sup + 1) * nblk] : (uint32_t)n_total;
+  const uint32_t seg0 = base[sup], seg1 = base[sup + 1];
   for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
   __syncthreads();
+  // the histogram reads the 2-byte bucket indices, not the records
   for (uint32_t ib = seg0 + threadIdx.x; ib < seg1; ib += kSortBatch * kSortThreads) {
     uint32_t f[kSortBatch];
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q) {
       const uint32_t i = ib + q * kSortThreads;
-      // the bucket index sits in the top bytes of the z and w words
-      f[q] = (i < seg1) ? ((trec[i].z >> 24) | ((trec[i].w >> 24) << 8)) : 0u;
+      f[q] = (i < seg1) ? (uint32_t)tfine[i] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kSortBatch; ++q)
@@ -524,6 +534,41 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   }
 }
 
+// The histograms are stored block-major (h[b][s], b < nblk, s < nsup, so
+// that every pass reads and writes them in whole rows).  Per super-bucket s
+// this replaces h[b][s] by its exclusive prefix over the blocks and writes
+// the column total to tot[s].  A workgroup takes 64 consecutive s (one per
+// lane) and splits the blocks over its 16 waves.
+constexpr int kColThreads = 1024;
+constexpr int kColWaves = kColThreads / 64;
+
+__global__ __launch_bounds__(kColThreads) void k_sup_colscan(uint32_t* __restrict__ h, int nsup,
+                                                             int nblk, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t part[kColWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sup = blockIdx.x * 64 + lane;
+  const int b0 = nblk * wave / kColWaves, b1 = nblk * (wave + 1) / kColWaves;
+  uint32_t sum = 0;
+  if (sup < nsup)
+    for (int b = b0; b < b1; ++b) sum += h[(int64_t)b * nsup + sup];
+  part[wave][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, all = 0;
+  for (int w = 0; w < kColWaves; ++w) {
+    const uint32_t v = part[w][lane];
+    run += (w < wave) ? v : 0u;
+    all += v;
+  }
+  if (sup < nsup) {
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t v = h[(int64_t)b * nsup + sup];
+      h[(int64_t)b * nsup + sup] = run;
+      run += v;
+    }
+    if (wave == 0) tot[sup] = all;
+  }
+}
+
 template <typename TP>
 static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* offsets,
                                  int64_t n_total, const float* w, const Buffers& b, hipStream_t s) {
@@ -532,16 +577,24 @@ static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* of
   const int64_t chunk = (n_total + nblk - 1) / nblk;
   hipLaunchKernelGGL(k_sort_hist<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
                      offsets, g, chunk, nblk, b.hsup);
+  // per-block offsets inside each super-bucket, then the super-bucket starts
+  // (base[nsup] = n_total) after the kMaxSortBlocks rows of histograms
+  uint32_t* base = b.hsup + (size_t)g.nsup * kMaxSortBlocks;
+  hipLaunchKernelGGL(k_sup_colscan, dim3((g.nsup + 63) / 64), dim3(kColThreads), 0, s, b.hsup,
+                     g.nsup, nblk, base);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the scan's largest-entry output is not a bucket count here
-  if ((e = scan_in_place(b.hsup, (size_t)g.nsup * nblk, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
+  if ((e = scan_in_place(base, (size_t)g.nsup + 1, b.scan_tmp, b.stats + 2, s)) != hipSuccess)
     return e;
+  // the per-particle ranks of the atomic sort are not used here: their
+  // buffer holds each particle's bucket inside its super-bucket (2 bytes)
+  uint16_t* tfine = reinterpret_cast<uint16_t*>(b.rank);
   hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
-                     offsets, g, chunk, nblk, b.hsup, b.trecs, w, b.tw);
+                     offsets, g, chunk, b.hsup, (const uint32_t*)base, b.trecs, tfine, w, b.tw);
   hipLaunchKernelGGL(k_sort_fine, dim3(g.nsup), dim3(kSortThreads), 0, s, (const uint4*)b.trecs,
-                     n_total, g, nblk, b.hsup, b.recs, b.boff, b.bcnt, b.stats,
-                     w ? b.tw : nullptr, b.sw);
+                     (const uint16_t*)tfine, g, (const uint32_t*)base, b.recs,
+                     b.boff, b.bcnt, b.stats, w ? b.tw : nullptr, b.sw);
   return hipGetLastError();
 }
 
