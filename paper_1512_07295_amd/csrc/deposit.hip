@@ -21,17 +21,21 @@ namespace fsest {
 //    cell can overflow;
 //  * narrow (32-bit): S = 2^F with F chosen on the device from the largest
 //    bucket count M of this deposit.  A cell only receives particles whose
-//    base cell lies in a 5^3 block, which meets at most 8 buckets (27 for
-//    p = 5, 6), and one particle gives a cell at most w_max^3 (w_max the
-//    largest 1D weight of the order: 1, 1, 3/4, 2/3, 115/192, 11/20), so its
-//    sum is at most K (w_max^3 S + 1/2) units with K = 8 M (27 M) possible
-//    contributors; F is the largest value keeping that below 2^32.  When
-//    F < 24 (coarser than the float32 resolution of a unit weight) the wide
+//    first grid's first stencil cell lies within p + 1 cells of it per axis
+//    (at most 2 buckets per axis for p <= 4, 3 for p = 5, 6), and one
+//    particle gives a cell at most w_max^3 (w_max the largest 1D weight of
+//    the order: 1, 1, 3/4, 2/3, 115/192, 11/20), so its sum is at most
+//    K (w_max^3 S + 1/2) units with K = 8 M (27 M) possible contributors; F
+//    is the largest value keeping that below 2^32.  F >= 22 is required
+//    (24 with masses, where the unit is the largest mass), or the wide
 //    kernel runs instead (both are launched; the one not selected returns
-//    at once).
+//    at once).  Each contribution is rounded to 2^-(F+1) <= 2^-23 of a unit
+//    mass; F < 24 only happens when the largest bucket (64 cells) holds more
+//    than 32 (NGP) to 108 (PCS) particles, where cells sum several units and
+//    float32 accumulation would round each addition at least as coarsely.
 // Integer sums are exact, so deposits are bitwise reproducible.
 constexpr float kFixWide = 4294967040.0f;  // 2^32 - 2^8
-constexpr int kNarrowMinBits = 24;
+constexpr int kNarrowMinBits = 22;
 
 // The base cells of the particles that reach one cell span p + 1 cells per
 // axis (both grids), so they meet at most 2 buckets per axis for p <= 4 and
@@ -285,8 +289,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   // fixed-point format for this deposit (uniform over the grid; k_narrow
   // computed it from the sort's largest bucket count)
   const int nbits = (int)stats[6];
-  if (!WIDE && nbits < kNarrowMinBits) return;                // the wide kernel does it
-  if (WIDE && !exclusive && nbits >= kNarrowMinBits) return;  // the narrow one does it
+  // with masses the step is relative to the largest mass: F >= 24 there
+  constexpr int kMinBits = WT ? 24 : kNarrowMinBits;
+  if (!WIDE && nbits < kMinBits) return;                // the wide kernel does it
+  if (WIDE && !exclusive && nbits >= kMinBits) return;  // the narrow one does it
   const float scale = WIDE ? kFixWide : ldexpf(1.0f, nbits);
   const double inv_scale = 1.0 / (double)scale;
   // masses: items carry w / w_max (in [0, 1], so the bounds above hold) and

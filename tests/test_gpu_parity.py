@@ -303,6 +303,25 @@ def test_dense_tiles_deposit_their_item_list_several_times(torch, choice):
     est.close()
 
 
+@pytest.mark.parametrize("choice", [7, 4])
+def test_dense_buckets_keep_the_32_bit_format_down_to_22_bits(torch, choice):
+    """80000 particles on 32^3 (about 160 per 4^3 bucket, at most ~200): the
+    bound 8 M (w_max^3 2^F + 1/2) < 2^32 gives F = 23 for PCS, below 24 but
+    above the 22-bit minimum, so the 32-bit kernel deposits (choice 7); the
+    64-bit kernel (choice 4) gives the same grids within the same tolerance."""
+    box, n = 100.0, 32
+    pos = synth.uniform(80000, box, 14, np.float32)
+    est = _est(torch, n, box, 4, True, maxp=len(pos))
+    est.set_launch(choice)
+    est.deposit(to_dev(torch, pos))
+    r1, r2 = assign.deposit(pos, box, n, 4, True)
+    assert np.max(np.abs(est.copy_grid(1).cpu().numpy() - r1)) <= 2e-6 * r1.max()
+    assert np.max(np.abs(est.copy_grid(2).cpu().numpy() - r2)) <= 2e-6 * r2.max()
+    _, pk, _ = est.power(to_dev(torch, pos))
+    assert rel_err(pk.cpu().numpy()[0], oracle.power(pos, box, n, 4, True)[1]) < P_TOL
+    est.close()
+
+
 @pytest.mark.parametrize("n,p", [(16, 1), (16, 2), (32, 1), (32, 2), (32, 4), (24, 1), (24, 2),
                                  (40, 4)])
 @pytest.mark.parametrize("choice", [None, 42])
