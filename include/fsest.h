@@ -201,11 +201,13 @@ est_status estimator_graph_capture(est_handle h, const void* pos,
 est_status estimator_graph_launch(est_handle h);
 
 /* Pick this handle's launch shapes (strided-FFT lines per workgroup, P(k)
- * reduction workgroups, deposit workgroup size, 32- or 64-bit fixed-point
- * deposit, deposit tiles grouped per XCD) by timing the whole pipeline on the
- * given input `iters` times per candidate, one parameter at a time.  Returns
- * the chosen combination as an index in [0, 48) in *choice.  Results do not
- * depend on the choice beyond rounding.  Host-synchronising. */
+ * reduction workgroups, deposit workgroup size, deposit work grouped per
+ * XCD) by timing the whole pipeline on the given input `iters` times per
+ * candidate, one parameter at a time.  The 32-bit fixed-point deposit stays
+ * selected (it runs only where provably safe); estimator_set_launch can
+ * force the 64-bit one.  Returns the chosen combination as an index in
+ * [0, 48) in *choice.  Results do not depend on the choice beyond rounding.
+ * Host-synchronising. */
 est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype,
                               const int64_t* offsets, int64_t n_total,
                               int32_t n_dk, int32_t n_bins, int32_t iters,

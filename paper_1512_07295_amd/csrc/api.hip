@@ -169,11 +169,27 @@ Geom make_geom(const est_config& c) {
   g.il = c.interlace ? 1 : 0;
   g.batch = c.batch;
   g.nb = c.n_grid / kBucket;
-  // largest divisor of nb up to kFineMax (at least 5 whenever nb > kFineMax,
-  // since nb has no prime factor above 5), so super-buckets tile the axis
-  g.fb = 1;
-  for (int d = 1; d <= kFineMax && d <= g.nb; ++d)
-    if (g.nb % d == 0) g.fb = d;
+  // Super-bucket edge fb: a divisor of nb up to kFineMax, so super-buckets
+  // tile the axis, and at least 5 unless it is nb itself, so that a deposit
+  // run of up to 6 buckets in z meets at most one super-bucket edge (nb has
+  // no prime factor above 5, so such a divisor exists when nb > kFineMax).
+  // Of these, the smallest whose super-bucket count batch (nb/fb)^3 stays at
+  // or below max_particles / 16384: about 16K particles per super-bucket,
+  // enough per (workgroup chunk, super-bucket) for whole-line writes in the
+  // super-bucket pass, and as many super-buckets as that allows for the
+  // bucket pass, which runs one workgroup per super-bucket (many uneven sets
+  // then spread over the chip).  If none qualifies, the largest.
+  {
+    const int64_t target = c.max_particles / 16384 > 1 ? c.max_particles / 16384 : 1;
+    int small_ok = 0, largest = 0;
+    for (int d = 1; d <= kFineMax && d <= g.nb; ++d) {
+      if (g.nb % d != 0 || (d < 5 && d != g.nb)) continue;
+      largest = d;
+      const int64_t sa = g.nb / d;
+      if (!small_ok && (int64_t)c.batch * sa * sa * sa <= target) small_ok = d;
+    }
+    g.fb = small_ok ? small_ok : largest;
+  }
   g.sa = g.nb / g.fb;
   g.fb_mul = g.fb >= 2 ? (uint32_t)(4294967296ull / (uint64_t)g.fb + 1) : 0u;
   const int64_t nsup = (int64_t)c.batch * g.sa * g.sa * g.sa;
@@ -667,11 +683,12 @@ est_status estimator_graph_launch(est_handle h) {
   return ok();
 }
 
-static Tune tune_from_index(const int* id) {
+static Tune tune_from_index(const int* id, int cus) {
   static const int vals_cols[2] = {8, 16};
   static const int vals_bins[3] = {256, 1024, 2048};
   static const int vals_dep[2] = {512, 1024};
   Tune t;
+  t.cus = cus;
   t.cols_c = vals_cols[id[0]];
   t.bin_blocks = vals_bins[id[1]];
   t.dep_threads = vals_dep[id[2]];
@@ -690,7 +707,7 @@ est_status estimator_set_launch(est_handle h, int32_t choice) {
   id[2] = (choice / 4) % 2;
   id[1] = (choice / 8) % 3;
   id[0] = choice / 24;
-  h->tu = tune_from_index(id);
+  h->tu = tune_from_index(id, h->tu.cus);
   return ok();
 }
 
@@ -735,11 +752,15 @@ est_status estimator_autotune(est_handle h, const void* pos, est_dtype dtype, co
     return dev_err(hipEventElapsedTime(ms, e0, e1), "elapsed time");
   };
   int idx[5] = {1, 1, 0, 1, 1};  // start from the defaults
-  auto make = [&](const int* id) { return tune_from_index(id); };
-  const int nvals[5] = {2, 3, 2, 2, 2};
+  const int cus = h->tu.cus;
+  auto make = [&](const int* id) { return tune_from_index(id, cus); };
+  // the 32-bit deposit format (parameter 3) is not a launch shape: it stays
+  // on (it is used only when provably safe, and is then always the faster)
+  const int nvals[5] = {2, 3, 2, 1, 2};
   float best_ms = 1e30f;
   if (st == EST_OK) st = measure(make(idx), &best_ms);
   for (int p = 0; p < 5 && st == EST_OK; ++p) {
+    if (nvals[p] < 2) continue;
     int best_v = idx[p];
     for (int v = 0; v < nvals[p] && st == EST_OK; ++v) {
       if (v == idx[p]) continue;

@@ -254,9 +254,9 @@ __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_
 // Workgroups loop over units b, b + gridDim, ... (a persistent grid of a few
 // workgroups per CU, so the per-workgroup set-up is paid once per many
 // units); `dynamic`: units are taken from a global counter (stats[1],
-// zeroed with the sort) instead.  `xcd`: consecutive units go to the same
-// XCD (workgroup b runs on XCD b mod 8), so the buckets that neighbouring
-// columns share are read through one L2.
+// zeroed with the sort) instead.  `xcd`: runs of consecutive units go to
+// the same XCD (workgroup b runs on XCD b mod 8), so the buckets that
+// neighbouring columns share are read through one L2.
 // WT: per-particle masses (sw, bucket order, divided by the largest mass);
 // a separate instantiation so that the equal-mass kernel keeps its registers
 // IL: 0 one grid; 1 the interlaced pair (masks 0 and 7); 2 a pair of grids
@@ -309,9 +309,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   const uint32_t nunits = (uint32_t)g.batch * units_per_set;
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // workgroup b runs on XCD b mod 8: with xcd, the units of XCD x are the
-  // x-th eighth, taken in order by its workgroups (gridDim a multiple of 8)
-  const bool remap = xcd && !dynamic && (gridDim.x & 7) == 0 && (nunits & 7) == 0;
+  // workgroup b runs on XCD b mod 8: with xcd, the units are dealt to the
+  // XCDs in chunks of kXcdChunk consecutive units (XCD x takes chunks x,
+  // x + 8, ...), each XCD's workgroups taking its units in order (gridDim a
+  // multiple of 8); chunks rather than eighths, so that sets of very
+  // different sizes in a batch still spread over all XCDs
+  constexpr uint32_t kXcdChunk = 16;
+  const bool remap =
+      xcd && !dynamic && (gridDim.x & 7) == 0 && (nunits % (8 * kXcdChunk)) == 0;
   // buckets below a tile whose particles can reach it (see the ranges below)
   constexpr int kLow = (P - 1 + (IL ? 1 : 0) + kBucket - 1) / kBucket;
 
@@ -322,7 +327,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
     b = (uint32_t)next_tile;
   }
   while (b < nunits) {
-    const uint32_t uid = remap ? ((b & 7) * (nunits >> 3) + (b >> 3)) : b;
+    const uint32_t li = b >> 3;  // the unit's index among its XCD's units
+    const uint32_t uid =
+        remap ? ((li / kXcdChunk) * 8 + (b & 7)) * kXcdChunk + li % kXcdChunk : b;
     const int mock = (int)(uid / units_per_set);
     const int urem = (int)(uid % units_per_set);
     const int tx = urem / (tpa * upc), ty = (urem / upc) % tpa, sg = urem % upc;
