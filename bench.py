@@ -69,13 +69,13 @@ def algorithmic_bytes(label, n_particles, n, nz, n_grids, nkeys, sets=1):
     particle sets of n^3 cells each)."""
     cells = sets * n * n * nz
     return {
-        # positions read twice (histogram, super-bucket pass); positions and
-        # 8-byte cell records written and read once in super-bucket order and
-        # written once in bucket order (12 + 12 + 20 + 20 + 20 B); bucket
-        # offsets and counts written
-        "bucket_sort": 84 * n_particles + 8 * nkeys,
-        # positions read once, every grid written once
-        "deposit": 12 * n_particles + 4 * n_grids * sets * n * n * n,
+        # positions read twice (histogram, super-bucket pass); 16-byte
+        # records written and read once in super-bucket order with their
+        # 2-byte bucket index, and written once in bucket order
+        # (12 + 12 + 18 + 18 + 16 B); bucket offsets and counts written
+        "bucket_sort": 76 * n_particles + 8 * nkeys,
+        # 16-byte records read once, every grid written once
+        "deposit": 16 * n_particles + 4 * n_grids * sets * n * n * n,
         # complex grid read and written once per pass
         "fft_x": 16 * cells,
         "fft_y": 16 * cells,

@@ -209,23 +209,31 @@ __device__ __forceinline__ void deposit_item(uint4 rec, int gi, const Geom& g, i
   }
 }
 
-// Segment of each lane's candidate: a scalar search for the wave's first
-// item c0, then the few segment starts inside the wave's 64 items.
+// Segment of each lane's candidate `item` (the wave's candidates are c0 ..
+// c0 + 63): the last t < nr with pref[t] <= item, i.e. the number of
+// starts pref[0..nr] at or below it, minus one (pref[nr] = total lies above
+// every candidate; empty pieces repeat a start and count twice, which
+// still lands on the non-empty piece).  Lane t holds starts t and t + 64:
+// one ballot counts those at or below c0 for the whole wave, and the few
+// inside the window are added lane by lane.
 __device__ __forceinline__ int find_segment(const DepRanges& rg, int nr, uint32_t c0,
-                                            uint32_t item) {
-  int lo = 0, hi = nr;  // pref[lo] <= c0 < pref[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)rg.pref[mid]) <= c0) lo = mid;
-    else hi = mid;
+                                            uint32_t item, int lane) {
+  const uint32_t pa = lane <= nr ? rg.pref[lane] : 0xFFFFFFFFu;
+  const uint32_t pb = lane + 64 <= nr ? rg.pref[lane + 64] : 0xFFFFFFFFu;
+  int cnt = __popcll(__ballot(pa <= c0)) + __popcll(__ballot(pb <= c0));
+  unsigned long long ia = __ballot(pa > c0 && pa <= c0 + 63);
+  unsigned long long ib = __ballot(pb > c0 && pb <= c0 + 63);
+  while (ia) {
+    const int t = __builtin_ctzll(ia);
+    cnt += item >= (uint32_t)__builtin_amdgcn_readlane((int)pa, t) ? 1 : 0;
+    ia &= ia - 1;
   }
-  int seg = lo;
-  for (int t = lo + 1; t < nr; ++t) {
-    const uint32_t pt = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.pref[t]);
-    if (pt > c0 + 63) break;
-    if (item >= pt) seg = t;
+  while (ib) {
+    const int t = __builtin_ctzll(ib);
+    cnt += item >= (uint32_t)__builtin_amdgcn_readlane((int)pb, t) ? 1 : 0;
+    ib &= ib - 1;
   }
-  return seg;
+  return cnt - 1;
 }
 
 // One workgroup owns one T^3 output tile (T = min(kTileMax, N)) of every
@@ -501,7 +509,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           jj[q] = 0;
           rec[q] = make_uint2(0u, 0u);
           if (r0 < total) {
-            const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item);
+            const int seg = find_segment(rg, nr, r0 + (uint32_t)(wave * 64), item, lane);
             if (item < total) {
               jj[q] = rg.start[seg] + (item - rg.pref[seg]);
               // cells and steps: the record's x word and the y word's step bit
