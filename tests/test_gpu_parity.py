@@ -77,6 +77,23 @@ def test_power_parity_zeldovich_f32(torch, p, il):
     est.close()
 
 
+@pytest.mark.parametrize("n,p,il", [(128, 4, True), (256, 4, True), (256, 3, False)])
+def test_power_parity_staged_rows(torch, n, p, il):
+    """Grids of 128^3 and 256^3: rows of 128 to 256 elements in the fused z
+    + P(k) pass, several row groups per workgroup and a ragged last group."""
+    box = 1000.0
+    pos = synth.zeldovich(32, box, 9 + n, dtype=np.float32)
+    est = _est(torch, n, box, p, il, maxp=len(pos))
+    k0, p0, n0 = oracle.power(pos, box, n, p, il)
+    for choice in (None, 0):  # default and 256 reduction workgroups
+        if choice is not None:
+            est.set_launch(choice)
+        k, pk, nm = est.power(to_dev(torch, pos))
+        assert np.array_equal(nm.cpu().numpy()[0], n0)
+        assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
 def test_power_parity_f64_positions_cic(torch):
     """Config-1 shape: 32^3 uniform float64 particles, 32^3 grid, CIC, no interlacing."""
     box = 1000.0
