@@ -38,10 +38,10 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
                     "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
-        "sha256_16": "fcf6e98a7ee68a9e",
+        "sha256_16": "e16839467d04486e",
         "workload": "pcs_il_n1024_za512",
-        "read_bytes": 2 * 4500062 * 1024,
-        "write_bytes": 8388612 * 1024,
+        "read_bytes": 2 * 1836578 * 1024,
+        "write_bytes": 8388622 * 1024,
     },
 }
 
