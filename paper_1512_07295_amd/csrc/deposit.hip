@@ -132,8 +132,8 @@ __device__ __forceinline__ int rel_first(int first, int t0, int n) {
     r = r < 0 ? r + n : r;
     return r >= n ? r - n : r;
   } else if constexpr (WRAP == kMasked) {
-    r &= n - 1;
-    return (r >= n - (P - 1)) ? r - n : r;
+    // ((r + P - 1) mod N) - (P - 1): the same map in three operations
+    return ((r + (P - 1)) & (n - 1)) - (P - 1);
   } else {
     r = r < -(P - 1) ? r + n : r;
     return (r >= n - (P - 1)) ? r - n : r;
@@ -155,21 +155,25 @@ __device__ __forceinline__ int bank_class(int rx, int ry, int rz) {
 // the tile.  Grid gi is sampled at u + 1/2 on the axes whose bit is set in
 // its mask mk: there the first cell moves by the record's step and the
 // offset by -/+ 1/2.
-template <int P, typename AT, int WRAP>
+template <int P, typename AT, int WRAP, int IL>
 __device__ __forceinline__ void deposit_item(uint4 rec, int gi, const Geom& g, int t0x, int t0y,
                                              int t0z, AT* sm, float scale, int mk) {
   const int n = g.n;
   constexpr int off = (P % 2 == 0) ? (P / 2 - 1) : (P - 1) / 2;
   const int sx = (int)((rec.x >> 30) & 1u), sy = (int)(rec.x >> 31), sz = (int)((rec.y >> 24) & 1u);
+  // the interlaced pair's second grid is shifted on all three axes
+  const bool hx = IL == 1 ? gi != 0 : (mk & 1) != 0;
+  const bool hy = IL == 1 ? gi != 0 : (mk & 2) != 0;
+  const bool hz = IL == 1 ? gi != 0 : (mk & 4) != 0;
   float wx[P], wy[P], wz[P];
-  weights_from_offset<P>(record_offset<P>(rec.y, sx, (mk & 1) != 0), wx);
-  weights_from_offset<P>(record_offset<P>(rec.z, sy, (mk & 2) != 0), wy);
-  weights_from_offset<P>(record_offset<P>(rec.w, sz, (mk & 4) != 0), wz);
+  weights_from_offset<P>(record_offset<P>(rec.y, sx, hx), wx);
+  weights_from_offset<P>(record_offset<P>(rec.z, sy, hy), wy);
+  weights_from_offset<P>(record_offset<P>(rec.w, sz, hz), wz);
 #pragma unroll
   for (int i = 0; i < P; ++i) wx[i] *= scale;
-  const int fx = (int)(rec.x & 1023u) - off + ((mk & 1) ? sx : 0);
-  const int fy = (int)((rec.x >> 10) & 1023u) - off + ((mk & 2) ? sy : 0);
-  const int fz = (int)((rec.x >> 20) & 1023u) - off + ((mk & 4) ? sz : 0);
+  const int fx = (int)(rec.x & 1023u) - off + (hx ? sx : 0);
+  const int fy = (int)((rec.x >> 10) & 1023u) - off + (hy ? sy : 0);
+  const int fz = (int)((rec.x >> 20) & 1023u) - off + (hz ? sz : 0);
   constexpr bool PERIODIC = WRAP == kPeriodic;
   const int rx = rel_first<P, WRAP>(fx, t0x, n);
   const int ry = rel_first<P, WRAP>(fy, t0y, n);
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
             if constexpr (WT) sc *= sw[item_j[e_cur]];
             const int gi = item_meta[e_cur] >> 6;
             const int mk = (IL == 2) ? (gi ? mask_b : mask_a) : (gi ? 7 : 0);
-            deposit_item<P, AT, WRAP>(rc, gi, g, t0x, t0y, t0z, sm, sc, mk);
+            deposit_item<P, AT, WRAP, IL>(rc, gi, g, t0x, t0y, t0z, sm, sc, mk);
           }
           e_cur = e_nxt;
           rc = rn;
