@@ -96,7 +96,9 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   }
   __shared__ float2 rows[PairShape<L>::ROWS_LDS];
   __shared__ double hist[kMaxBins];
-  // per half-space z index: the z part of the phase and 1/W^2
+  // per half-space z index: the z part of the phase, and 1/W^2 times the
+  // mode's weight in the half-space sum (1 on the planes mz = 0 and N/2,
+  // which hold their own mirror images, 2 elsewhere)
   __shared__ float4 ztab[MODE != 2 ? kMaxBins + 1 : 1];
 
   const int n = g.n;
@@ -114,7 +116,8 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
     for (int i = threadIdx.x; i <= n / 2; i += blockDim.x) {
       // interlaced: exp(+i pi mz/N); packed: exp(-2 pi i mz/N)
       const float2 ph = IL ? phase[i] : cconj(phase[mod_2n<P2>(2 * i, n)]);
-      ztab[i] = make_float4(ph.x, ph.y, inv_w2[i], 0.0f);
+      const float wgt = (i == 0 || i == n / 2) ? 1.0f : 2.0f;
+      ztab[i] = make_float4(ph.x, ph.y, wgt * inv_w2[i], 0.0f);
     }
   }
 
@@ -156,14 +159,14 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
           const float wxy = inv_w2[xr] * inv_w2[yr] * (IL ? 0.0625f : 0.25f);
           const float2 ph_xy = IL ? phase[mod_2n<P2>(mxr + myr, n)] : make_float2(1.0f, 0.0f);
           const int r2 = mxr * mxr + myr * myr;
-          const int m2_0 = r2 + z0 * z0;
-          int b = m2_0 ? shell_of(m2_0, n_dk) : 0;
+          int m2 = r2 + z0 * z0;  // |m|^2 of mode mz, advanced by 2 mz + 1 per step
+          int b = m2 ? shell_of(m2, n_dk) : 0;
           int edge = (2 * b + 1) * n_dk;
           edge *= edge;
           int cur_b = -1;
           float cur = 0.0f;
-          for (int mz = z0; mz < z1; ++mz) {
-            const int m4 = 4 * (r2 + mz * mz);
+          for (int mz = z0; mz < z1; m2 += 2 * mz + 1, ++mz) {
+            const int m4 = 4 * m2;
             while (edge <= m4) {
               ++b;
               edge = (2 * b + 1) * n_dk;
@@ -183,8 +186,7 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
             }
             const float4 zt = ztab[mz];
             const float2 ph = IL ? cmul(ph_xy, make_float2(zt.x, zt.y)) : make_float2(zt.x, zt.y);
-            const float wgt = (mz == 0 || mz == n / 2) ? 1.0f : 2.0f;
-            const float val = wgt * pair_power(za, zb, ph) * zt.z;
+            const float val = pair_power(za, zb, ph) * zt.z;
             if (b != cur_b) {
               if (cur_b > 0) atomicAdd(&hist[cur_b - 1], (double)(cur * wxy));
               cur_b = b;
