@@ -38,10 +38,10 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
                     "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
-        "sha256_16": "e16839467d04486e",
+        "sha256_16": "206332fbdabb94b7",
         "workload": "pcs_il_n1024_za512",
-        "read_bytes": 2 * 1836578 * 1024,
-        "write_bytes": 8388622 * 1024,
+        "read_bytes": 2 * 1835382 * 1024,
+        "write_bytes": 8388619 * 1024,
     },
 }
 
