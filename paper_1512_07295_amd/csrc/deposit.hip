@@ -84,6 +84,7 @@ constexpr int kRow = 28;
 constexpr int kPlane = 464;
 constexpr int kGridWords = kTileMax * kPlane;
 constexpr int kItemCap = 2048;
+static_assert(kItemCap >= 2 * 1024, "an empty list holds a whole round of items (two grids)");
 constexpr int kAccWord = kItemCap + kItemCap / 4 + kItemCap / 2;
 
 constexpr bool offsets_cover_banks() {
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
   constexpr int kWords = acc_first_word<AT>() + NG * kGridWords * (int)(sizeof(AT) / 4);
   __shared__ __align__(16) uint32_t smem[kWords];
   __shared__ DepRanges rg;
-  __shared__ int round_cnt[2];
+  __shared__ int round_cnt[3];
   __shared__ int cls_cnt[64];
   __shared__ int cls_cur[64];
   __shared__ int next_tile;
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
       const int ex = min(T, n - t0x), ey = min(T, n - t0y), ez = min(T, n - t0z);
 
       if (threadIdx.x < 64) cls_cnt[threadIdx.x] = 0;
-      if (threadIdx.x < 2) round_cnt[threadIdx.x] = 0;
+      if (threadIdx.x < 3) round_cnt[threadIdx.x] = 0;
 
       // bucket neighbourhood: particles are bucketed by their first grid's
       // first stencil cell f, and a stencil of either grid reaches the tile
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
         __syncthreads();
       };
       int fill = 0;  // items in the list (the same value in every thread)
-      int rpar = 0;  // which of the two round counters this round uses
+      int rpar = 0;  // which of the three round counters this round uses
 
       // rounds of blockDim candidates; the cell records of kPre rounds are
       // loaded together so that their latencies overlap (one round where the
@@ -579,30 +580,42 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(CAP ? 8 : 
           int before = 0;
           if (lane == 0) before = atomicAdd(&round_cnt[rpar], mine);
           before = __builtin_amdgcn_readfirstlane(before);
-          __syncthreads();
-          const int tot = round_cnt[rpar];
-          // the other counter was last read before the previous round's
-          // insertion barrier and is next used after this round's
-          if (threadIdx.x == 0) round_cnt[rpar ^ 1] = 0;
-          rpar ^= 1;
-          // (2) the list is deposited first if this round's items would not fit
-          if (fill + tot > kItemCap) {
-            deposit_list(fill);
-            fill = 0;
-          }
-          const unsigned long long below = (1ull << lane) - 1ull;
-          int pos = fill + before;
+          // three counters in turn: the next round's was last read before
+          // the previous round's last barrier and is next used after this
+          // round's
+          if (threadIdx.x == 0) round_cnt[rpar == 2 ? 0 : rpar + 1] = 0;
+          auto insert = [&](int pos) __attribute__((always_inline)) {
+            const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
-          for (int gi = 0; gi < NG; ++gi) {
-            if (ok[gi]) {
-              const int p = pos + __popcll(bal[gi] & below);
-              item_j[p] = j;
-              item_meta[p] = (uint8_t)(cls[gi] | (gi << 6));
-              atomicAdd(&cls_cnt[cls[gi]], 1);
+            for (int gi = 0; gi < NG; ++gi) {
+              if (ok[gi]) {
+                const int p = pos + __popcll(bal[gi] & below);
+                item_j[p] = j;
+                item_meta[p] = (uint8_t)(cls[gi] | (gi << 6));
+                atomicAdd(&cls_cnt[cls[gi]], 1);
+              }
+              pos += __popcll(bal[gi]);
             }
-            pos += __popcll(bal[gi]);
+          };
+          int tot;
+          if (fill == 0) {
+            // an empty list holds any round (at most NG x blockDim items):
+            // insert at once, learn the round's total after the barrier
+            insert(before);
+            __syncthreads();
+            tot = round_cnt[rpar];
+          } else {
+            __syncthreads();
+            tot = round_cnt[rpar];
+            // (2) the list is deposited first if this round's items would not fit
+            if (fill + tot > kItemCap) {
+              deposit_list(fill);
+              fill = 0;
+            }
+            insert(fill + before);
+            __syncthreads();
           }
-          __syncthreads();
+          rpar = rpar == 2 ? 0 : rpar + 1;
           fill += tot;
           if (r0 + nthreads >= total) {  // the last round: deposit what is left
             deposit_list(fill);
