@@ -38,10 +38,10 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_1512_07295_amd/csrc/deposit.hip",
                     "paper_1512_07295_amd/csrc/particles.hpp",
                     "paper_1512_07295_amd/csrc/fsest_internal.hpp"],
-        "sha256_16": "206332fbdabb94b7",
+        "sha256_16": "ed4bfdfd521b6dbe",
         "workload": "pcs_il_n1024_za512",
-        "read_bytes": 2 * 1835382 * 1024,
-        "write_bytes": 8388619 * 1024,
+        "read_bytes": 2 * 1835336 * 1024,
+        "write_bytes": 8388615 * 1024,
     },
 }
 
