@@ -39,16 +39,21 @@ __global__ __launch_bounds__(RowShape<L>::LPB * RowShape<L>::TPL) void k_fft_row
   if (valid) static_for<0, EPT>([&](auto e) { p[t + e * TPL] = v[e]; });
 }
 
+// spread > 0: the chunks of one outer block form spread rows of
+// chunks_per_outer / spread chunks, and consecutive workgroups take the same
+// chunk of consecutive rows (for the x pass: consecutive y at one z range,
+// measured 5.02 -> 4.91 ms at 1024^3 against consecutive z chunks of one y).
 template <int L, int DIR, int C>
 __global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols(
     float2* __restrict__ data, int64_t elem_stride, int64_t chunks_per_outer, int64_t outer_stride,
-    const float2* __restrict__ tw) {
+    const float2* __restrict__ tw, int64_t spread) {
   constexpr int TPL = LinePlan<L>::TPL;
   constexpr int EPT = LinePlan<L>::EPT;
   extern __shared__ float2 lds_dyn[];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int64_t outer = blockIdx.x / chunks_per_outer;
-  const int64_t ic = blockIdx.x % chunks_per_outer;
+  const int64_t ib = blockIdx.x % chunks_per_outer;
+  const int64_t ic = spread ? (ib % spread) * (chunks_per_outer / spread) + ib / spread : ib;
   float2* p = data + outer * outer_stride + ic * C + c;
   float2 v[EPT];
   static_for<0, EPT>([&](auto e) { v[e] = p[(int64_t)(t + e * TPL) * elem_stride]; });
@@ -67,8 +72,9 @@ static hipError_t rows_t(float2* data, int64_t nrows, int rpp, int64_t ps, const
 
 template <int L, int DIR, int C>
 static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
-                          int64_t outer_stride, const float2* tw, hipStream_t s) {
+                          int64_t outer_stride, int64_t spread, const float2* tw, hipStream_t s) {
   const int64_t chunks = inner / C;
+  if (spread && chunks % spread != 0) spread = 0;
   const size_t lds = sizeof(float2) * (size_t)L * C;
   static bool attr_set = false;
   if (!attr_set) {
@@ -77,16 +83,20 @@ static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int6
     attr_set = true;
   }
   hipLaunchKernelGGL((k_fft_cols<L, DIR, C>), dim3((unsigned)(chunks * outer)),
-                     dim3(C * LinePlan<L>::TPL), lds, s, data, elem_stride, chunks, outer_stride, tw);
+                     dim3(C * LinePlan<L>::TPL), lds, s, data, elem_stride, chunks, outer_stride, tw,
+                     spread);
   return hipGetLastError();
 }
 
 template <int L, int DIR>
 static hipError_t cols_t(float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
-                         int64_t outer_stride, int c, const float2* tw, hipStream_t s) {
-  if (c >= 16 && inner % 16 == 0) return cols_tc<L, DIR, 16>(data, elem_stride, inner, outer, outer_stride, tw, s);
-  if (c >= 8 && inner % 8 == 0) return cols_tc<L, DIR, 8>(data, elem_stride, inner, outer, outer_stride, tw, s);
-  return cols_tc<L, DIR, 4>(data, elem_stride, inner, outer, outer_stride, tw, s);
+                         int64_t outer_stride, int64_t spread, int c, const float2* tw,
+                         hipStream_t s) {
+  if (c >= 16 && inner % 16 == 0)
+    return cols_tc<L, DIR, 16>(data, elem_stride, inner, outer, outer_stride, spread, tw, s);
+  if (c >= 8 && inner % 8 == 0)
+    return cols_tc<L, DIR, 8>(data, elem_stride, inner, outer, outer_stride, spread, tw, s);
+  return cols_tc<L, DIR, 4>(data, elem_stride, inner, outer, outer_stride, spread, tw, s);
 }
 
 // ---- lengths 2^a 3^b 5^c (run-time plan) ----
@@ -203,18 +213,22 @@ static hipError_t rows_dir(int L, float2* data, int64_t nrows, int rpp, int64_t 
 
 template <int DIR>
 static hipError_t cols_dir(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
-                           int64_t outer_stride, int c, const float2* tw, hipStream_t s) {
+                           int64_t outer_stride, int64_t spread, int c, const float2* tw,
+                           hipStream_t s) {
+#define FSEST_COLS_CASE(LL) \
+  case LL: return cols_t<LL, DIR>(data, elem_stride, inner, outer, outer_stride, spread, c, tw, s);
   switch (L) {
-    case 8: return cols_t<8, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 16: return cols_t<16, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 32: return cols_t<32, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 64: return cols_t<64, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 128: return cols_t<128, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 256: return cols_t<256, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 512: return cols_t<512, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
-    case 1024: return cols_t<1024, DIR>(data, elem_stride, inner, outer, outer_stride, c, tw, s);
+    FSEST_COLS_CASE(8)
+    FSEST_COLS_CASE(16)
+    FSEST_COLS_CASE(32)
+    FSEST_COLS_CASE(64)
+    FSEST_COLS_CASE(128)
+    FSEST_COLS_CASE(256)
+    FSEST_COLS_CASE(512)
+    FSEST_COLS_CASE(1024)
     default: return cols_rt<DIR>(L, data, elem_stride, inner, outer, outer_stride, tw, s);
   }
+#undef FSEST_COLS_CASE
 }
 
 hipError_t launch_fft_rows_len(int L, float2* data, int64_t nrows, int rows_per_plane,
@@ -225,8 +239,8 @@ hipError_t launch_fft_rows_len(int L, float2* data, int64_t nrows, int rows_per_
 
 hipError_t launch_fft_cols_len(int L, float2* data, int64_t elem_stride, int64_t inner, int64_t outer,
                                int64_t outer_stride, int dir, int c, const float2* tw, hipStream_t s) {
-  return dir < 0 ? cols_dir<-1>(L, data, elem_stride, inner, outer, outer_stride, c, tw, s)
-                 : cols_dir<+1>(L, data, elem_stride, inner, outer, outer_stride, c, tw, s);
+  return dir < 0 ? cols_dir<-1>(L, data, elem_stride, inner, outer, outer_stride, 0, c, tw, s)
+                 : cols_dir<+1>(L, data, elem_stride, inner, outer, outer_stride, 0, c, tw, s);
 }
 
 hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int batch, int nz_len,
@@ -237,20 +251,25 @@ hipError_t launch_fft_axis(const Geom& g, float2* data, int axis, int dir, int b
     return dir < 0 ? rows_dir<-1>((int)nz, data, nrows, (int)n, ps, tw_axis, s)
                    : rows_dir<+1>((int)nz, data, nrows, (int)n, ps, tw_axis, s);
   }
-  int64_t elem_stride, inner, outer, outer_stride;
+  int64_t elem_stride, inner, outer, outer_stride, spread;
   if (axis == 0) {
+    // x lines at each (y, z): workgroups spread over y first
     elem_stride = ps;
     inner = n * nz;
     outer = batch;
     outer_stride = n * ps;
+    spread = n;
   } else {
     elem_stride = nz;
     inner = nz;
     outer = (int64_t)batch * n;
     outer_stride = ps;
+    spread = 0;
   }
-  return dir < 0 ? cols_dir<-1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s)
-                 : cols_dir<+1>((int)n, data, elem_stride, inner, outer, outer_stride, tu.cols_c, tw_axis, s);
+  return dir < 0 ? cols_dir<-1>((int)n, data, elem_stride, inner, outer, outer_stride, spread,
+                                tu.cols_c, tw_axis, s)
+                 : cols_dir<+1>((int)n, data, elem_stride, inner, outer, outer_stride, spread,
+                                tu.cols_c, tw_axis, s);
 }
 
 }  // namespace fsest
