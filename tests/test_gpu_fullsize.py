@@ -8,6 +8,7 @@ times (autotuned the same way), on outputs the oracle can reach:
   delta(m) at sampled modes including Bragg peaks of the particle lattice on
   the Nyquist planes (1e-5 relative); the same particles and grid with
   NGP, CIC and TSC, with and without interlacing (sampled cells and modes);
+  P(k) and the adjoint with both strided-FFT workgroup shapes;
 * 256^3 particles on a 256^3 grid: all 128 P(k) shells (1e-5) and every
   one of the 3,384 closed bispectrum triangles of 2 k_f shells up to k_N/2
   (tolerance relative to the L1 scale of the summands);
@@ -154,6 +155,31 @@ def test_headline_other_orders_sampled(torch, headline, p, il):
     w = np.prod([kernels.window_1d(p, modes[:, a], 1024) for a in range(3)], axis=0)
     assert np.max(np.abs(got - ref) * w) <= 1e-5 * np.max(np.abs(ref) * w), (got, ref)
     est.close()
+
+
+def test_headline_strided_pass_shapes_agree(torch, headline, headline_oracle):
+    """The headline P(k) and its adjoint with 16 lines per strided-FFT
+    workgroup (the persistent kernel that prefetches the next chunk, forward
+    and inverse 1024-point lines) and with 8 (one chunk per workgroup): P(k)
+    of both against the FP64 oracle (1e-5), and the position gradients of
+    both within 1e-4 of the largest component (the adjoint's tolerance
+    against the oracle): the lines take the same operations in both kernels,
+    but the compiler may fuse their multiply-adds differently."""
+    pos, dpos, est = headline
+    k0, p0, n0, _ = headline_oracle
+    dldp = np.random.default_rng(11).standard_normal(512)
+    ddldp = to_dev(torch, dldp[None, :])
+    grads = []
+    for choice in (46, 22):  # 16 and 8 lines per workgroup, the rest equal
+        est.set_launch(choice)
+        _, pk, nm = est.power(dpos, n_bins=512)
+        assert np.array_equal(nm.cpu().numpy()[0], n0)
+        assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL, choice
+        grads.append(est.backward(dpos, ddldp, n_bins=512))
+    assert bool(torch.isfinite(grads[0]).all())
+    scale = float(grads[0].abs().max())
+    assert scale > 0 and float((grads[0] - grads[1]).abs().max()) <= 1e-4 * scale
+    est.autotune(dpos, n_bins=512, iters=1)
 
 
 def test_c2_power_all_shells_and_every_triangle(torch):
