@@ -67,17 +67,27 @@ __global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols(
 // a fixed grid of workgroups walks the chunks b = blockIdx.x + k gridDim.x,
 // and each loads the next chunk's elements into registers before the
 // transform of the current one, so that a CU's loads stay in flight while
-// it transforms and stores (x pass at 1024^3: 4.91 -> 4.28 ms in a probe).
-// Addresses are a uniform chunk base plus a 32-bit per-thread byte offset
-// (the host checks that it fits).  The twiddle pointer passes through an
-// empty asm statement in every iteration so that the compiler reloads the
-// twiddles per chunk instead of keeping them all in registers (which spills).
+// it transforms and stores.  1024-point lines take the 32 x 32 plan (32
+// threads per line, one LDS exchange).  At 1024^3 (probe, 16 lines per
+// workgroup): x pass 4.91 ms one chunk per workgroup, 4.26 ms prefetching
+// with the 16 x 16 x 4 plan, 3.93 ms with the 32 x 32 plan; y pass 4.00,
+// 3.96 and 3.65 ms.  Addresses are a uniform chunk base plus a 32-bit
+// per-thread byte offset (the host checks that it fits).  The twiddle
+// pointer passes through an empty asm statement in every iteration so that
+// the compiler reloads the twiddles per chunk instead of keeping them all in
+// registers (which spills).
+template <int L>
+struct PfPlan {
+  static constexpr int TPL = L == 1024 ? 32 : LinePlan<L>::TPL;
+  static constexpr int EPT = L / TPL;
+};
+
 template <int L, int DIR, int C>
-__global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols_pf(
+__global__ __launch_bounds__(C * PfPlan<L>::TPL) void k_fft_cols_pf(
     float2* __restrict__ data, int64_t elem_stride, int64_t chunks_per_outer, int64_t outer_stride,
     const float2* __restrict__ tw, int64_t spread, int64_t total) {
-  constexpr int TPL = LinePlan<L>::TPL;
-  constexpr int EPT = LinePlan<L>::EPT;
+  constexpr int TPL = PfPlan<L>::TPL;
+  constexpr int EPT = PfPlan<L>::EPT;
   extern __shared__ float2 lds_dyn[];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   auto chunk_base = [&](int64_t b) {
@@ -105,7 +115,8 @@ __global__ __launch_bounds__(C * LinePlan<L>::TPL) void k_fft_cols_pf(
     }
     const float2* twb = tw;
     asm volatile("" : "+s"(twb));
-    line_fft<L, DIR, C>(v, t, lds_dyn + c, twb);
+    if constexpr (L == 1024) line_fft_1024_r32<DIR, C>(v, t, lds_dyn + c, twb);
+    else line_fft<L, DIR, C>(v, t, lds_dyn + c, twb);
     static_for<0, EPT>([&](auto e) { *(float2*)(p + e * estep + voff) = v[e]; });
   }
 }
@@ -128,7 +139,7 @@ static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int6
   const size_t lds = sizeof(float2) * (size_t)L * C;
   if constexpr (L * C >= 16384) {
     const int64_t total = chunks * outer;
-    const int64_t span = ((int64_t)(LinePlan<L>::TPL - 1) * elem_stride + C) * (int64_t)sizeof(float2);
+    const int64_t span = ((int64_t)(PfPlan<L>::TPL - 1) * elem_stride + C) * (int64_t)sizeof(float2);
     if (cus > 0 && span < ((int64_t)1 << 32)) {
       static bool pf_attr_set = false;
       if (!pf_attr_set) {
@@ -138,7 +149,7 @@ static hipError_t cols_tc(float2* data, int64_t elem_stride, int64_t inner, int6
       }
       const int64_t grid = total < 2 * (int64_t)cus ? total : 2 * (int64_t)cus;
       hipLaunchKernelGGL((k_fft_cols_pf<L, DIR, C>), dim3((unsigned)grid),
-                         dim3(C * LinePlan<L>::TPL), lds, s, data, elem_stride, chunks,
+                         dim3(C * PfPlan<L>::TPL), lds, s, data, elem_stride, chunks,
                          outer_stride, tw, spread, total);
       return hipGetLastError();
     }

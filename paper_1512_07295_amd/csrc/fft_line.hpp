@@ -160,6 +160,78 @@ __device__ __forceinline__ void line_fft(float2 (&v)[LinePlan<L>::EPT], int t, f
   fft_stage<L, DIR, LS, 1>(v, t, lb, tw);
 }
 
+// ------------------------------------------------------- 1024 = 32 x 32 lines
+// A 1024-point line held by 32 threads with 32 elements each (thread t holds
+// elements t + 32 e on entry and exit): a radix-32 stage in registers, one
+// exchange through LDS, a second radix-32 stage with the twiddles
+// tw[q t] (q < 32).  One LDS round trip and two barriers instead of the two
+// of the 16 x 16 x 4 plan.
+
+// cos of 2 pi k / 32; sin(2 pi k / 32) = cos(2 pi (k + 24) / 32)
+struct Tw32 {
+  static constexpr float c[32] = {
+      1.0f, 0.98078528040323044f, 0.92387953251128674f, 0.83146961230254524f,
+      0.70710678118654752f, 0.55557023301960218f, 0.38268343236508977f, 0.19509032201612826f,
+      0.0f, -0.19509032201612826f, -0.38268343236508977f, -0.55557023301960218f,
+      -0.70710678118654752f, -0.83146961230254524f, -0.92387953251128674f, -0.98078528040323044f,
+      -1.0f, -0.98078528040323044f, -0.92387953251128674f, -0.83146961230254524f,
+      -0.70710678118654752f, -0.55557023301960218f, -0.38268343236508977f, -0.19509032201612826f,
+      0.0f, 0.19509032201612826f, 0.38268343236508977f, 0.55557023301960218f,
+      0.70710678118654752f, 0.83146961230254524f, 0.92387953251128674f, 0.98078528040323044f};
+};
+
+// a * exp(DIR * 2 pi i K / 32)
+template <int DIR, int K>
+__device__ __forceinline__ float2 mul_tw32(float2 a) {
+  constexpr int idx = K & 31;
+  if constexpr (idx % 2 == 0) {
+    return mul_const_tw<DIR, 16, idx / 2>(a);
+  } else {
+    constexpr float c = Tw32::c[idx];
+    constexpr float s = DIR * Tw32::c[(idx + 24) & 31];
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// In-register 32-point DFT (natural order in and out): two 16-point DFTs of
+// the even and odd elements, then radix-2 butterflies.
+template <int DIR>
+__device__ __forceinline__ void dft32(float2 (&a)[32]) {
+  float2 e[16], o[16];
+  static_for<0, 16>([&](auto k) {
+    e[k] = a[2 * k];
+    o[k] = a[2 * k + 1];
+  });
+  Dft<16, DIR>::run(e);
+  Dft<16, DIR>::run(o);
+  static_for<0, 16>([&](auto k) {
+    const float2 t = mul_tw32<DIR, decltype(k)::value>(o[k]);
+    a[k] = cadd(e[k], t);
+    a[k + 16] = csub(e[k], t);
+  });
+}
+
+// Whole 1024-point line, LS interleaved lines in LDS (element i at i * LS).
+// Every thread of the workgroup must call it (barriers).
+template <int DIR, int LS>
+__device__ __forceinline__ void line_fft_1024_r32(float2 (&v)[32], int t, float2* lb,
+                                                  const float2* __restrict__ tw) {
+  // stage 1: sub-transforms of length 1, butterfly t reads t + 32 q and
+  // writes 32 t + q
+  dft32<DIR>(v);
+  static_for<0, 32>([&](auto q) { lb[(32 * t + decltype(q)::value) * LS] = v[q]; });
+  __syncthreads();
+  static_for<0, 32>([&](auto e) { v[e] = lb[(t + 32 * decltype(e)::value) * LS]; });
+  __syncthreads();
+  // stage 2: sub-transforms of length 32, twiddle w^(q t), w = exp(DIR 2 pi i / 1024)
+  static_for<1, 32>([&](auto q) {
+    float2 w = tw[decltype(q)::value * t];
+    if constexpr (DIR > 0) w.y = -w.y;
+    v[q] = cmul(v[q], w);
+  });
+  dft32<DIR>(v);
+}
+
 // ---------------------------------------------------------------- mixed radix
 // Lengths L = 2^a 3^b 5^c that are not powers of two use a plan chosen at
 // run time: Stockham stages of radix 16, 8, 4, 2 (the power-of-two part,

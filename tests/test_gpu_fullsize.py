@@ -159,12 +159,12 @@ def test_headline_other_orders_sampled(torch, headline, p, il):
 
 def test_headline_strided_pass_shapes_agree(torch, headline, headline_oracle):
     """The headline P(k) and its adjoint with 16 lines per strided-FFT
-    workgroup (the persistent kernel that prefetches the next chunk, forward
-    and inverse 1024-point lines) and with 8 (one chunk per workgroup): P(k)
-    of both against the FP64 oracle (1e-5), and the position gradients of
-    both within 1e-4 of the largest component (the adjoint's tolerance
-    against the oracle): the lines take the same operations in both kernels,
-    but the compiler may fuse their multiply-adds differently."""
+    workgroup (the persistent kernel that prefetches the next chunk and runs
+    forward and inverse 1024-point lines as 32 x 32) and with 8 (one chunk
+    per workgroup, 16 x 16 x 4): P(k) of both against the FP64 oracle
+    (1e-5), and the position gradients of both within 1e-4 of the largest
+    component (the adjoint's tolerance against the oracle; the two plans
+    round differently in FP32)."""
     pos, dpos, est = headline
     k0, p0, n0, _ = headline_oracle
     dldp = np.random.default_rng(11).standard_normal(512)
