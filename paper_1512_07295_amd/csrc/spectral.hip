@@ -150,16 +150,28 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
       if (valid && !(r == 1 && self)) {
         // this thread's run of half-space z indices; the shell index only
         // grows along it, so it advances by comparing 4|m|^2 with the next
-        // shell's lower edge ((2b+1) n_dk)^2 (same rule as shell_of)
+        // shell's lower edge ((2b+1) n_dk)^2 (same rule as shell_of).  The
+        // row's modes below the last shell's upper edge, 4 |m|^2 <
+        // ((2 n_bins + 1) n_dk)^2, are mz <= zmax; they are split evenly
+        // over the row's threads, so no lane idles past the sphere
         const int nm = n / 2 + 1;
-        const int per = (nm + TPL - 1) / TPL;
+        const int r2xy = mxr * mxr + myr * myr;
+        const int top = (2 * n_bins + 1) * n_dk;
+        const int lim = top * top - 4 * r2xy;  // 4 mz^2 < lim
+        int zmax = -1;
+        if (lim > 0) {
+          zmax = (int)sqrtf(0.25f * (float)lim);
+          while (zmax >= 0 && 4 * zmax * zmax >= lim) --zmax;
+          while (4 * (zmax + 1) * (zmax + 1) < lim) ++zmax;
+          zmax = min(zmax, nm - 1);
+        }
+        const int per = (zmax + TPL) / TPL;
         const int z0 = t * per;
-        const int z1 = min(z0 + per, nm);
+        const int z1 = min(z0 + per, zmax + 1);
         if (z0 < z1) {
           const float wxy = inv_w2[xr] * inv_w2[yr] * (IL ? 0.0625f : 0.25f);
           const float2 ph_xy = IL ? phase[mod_2n<P2>(mxr + myr, n)] : make_float2(1.0f, 0.0f);
-          const int r2 = mxr * mxr + myr * myr;
-          int m2 = r2 + z0 * z0;  // |m|^2 of mode mz, advanced by 2 mz + 1 per step
+          int m2 = r2xy + z0 * z0;  // |m|^2 of mode mz, advanced by 2 mz + 1 per step
           int b = m2 ? shell_of(m2, n_dk) : 0;
           int edge = (2 * b + 1) * n_dk;
           edge *= edge;
