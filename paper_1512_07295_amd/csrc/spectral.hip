@@ -100,14 +100,20 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   // mode's weight in the half-space sum (1 on the planes mz = 0 and N/2,
   // which hold their own mirror images, 2 elsewhere)
   __shared__ float4 ztab[MODE != 2 ? kMaxBins + 1 : 1];
+  // shell sums: the row pairs that hold a mode inside the last shell,
+  // 4 (mx^2 + my^2) < top^2 with top = (2 n_bins + 1) n_dk, column by
+  // column (x = 0 .. N/2, in pair_rows' order); colpre[c] is the number of
+  // such pairs in the columns before c, coly[c] the largest |my| of column c
+  constexpr int kCols = MODE != 2 ? kMaxBins + 2 : 1;
+  __shared__ int colpre[kCols];
+  __shared__ int coly[kCols];
 
   const int n = g.n;
   const int mock = blockIdx.y;
   const int ps = threadIdx.x / (2 * TPL);
   const int r = (threadIdx.x / TPL) & 1;
   const int t = threadIdx.x % TPL;
-  const int64_t npairs = (int64_t)n * n / 2 + 2;
-  const int64_t ngroups = (npairs + PPB - 1) / PPB;
+  int64_t npairs = (int64_t)n * n / 2 + 2;
   float2* own_lds = rows + (2 * ps + r) * ROWP;
   const float2* par_lds = rows + (2 * ps + (r ^ 1)) * ROWP;
 
@@ -119,13 +125,77 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
       const float wgt = (i == 0 || i == n / 2) ? 1.0f : 2.0f;
       ztab[i] = make_float4(ph.x, ph.y, wgt * inv_w2[i], 0.0f);
     }
+    if (threadIdx.x < 64) {
+      // wave 0: per-column pair counts and their exclusive scan
+      const int h = n / 2, lane = threadIdx.x;
+      const int top = (2 * n_bins + 1) * n_dk;
+      const int per = (h + 1 + 63) / 64;
+      int cnt[(kMaxBins + 1 + 63) / 64];
+      int run = 0;
+#pragma unroll
+      for (int k = 0; k < (kMaxBins + 1 + 63) / 64; ++k) {
+        const int c = lane * per + k;
+        int ny = 0;
+        if (k < per && c <= h) {
+          const int lim = top * top - 4 * c * c;  // 4 my^2 < lim
+          int ymax = -1;
+          if (lim > 0) {
+            ymax = (int)sqrtf(0.25f * (float)lim);
+            while (ymax >= 0 && 4 * ymax * ymax >= lim) --ymax;
+            while (4 * (ymax + 1) * (ymax + 1) < lim) ++ymax;
+          }
+          coly[c] = ymax;
+          if (ymax >= 0) {
+            // columns 0 and N/2 hold y = 0 .. N/2 (pair_rows), the others all y
+            if (c == 0 || c == h) ny = min(ymax, h) + 1;
+            else ny = ymax >= h ? n : 2 * ymax + 1;
+          }
+        }
+        cnt[k] = ny;
+        run += ny;
+      }
+      int incl = run;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      int acc = incl - run;
+#pragma unroll
+      for (int k = 0; k < (kMaxBins + 1 + 63) / 64; ++k) {
+        const int c = lane * per + k;
+        if (k < per && c <= h) colpre[c] = acc;
+        acc += cnt[k];
+      }
+      if (lane == 63) colpre[h + 1] = incl;
+    }
+    __syncthreads();
+    npairs = colpre[n / 2 + 1];
   }
+  const int64_t ngroups = (npairs + PPB - 1) / PPB;
 
   for (int64_t pg = blockIdx.x; pg < ngroups; pg += gridDim.x) {
     const int64_t q = pg * PPB + ps;
     const bool valid = q < npairs;
     int xa = 0, ya = 0;
-    if (valid) pair_rows(q, n, xa, ya);
+    if (valid) {
+      if constexpr (MODE != 2) {
+        // the column holding pair q, then its y: 0 .. Y, then N - Y .. N - 1
+        const int h = n / 2;
+        int lo = 0, hi = h;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (colpre[mid] <= (int)q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int o = (int)q - colpre[lo];
+        const int ymax = coly[lo];
+        xa = lo;
+        ya = (lo == 0 || lo == h || ymax >= h || o <= ymax) ? o : o + n - 2 * ymax - 1;
+      } else {
+        pair_rows(q, n, xa, ya);
+      }
+    }
     const int xb = neg_mod<P2>(xa, n), yb = neg_mod<P2>(ya, n);
     const bool self = (xa == xb) && (ya == yb);
     const int xr = r ? xb : xa, yr = r ? yb : ya;
