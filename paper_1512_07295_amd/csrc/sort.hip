@@ -346,6 +346,7 @@ static hipError_t sort_atomic(const Geom& g, const void* pos, est_dtype dt,
 // the deposit splits its bucket runs at super-bucket boundaries.
 constexpr int kSortThreads = 1024;
 constexpr int kSortBatch = 4;  // particles per thread whose loads are in flight together
+constexpr int kFineBlocks = 512;  // workgroups of the bucket pass (two per CU of an MI355X)
 
 __device__ __forceinline__ void particle_buckets(double ux, double uy, double uz, const Geom& g,
                                                  int& bx, int& by, int& bz) {
@@ -457,7 +458,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
   constexpr int kPer = kFineMax * kFineMax * kFineMax / kSortThreads;  // buckets per thread
   __shared__ uint32_t hist[kFineMax * kFineMax * kFineMax];
   __shared__ uint32_t wtot[kSortThreads / 64];
-  const int sup = blockIdx.x;
+  __shared__ int next_sup;
+  // a fixed grid takes the super-buckets in order from a counter (stats[3],
+  // zeroed with the sort's statistics), so that the ones in flight are
+  // neighbours and uneven ones balance
+  for (;;) {
+  if (threadIdx.x == 0) next_sup = (int)atomicAdd(&stats[3], 1u);
+  __syncthreads();  // also: the previous super-bucket's scatter is done
+  const int sup = next_sup;
+  if (sup >= g.nsup) break;
   const int nf = g.fb * g.fb * g.fb;
   const uint32_t seg0 = base[sup], seg1 = base[sup + 1];
   for (int i = threadIdx.x; i < nf; i += kSortThreads) hist[i] = 0u;
@@ -532,6 +541,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_fine(
       }
     }
   }
+  }
 }
 
 // The histograms are stored block-major (h[b][s], b < nblk, s < nsup, so
@@ -592,7 +602,7 @@ static hipError_t sort_two_level(const Geom& g, const TP* pos, const int64_t* of
   uint16_t* tfine = reinterpret_cast<uint16_t*>(b.rank);
   hipLaunchKernelGGL(k_sort_super<TP>, dim3(nblk), dim3(kSortThreads), 0, s, pos, n_total,
                      offsets, g, chunk, b.hsup, (const uint32_t*)base, b.trecs, tfine, w, b.tw);
-  hipLaunchKernelGGL(k_sort_fine, dim3(g.nsup), dim3(kSortThreads), 0, s, (const uint4*)b.trecs,
+  hipLaunchKernelGGL(k_sort_fine, dim3(g.nsup < kFineBlocks ? g.nsup : kFineBlocks), dim3(kSortThreads), 0, s, (const uint4*)b.trecs,
                      (const uint16_t*)tfine, g, (const uint32_t*)base, b.recs,
                      b.boff, b.bcnt, b.stats, w ? b.tw : nullptr, b.sw);
   return hipGetLastError();
