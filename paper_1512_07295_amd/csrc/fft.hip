@@ -224,7 +224,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols_rt(float2* __restrict__ data,
   const int64_t outer = blockIdx.x / chunks_per_outer;
   const int64_t ic = blockIdx.x % chunks_per_outer;
   const bool valid = ic * C + c < inner;
-  float2* p = data + outer * outer_stride + ic * C + c;
+  const float2* p = data + outer * outer_stride + ic * C + c;
   float2 v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -232,11 +232,17 @@ __global__ __launch_bounds__(1024) void k_fft_cols_rt(float2* __restrict__ data,
     v[e] = (valid && j < L) ? p[(int64_t)j * elem_stride] : make_float2(0.f, 0.f);
   }
   line_fft_rt<DIR, C>(v, t, lds_dyn + c, pl, tw);
+  // the store addresses are formed again from a base the compiler cannot
+  // match with the loads' (an empty asm statement), so that the 16 64-bit
+  // load addresses are not kept live across the transform (they spilled)
+  float2* ds = data;
+  asm volatile("" : "+s"(ds));
+  float2* q = ds + outer * outer_stride + ic * C + c;
   if (valid) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int j = t + e * tpl;
-      if (j < L) p[(int64_t)j * elem_stride] = v[e];
+      if (j < L) q[(int64_t)j * elem_stride] = v[e];
     }
   }
 }

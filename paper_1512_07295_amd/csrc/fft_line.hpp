@@ -293,8 +293,14 @@ __device__ __forceinline__ void dft_any(float2* a) {
 // sub-transforms of length ns: butterfly j reads elements j + q L/R, applies
 // the twiddles w^(q k), k = j mod ns, w = exp(DIR 2 pi i / (ns R)), and writes
 // its outputs to (j - k) R + k + q ns.
+// j mod ns as j - floor(j m / 2^32) ns with m = floor((2^32 - 1) / ns) + 1
+// (ns >= 2): exact for j ns < 2^32, far above these lines (j < L <= 1024)
+__device__ __forceinline__ int rt_mod(int j, int ns, uint32_t m) {
+  return ns > 1 ? j - (int)__umulhi((uint32_t)j, m) * ns : 0;
+}
+
 template <int R, int DIR, int LS>
-__device__ __forceinline__ void rt_stage(float2* lb, int t, int tpl, int L, int ns,
+__device__ __forceinline__ void rt_stage(float2* lb, int t, int tpl, int L, int ns, uint32_t nsm,
                                          const float2* __restrict__ tw) {
   constexpr int NB = (16 + R - 1) / R;
   const int nbf = L / R;
@@ -304,7 +310,7 @@ __device__ __forceinline__ void rt_stage(float2* lb, int t, int tpl, int L, int 
   for (int i = 0; i < NB; ++i) {
     const int j = t + i * tpl;
     if (j < nbf) {
-      const int k = j % ns;
+      const int k = rt_mod(j, ns, nsm);
 #pragma unroll
       for (int q = 0; q < R; ++q) a[i][q] = lb[lds_index<LS>(j + q * nbf)];
       if (ns > 1) {
@@ -323,7 +329,7 @@ __device__ __forceinline__ void rt_stage(float2* lb, int t, int tpl, int L, int 
   for (int i = 0; i < NB; ++i) {
     const int j = t + i * tpl;
     if (j < nbf) {
-      const int k = j % ns;
+      const int k = rt_mod(j, ns, nsm);
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int q = 0; q < R; ++q) lb[lds_index<LS>(base + q * ns)] = a[i][q];
@@ -344,19 +350,27 @@ __device__ __forceinline__ void line_fft_rt(float2 (&v)[16], int t, float2* lb, 
   int ns = 1;
   for (int s = 0; s < pl.nst; ++s) {
     const int r = pl.radix[s];
+    const uint32_t nsm = ns > 1 ? 0xFFFFFFFFu / (uint32_t)ns + 1u : 0u;
+    // the thread index passes through an empty asm statement in every stage,
+    // so that the compiler forms each stage's LDS addresses in that stage
+    // instead of hoisting those of every radix out of the loop (which spills)
+    int ts = t;
+    asm volatile("" : "+v"(ts));
     switch (r) {
-      case 16: rt_stage<16, DIR, LS>(lb, t, tpl, L, ns, tw); break;
-      case 8: rt_stage<8, DIR, LS>(lb, t, tpl, L, ns, tw); break;
-      case 4: rt_stage<4, DIR, LS>(lb, t, tpl, L, ns, tw); break;
-      case 2: rt_stage<2, DIR, LS>(lb, t, tpl, L, ns, tw); break;
-      case 3: rt_stage<3, DIR, LS>(lb, t, tpl, L, ns, tw); break;
-      default: rt_stage<5, DIR, LS>(lb, t, tpl, L, ns, tw); break;
+      case 16: rt_stage<16, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
+      case 8: rt_stage<8, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
+      case 4: rt_stage<4, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
+      case 2: rt_stage<2, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
+      case 3: rt_stage<3, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
+      default: rt_stage<5, DIR, LS>(lb, ts, tpl, L, ns, nsm, tw); break;
     }
     ns *= r;
   }
+  // elements past L are set to zero, not kept: their registers are then free
+  // during the stages
 #pragma unroll
   for (int e = 0; e < 16; ++e)
-    if (t + e * tpl < L) v[e] = lb[lds_index<LS>(t + e * tpl)];
+    v[e] = t + e * tpl < L ? lb[lds_index<LS>(t + e * tpl)] : make_float2(0.f, 0.f);
   __syncthreads();
 }
 
