@@ -8,7 +8,8 @@ times (autotuned the same way), on outputs the oracle can reach:
   delta(m) at sampled modes including Bragg peaks of the particle lattice on
   the Nyquist planes (1e-5 relative); the same particles and grid with
   NGP, CIC and TSC, with and without interlacing (sampled cells and modes);
-  P(k) and the adjoint with both strided-FFT workgroup shapes;
+  P(k) and the adjoint with both strided-FFT workgroup shapes; a batch of
+  two sets on 1024^3 grids against each set alone;
 * 256^3 particles on a 256^3 grid: all 128 P(k) shells (1e-5) and every
   one of the 3,384 closed bispectrum triangles of 2 k_f shells up to k_N/2
   (tolerance relative to the L1 scale of the summands);
@@ -180,6 +181,32 @@ def test_headline_strided_pass_shapes_agree(torch, headline, headline_oracle):
     scale = float(grads[0].abs().max())
     assert scale > 0 and float((grads[0] - grads[1]).abs().max()) <= 1e-4 * scale
     est.autotune(dpos, n_bins=512, iters=1)
+
+
+def test_batch_of_two_sets_at_1024_matches_single_sets(torch):
+    """Two particle sets on 1024^3 grids in one batch (the strided passes'
+    prefetching kernel with two outer blocks, the fused pass with one grid
+    row of workgroups per set) give each set's P(k) and mode counts as a
+    handle of its own does: counts exactly, P(k) to 1e-6 (the transforms
+    and sums take the same arithmetic; the deposit's fixed-point step
+    follows the fullest bucket of the whole batch, so the grids round
+    differently at about 1e-7)."""
+    from paper_1512_07295_amd.estimator import Estimator
+    box, n = 2000.0, 1024
+    parts = [synth.zeldovich(128, box, 21, dtype=np.float32),
+             synth.uniform(1 << 20, box, 22, np.float32)]
+    pos = np.concatenate(parts)
+    offs = np.array([0, len(parts[0]), len(pos)], dtype=np.int64)
+    est = Estimator(n, box, 4, True, 2, len(pos))
+    _, pk, nm = est.power(to_dev(torch, pos), offsets=to_dev(torch, offs), n_bins=512)
+    pk, nm = pk.cpu().numpy(), nm.cpu().numpy()
+    est.close()
+    for i, part in enumerate(parts):
+        one = Estimator(n, box, 4, True, 1, len(part))
+        _, p1, n1 = one.power(to_dev(torch, part), n_bins=512)
+        one.close()
+        assert np.array_equal(nm[i], n1.cpu().numpy()[0])
+        assert rel_err(pk[i], p1.cpu().numpy()[0]) < 1e-6, i
 
 
 def test_c2_power_all_shells_and_every_triangle(torch):
