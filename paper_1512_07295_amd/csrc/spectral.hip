@@ -254,8 +254,8 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
               edge = (2 * b + 1) * n_dk;
               edge *= edge;
             }
-            if (b > n_bins) break;
-            if (b < 1) continue;  // below the first shell (and the k = 0 mode)
+            // b <= n_bins by the choice of zmax; modes below the first shell
+            // (b = 0, the k = 0 mode among them) form a run that is never added
             float2 za, zb;
             if constexpr (IL) {
               za = own_lds[lds_index<1>(mz)];
