@@ -96,9 +96,10 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
   }
   __shared__ float2 rows[PairShape<L>::ROWS_LDS];
   __shared__ double hist[kMaxBins];
-  // per half-space z index: the z part of the phase, and 1/W^2 times the
-  // mode's weight in the half-space sum (1 on the planes mz = 0 and N/2,
-  // which hold their own mirror images, 2 elsewhere)
+  // per half-space z index: the z part of the phase, 1/W^2 times the mode's
+  // weight in the half-space sum (1 on the planes mz = 0 and N/2, which hold
+  // their own mirror images, 2 elsewhere), and the LDS row indices of Z(mz)
+  // and Z(-mz) (16 bits each)
   __shared__ float4 ztab[MODE != 2 ? kMaxBins + 1 : 1];
   // shell sums: the row pairs that hold a mode inside the last shell,
   // 4 (mx^2 + my^2) < top^2 with top = (2 n_bins + 1) n_dk, column by
@@ -123,7 +124,18 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
       // interlaced: exp(+i pi mz/N); packed: exp(-2 pi i mz/N)
       const float2 ph = IL ? phase[i] : cconj(phase[mod_2n<P2>(2 * i, n)]);
       const float wgt = (i == 0 || i == n / 2) ? 1.0f : 2.0f;
-      ztab[i] = make_float4(ph.x, ph.y, wgt * inv_w2[i], 0.0f);
+      int ia, ib;
+      if constexpr (IL) {
+        ia = i;
+        ib = neg_mod<P2>(i, n);
+      } else {
+        // packed rows: N/2 complex values, the plane mz = N/2 folds onto 0
+        const int h = n / 2;
+        ia = (i == h) ? 0 : i;
+        ib = neg_mod<P2>(ia, h);
+      }
+      const uint32_t zi = (uint32_t)lds_index<1>(ia) | ((uint32_t)lds_index<1>(ib) << 16);
+      ztab[i] = make_float4(ph.x, ph.y, wgt * inv_w2[i], __uint_as_float(zi));
     }
     if (threadIdx.x < 64) {
       // wave 0: per-column pair counts and their exclusive scan
@@ -256,17 +268,11 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
             }
             // b <= n_bins by the choice of zmax; modes below the first shell
             // (b = 0, the k = 0 mode among them) form a run that is never added
-            float2 za, zb;
-            if constexpr (IL) {
-              za = own_lds[lds_index<1>(mz)];
-              zb = par_lds[lds_index<1>(neg_mod<P2>(mz, n))];
-            } else {
-              const int h = n / 2;
-              const int kz = (mz == h) ? 0 : mz;
-              za = own_lds[lds_index<1>(kz)];
-              zb = par_lds[lds_index<1>(neg_mod<P2>(kz, h))];
-            }
+            // the LDS elements of the mode and of its mirror, from the table
             const float4 zt = ztab[mz];
+            const uint32_t zi = __float_as_uint(zt.w);
+            const float2 za = own_lds[zi & 0xFFFFu];
+            const float2 zb = par_lds[zi >> 16];
             const float2 ph = IL ? cmul(ph_xy, make_float2(zt.x, zt.y)) : make_float2(zt.x, zt.y);
             const float val = pair_power(za, zb, ph) * zt.z;
             if (b != cur_b) {
