@@ -255,16 +255,20 @@ __global__ __launch_bounds__(PairShape<L>::THREADS) void k_pairs(
           const float2 ph_xy = IL ? phase[mod_2n<P2>(mxr + myr, n)] : make_float2(1.0f, 0.0f);
           int m2 = r2xy + z0 * z0;  // |m|^2 of mode mz, advanced by 2 mz + 1 per step
           int b = m2 ? shell_of(m2, n_dk) : 0;
+          // the next shell's lower edge ((2b+1) n_dk)^2 and its step to the
+          // one after, 8 (b+1) n_dk^2, both advanced by additions
+          const int nd2 = n_dk * n_dk;
           int edge = (2 * b + 1) * n_dk;
           edge *= edge;
+          int dedge = 8 * (b + 1) * nd2;
           int cur_b = -1;
           float cur = 0.0f;
           for (int mz = z0; mz < z1; m2 += 2 * mz + 1, ++mz) {
             const int m4 = 4 * m2;
             while (edge <= m4) {
               ++b;
-              edge = (2 * b + 1) * n_dk;
-              edge *= edge;
+              edge += dedge;
+              dedge += 8 * nd2;
             }
             // b <= n_bins by the choice of zmax; modes below the first shell
             // (b = 0, the k = 0 mode among them) form a run that is never added
