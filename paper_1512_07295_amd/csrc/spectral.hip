@@ -534,9 +534,15 @@ __global__ __launch_bounds__(1024) void k_multi_pairs(
   const int t = threadIdx.x % half;
   const int per = (nm + half - 1) / half;
   const float inv_g = 1.0f / (float)g.ng;
+  const int top = (2 * n_bins + 1) * n_dk;
   for (int64_t pg = blockIdx.x; pg < npairs; pg += gridDim.x) {
     int xa, ya;
     pair_rows(pg, n, xa, ya);
+    // a pair whose rows hold no mode inside the last shell, 4 |m|^2 >=
+    // ((2 n_bins + 1) n_dk)^2 at mz = 0, adds nothing: skipped by the whole
+    // workgroup
+    const int mxa = signed_freq(xa, n), mya = signed_freq(ya, n);
+    if (4 * (mxa * mxa + mya * mya) >= top * top) continue;
     const int xb = neg_mod<false>(xa, n), yb = neg_mod<false>(ya, n);
     const bool self = (xa == xb) && (ya == yb);
     __syncthreads();  // the previous pair's rows are consumed
