@@ -94,6 +94,24 @@ def test_power_parity_staged_rows(torch, n, p, il):
     est.close()
 
 
+@pytest.mark.parametrize("n,il,n_dk,n_bins", [(256, True, 2, 20), (256, False, 1, 100),
+                                               (240, True, 3, 30)])
+def test_power_few_shells_large_grid(torch, n, il, n_dk, n_bins):
+    """Shells well below the Nyquist frequency on 240^3 and 256^3 grids: the
+    fused pass enumerates only the row pairs inside the last shell (columns
+    whose valid y wrap around in two pieces) and splits each row's modes
+    below the last edge over its threads; counts exact, P within 1e-5."""
+    box = 1000.0
+    pos = synth.zeldovich(32, box, 19 + n, dtype=np.float32)
+    est = _est(torch, n, box, 4, il, maxp=len(pos))
+    k, pk, nm = est.power(to_dev(torch, pos), n_dk=n_dk, n_bins=n_bins)
+    k0, p0, n0 = oracle.power(pos, box, n, 4, il, n_dk, n_bins)
+    assert np.array_equal(nm.cpu().numpy()[0], n0)
+    assert rel_err(k.cpu().numpy()[0], k0) < 1e-12
+    assert rel_err(pk.cpu().numpy()[0], p0) < P_TOL
+    est.close()
+
+
 def test_power_parity_f64_positions_cic(torch):
     """Config-1 shape: 32^3 uniform float64 particles, 32^3 grid, CIC, no interlacing."""
     box = 1000.0
