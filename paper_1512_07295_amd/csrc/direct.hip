@@ -8,10 +8,12 @@
 //  * each particle's position becomes three 32-bit fixed-point phases
 //    q_a = floor(wrap(x_a) / L * 2^32), so m . x / L mod 1 is the exact
 //    integer m_x q_x + m_y q_y + m_z q_z mod 2^32 (phase error < 2^-32 m);
-//  * a thread owns one (m_x, m_y) and kDirMz consecutive m_z: per particle one
+//  * a thread owns one (m_x, m_y) and MZ consecutive m_z: per particle one
 //    accurate sincos of the first phase, then complex steps by
 //    exp(-2 pi i q_z / 2^32) for the others; particles are staged in LDS in
-//    chunks and summed in FP32 per chunk, then in FP64;
+//    chunks and summed in FP32 per chunk, then in FP64.  MZ (8, 11, 13 or
+//    16) is the one that leaves fewest idle slots in a row's N/2 + 1 modes
+//    (11 for N = 64, 13 for N = 128), so the sincos is shared by more terms;
 //  * particles are split into S slices (a grid dimension) for parallelism;
 //    a fixed-order FP64 reduction over the slices gives deterministic output.
 #include <mutex>
@@ -20,7 +22,6 @@
 
 namespace fsest {
 
-constexpr int kDirMz = 8;        // m_z per thread
 constexpr int kDirThreads = 256;
 constexpr int kDirChunk = 256;   // particles per LDS chunk
 
@@ -38,7 +39,7 @@ __global__ void k_dir_prep(const TP* __restrict__ pos, int64_t n, double box,
 
 // partial[slice][mode] (complex128) of the half spectrum, mode index
 // (ix * N + iy) * (N/2 + 1) + mz with ix, iy the FFT indices
-template <bool WT>
+template <bool WT, int MZ>
 __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restrict__ q, int64_t n,
                                                         int ngrid, int nslices,
                                                         const float* __restrict__ w,
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
   __shared__ float2 sstep[kDirChunk];
   __shared__ float swt[WT ? kDirChunk : 1];
   const int nh = ngrid / 2 + 1;
-  const int nzb = (nh + kDirMz - 1) / kDirMz;
+  const int nzb = (nh + MZ - 1) / MZ;
   const int64_t nthreads_modes = (int64_t)ngrid * ngrid * nzb;
   const int64_t tid = (int64_t)blockIdx.x * kDirThreads + threadIdx.x;
   const bool active = tid < nthreads_modes;
@@ -56,13 +57,13 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
   const int ix = (int)(tid / ((int64_t)nzb * ngrid));
   const int mx = (ix <= ngrid / 2) ? ix : ix - ngrid;
   const int my = (iy <= ngrid / 2) ? iy : iy - ngrid;
-  const int mz0 = zb * kDirMz;
+  const int mz0 = zb * MZ;
   const int slice = blockIdx.y;
   const int64_t j0 = n * slice / nslices, j1 = n * (slice + 1) / nslices;
 
-  double accr[kDirMz], acci[kDirMz];
+  double accr[MZ], acci[MZ];
 #pragma unroll
-  for (int r = 0; r < kDirMz; ++r) accr[r] = acci[r] = 0.0;
+  for (int r = 0; r < MZ; ++r) accr[r] = acci[r] = 0.0;
 
   for (int64_t c0 = j0; c0 < j1; c0 += kDirChunk) {
     const int cn = (int)((j1 - c0) < kDirChunk ? (j1 - c0) : kDirChunk);
@@ -83,9 +84,9 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
     }
     __syncthreads();
     if (active) {
-      float fr[kDirMz], fi[kDirMz];
+      float fr[MZ], fi[MZ];
 #pragma unroll
-      for (int r = 0; r < kDirMz; ++r) fr[r] = fi[r] = 0.0f;
+      for (int r = 0; r < MZ; ++r) fr[r] = fi[r] = 0.0f;
       for (int i = 0; i < cn; ++i) {
         const uint32_t qx = sq[3 * i + 0], qy = sq[3 * i + 1], qz = sq[3 * i + 2];
         const uint32_t ph = (uint32_t)mx * qx + (uint32_t)my * qy + (uint32_t)mz0 * qz;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
         }
         const float2 st = sstep[i];
 #pragma unroll
-        for (int r = 0; r < kDirMz; ++r) {
+        for (int r = 0; r < MZ; ++r) {
           fr[r] += er;
           fi[r] += ei;
           const float tr = er * st.x - ei * st.y;
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
         }
       }
 #pragma unroll
-      for (int r = 0; r < kDirMz; ++r) {
+      for (int r = 0; r < MZ; ++r) {
         accr[r] += fr[r];
         acci[r] += fi[r];
       }
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(const uint32_t* __restri
   double* out = partial + 2 * nmodes * slice;
   const int64_t base = ((int64_t)ix * ngrid + iy) * nh;
 #pragma unroll
-  for (int r = 0; r < kDirMz; ++r) {
+  for (int r = 0; r < MZ; ++r) {
     const int mz = mz0 + r;
     if (mz < nh) {
       out[2 * (base + mz)] = accr[r];
@@ -140,9 +141,26 @@ __global__ void k_dir_reduce(const double* __restrict__ partial, int64_t nmodes,
   else out[i] = s * inv_n;
 }
 
+// m_z per thread: of 8, 11, 13 and 16 the one with the fewest idle slots in
+// a row's N/2 + 1 modes, the larger on a tie
+static int direct_mz(int ngrid) {
+  const int nh = ngrid / 2 + 1;
+  const int cand[4] = {8, 11, 13, 16};
+  int best = 8, idle = 1 << 30;
+  for (int c : cand) {
+    const int w = (nh + c - 1) / c * c - nh;
+    if (w < idle || (w == idle && c > best)) {
+      best = c;
+      idle = w;
+    }
+  }
+  return best;
+}
+
 int direct_slices(int ngrid, int64_t n) {
   const int nh = ngrid / 2 + 1;
-  const int64_t threads = (int64_t)ngrid * ngrid * ((nh + kDirMz - 1) / kDirMz);
+  const int mz = direct_mz(ngrid);
+  const int64_t threads = (int64_t)ngrid * ngrid * ((nh + mz - 1) / mz);
   int64_t s = (2 * 256 * 1024 + threads - 1) / threads;
   const int64_t by_n = (n + kDirChunk - 1) / kDirChunk;
   if (s > by_n) s = by_n;
@@ -218,14 +236,25 @@ hipError_t launch_direct(const Geom& g, const void* pos, est_dtype dt, int64_t n
   else
     hipLaunchKernelGGL(k_dir_prep<double>, dim3(pb), dim3(256), 0, s, (const double*)pos, n, g.box,
                        q);
-  const int64_t threads = (int64_t)ngrid * ngrid * ((nh + kDirMz - 1) / kDirMz);
+  const int mz = direct_mz(ngrid);
+  const int64_t threads = (int64_t)ngrid * ngrid * ((nh + mz - 1) / mz);
   const dim3 grid((unsigned)((threads + kDirThreads - 1) / kDirThreads), nslices);
-  if (w)
-    hipLaunchKernelGGL(k_direct<true>, grid, dim3(kDirThreads), 0, s, q, n, ngrid, nslices, w,
-                       partial);
-  else
-    hipLaunchKernelGGL(k_direct<false>, grid, dim3(kDirThreads), 0, s, q, n, ngrid, nslices, w,
-                       partial);
+#define FSEST_DIRECT_CASE(MZV)                                                                  \
+  case MZV:                                                                                     \
+    if (w)                                                                                      \
+      hipLaunchKernelGGL((k_direct<true, MZV>), grid, dim3(kDirThreads), 0, s, q, n, ngrid,     \
+                         nslices, w, partial);                                                  \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_direct<false, MZV>), grid, dim3(kDirThreads), 0, s, q, n, ngrid,    \
+                         nslices, w, partial);                                                  \
+    break;
+  switch (mz) {
+    FSEST_DIRECT_CASE(8)
+    FSEST_DIRECT_CASE(11)
+    FSEST_DIRECT_CASE(13)
+    default: FSEST_DIRECT_CASE(16)
+  }
+#undef FSEST_DIRECT_CASE
   hipLaunchKernelGGL(k_dir_reduce, dim3((unsigned)((2 * nmodes + 255) / 256)), dim3(256), 0, s,
                      partial, nmodes, nslices, 1.0 / (double)n, w ? norm : nullptr, stats, out);
   return hipGetLastError();
