@@ -40,17 +40,31 @@ __global__ __launch_bounds__(256) void k_gather_grad(const TP* __restrict__ pos,
       stencil_1d<P>(u[ax] + sh, n, c[ax], wt[ax]);
       stencil_1d_deriv<P>(u[ax] + sh, d[ax]);
     }
+    // float offsets of the stencil cells: x-plane (64-bit), then y and z
+    // inside the plane (32-bit); a complex grid holds the grid as component
+    // comp of each complex element, a packed real grid two reals per element
+    int64_t xo[P];
+    int yzo[P][P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) xo[a] = 2 * (((int64_t)slab * n + c[0][a]) * g.ps);
+#pragma unroll
+    for (int bq = 0; bq < P; ++bq)
+#pragma unroll
+      for (int cq = 0; cq < P; ++cq)
+        yzo[bq][cq] = IL ? 2 * (c[1][bq] * g.nz + c[2][cq]) + comp : c[1][bq] * n + c[2][cq];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
 #pragma unroll
       for (int bq = 0; bq < P; ++bq) {
+        // the x and y factors of the three derivative weights of this row
+        const float fx = d[0][a] * wt[1][bq], fy = wt[0][a] * d[1][bq], fz = wt[0][a] * wt[1][bq];
 #pragma unroll
         for (int cq = 0; cq < P; ++cq) {
-          const float gv = IL ? grid[2 * complex_index(g, slab, c[0][a], c[1][bq], c[2][cq]) + comp]
-                              : grid[real_cell_index(g, slab, c[0][a], c[1][bq], c[2][cq])];
-          gx += gv * d[0][a] * wt[1][bq] * wt[2][cq];
-          gy += gv * wt[0][a] * d[1][bq] * wt[2][cq];
-          gz += gv * wt[0][a] * wt[1][bq] * d[2][cq];
+          const float gv = grid[xo[a] + yzo[bq][cq]];
+          const float t = gv * wt[2][cq];
+          gx = __builtin_fmaf(fx, t, gx);
+          gy = __builtin_fmaf(fy, t, gy);
+          gz = __builtin_fmaf(fz * d[2][cq], gv, gz);
         }
       }
     }
